@@ -1,0 +1,227 @@
+"""Hyper-reduced SNS ROM with RK2-average and time windows (oracle, test infrastructure).
+
+Online system (eq. rom-hr-sns, windowed as eq. rom-hr-tw):
+
+    dv^/dt = -F^1,  de^/dt = F^tv,  dx^/dt = Phi_x^T v_os + Phi_x^T Phi_v v^,
+
+where, with the SNS bases Phi_F1 = M_V Phi_v and Phi_Ftv = M_E Phi_e
+(Sec. 3.5), the reduced right-hand sides are the DEIM least-squares
+coefficients F^1 = (Z1^T Phi_F1)^+ Z1^T F.1 and F^tv = (Z2^T Phi_Ftv)^+ Z2^T F^T.v
+(eq. sol-ls-hyper, eq. sol-ls-hyper-2).  The fully discrete scheme is
+RK2-average applied to it (eq. RK2-avg-rom-hr): the energy uses the lifted
+midpoint velocity in the first stage and the lifted average velocity in the
+second.  The FOM state is lifted only at the dofs of the sampled elements
+(y~ = y_os + Phi y^, eq. discretesolrepresentation) and the step size comes
+from the same controller as the FOM, evaluated on the lifted state at the
+sampled elements' quadrature points.
+
+On entering window w the reduced coordinates are re-expressed in the new
+basis by lifting with the old one and projecting (eq. ic-tw):
+y^w = Phi_w^T (y_os^{w-1} + Phi_{w-1} y^{w-1} - y_os^w).
+
+The relative error at the final time is the Euclidean one of eq. relerrors.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import deim as D
+from . import fom as F
+from .pod import pod_basis
+from .windows import snapshot_matrices
+
+
+@dataclass
+class WindowROM:
+    T_end: float
+    Phi: list  # [Phi_x, Phi_v, Phi_e]
+    os: list  # [x_os, v_os, e_os]
+    Z1: np.ndarray
+    Z2: np.ndarray
+    A1: np.ndarray
+    A2: np.ndarray
+    elems: np.ndarray
+    rows_k: np.ndarray  # kinematic dofs touched by the sampled elements
+    rows_t: np.ndarray  # thermodynamic dofs of the sampled elements
+    Bxv: np.ndarray
+    bx: np.ndarray
+    sigma: list = field(default_factory=list)
+    trans: list = field(default_factory=list)  # [(T, c)] per field from the previous window
+
+    @property
+    def dims(self):
+        return tuple(P.shape[1] for P in self.Phi)
+
+
+@dataclass
+class ROM:
+    windows: list
+
+
+def sns_bases(op: F.Operator, Phi_v: np.ndarray, Phi_e: np.ndarray):
+    """Phi_F1 = M_V Phi_v (eliminated form), Phi_Ftv = M_E Phi_e (Sec. 3.5)."""
+    return op.Mv_eff @ Phi_v, op.Me @ Phi_e
+
+
+def sampled_rows(op: F.Operator, elems: np.ndarray):
+    mesh = op.mesh
+    nodes = np.unique(op.en[elems].ravel())
+    rows_k = np.concatenate([c * mesh.n_nodes + nodes for c in range(mesh.dim)])
+    rows_t = op.et[elems].ravel()
+    return np.sort(rows_k), np.sort(rows_t)
+
+
+def build_window(op, S_list, os_list, T_end, energy_frac, n_fixed, lam, n_max=0) -> WindowROM:
+    Phis, sigmas = [], []
+    for f in range(3):
+        nf = n_fixed[f] if n_fixed else 0
+        Phi, sigma, _ = pod_basis(S_list[f], energy_frac, nf, n_max)
+        Phis.append(Phi)
+        sigmas.append(sigma)
+    PF1, PFtv = sns_bases(op, Phis[1], Phis[2])
+    nv, ne = Phis[1].shape[1], Phis[2].shape[1]
+    Z1 = D.greedy_deim(PF1, int(round(lam[0] * nv)))
+    Z2 = D.greedy_deim(PFtv, int(round(lam[1] * ne)))
+    A1 = D.deim_pinv(PF1, Z1)
+    A2 = D.deim_pinv(PFtv, Z2)
+    elems = D.closure_elements(op.mesh, op.en, Z1, Z2)
+    rows_k, rows_t = sampled_rows(op, elems)
+    Bxv = Phis[0].T @ Phis[1]
+    bx = Phis[0].T @ os_list[1]
+    return WindowROM(T_end, Phis, list(os_list), Z1, Z2, A1, A2, elems, rows_k, rows_t, Bxv, bx, sigmas)
+
+
+def build_rom(op, trajs, offsets, T_ends, energy_frac=0.9999, n_fixed=None, lam=(2.0, 2.0),
+              n_max=0, online_offsets=None) -> ROM:
+    """Offline phase: per-window POD, SNS, DEIM and reduced operators."""
+    mats = snapshot_matrices(trajs, offsets, T_ends)
+    os_on = offsets[0] if online_offsets is None else online_offsets
+    wins = []
+    for w, Tw in enumerate(T_ends):
+        win = build_window(op, mats[w], os_on, Tw, energy_frac, n_fixed, lam, n_max)
+        if w > 0:
+            prev = wins[-1]
+            win.trans = [(win.Phi[f].T @ prev.Phi[f], win.Phi[f].T @ (prev.os[f] - win.os[f])) for f in range(3)]
+        wins.append(win)
+    return ROM(wins)
+
+
+def lift_rows(win: WindowROM, f: int, yhat: np.ndarray, rows: np.ndarray, N: int) -> np.ndarray:
+    """Full-size vector holding os + Phi yhat on ``rows`` (zero elsewhere)."""
+    out = np.zeros(N)
+    out[rows] = win.os[f][rows] + win.Phi[f][rows, :] @ yhat
+    return out
+
+
+def lift_full(win: WindowROM, f: int, yhat: np.ndarray) -> np.ndarray:
+    return win.os[f] + win.Phi[f] @ yhat
+
+
+@dataclass
+class ROMStage:
+    xh: np.ndarray
+    vh: np.ndarray
+    eh: np.ndarray
+
+
+def rom_step(op: F.Operator, win: WindowROM, xh, vh, eh, dt):
+    """One RK2-average step of the hyper-reduced SNS system; returns new coords and tau."""
+    mesh = op.mesh
+    NV, NE = mesh.NV, mesh.NE
+    els = win.elems
+
+    def lift_state(xc, vc, ec):
+        return (lift_rows(win, 0, xc, win.rows_k, NV), lift_rows(win, 1, vc, win.rows_k, NV),
+                lift_rows(win, 2, ec, win.rows_t, NE))
+
+    def f1_hat(st):
+        return win.A1 @ F.force_one(op, st, elems=els)[win.Z1]
+
+    def ftv_hat(st, vc_hat):
+        u = lift_rows(win, 1, vc_hat, win.rows_k, NV)
+        return win.A2 @ F.force_tv(op, st, u, elems=els)[win.Z2]
+
+    # stage 1 at y~_n
+    s1 = F.stress(op, *lift_state(xh, vh, eh), elems=els)
+    v_half = vh - 0.5 * dt * f1_hat(s1)
+    e_half = eh + 0.5 * dt * ftv_hat(s1, v_half)
+    x_half = xh + 0.5 * dt * (win.bx + win.Bxv @ v_half)
+    # stage 2 at y~_{n+1/2}
+    s2 = F.stress(op, *lift_state(x_half, v_half, e_half), elems=els)
+    v_new = vh - dt * f1_hat(s2)
+    v_bar = 0.5 * (vh + v_new)
+    e_new = eh + dt * ftv_hat(s2, v_bar)
+    x_new = xh + dt * (win.bx + win.Bxv @ v_bar)
+    tau = min(float(np.min(s1.tau)), float(np.min(s2.tau)))
+    return (x_new, v_new, e_new), (x_half, v_half, e_half), tau
+
+
+@dataclass
+class ROMRun:
+    t: list
+    dt: list
+    w: int
+    yhat: tuple
+    rejections: int = 0
+    window_of_step: list = field(default_factory=list)
+
+
+def initial_coords(rom: ROM, y0: tuple):
+    win = rom.windows[0]
+    return tuple(win.Phi[f].T @ (y0[f] - win.os[f]) for f in range(3))
+
+
+def switch_window(rom: ROM, w: int, yhat: tuple) -> tuple:
+    win = rom.windows[w]
+    return tuple(win.trans[f][0] @ yhat[f] + win.trans[f][1] for f in range(3))
+
+
+def run_rom(op: F.Operator, rom: ROM, y0: tuple, t_final: float, dt_replay=None, fixed_dt=None,
+            max_steps=10**7) -> ROMRun:
+    """Online phase from t = 0 to t_final (same step control as the FOM)."""
+    w = 0
+    yhat = initial_coords(rom, y0)
+    t = 0.0
+    run = ROMRun([0.0], [], 0, yhat)
+    if fixed_dt is not None:
+        dt = fixed_dt
+    elif dt_replay is None:
+        win = rom.windows[0]
+        st = F.stress(op, lift_rows(win, 0, yhat[0], win.rows_k, op.mesh.NV),
+                      lift_rows(win, 1, yhat[1], win.rows_k, op.mesh.NV),
+                      lift_rows(win, 2, yhat[2], win.rows_t, op.mesh.NE), elems=win.elems)
+        dt = F.BETA1 * float(np.min(st.tau))
+    n = 0
+    while (F.not_done(t, t_final) if dt_replay is None else n < len(dt_replay)) and n < max_steps:
+        h = dt_replay[n] if dt_replay is not None else F.final_step_clip(t, t_final, dt)
+        new, _, tau = rom_step(op, rom.windows[w], *yhat, h)
+        if fixed_dt is None and dt_replay is None:
+            if h >= tau:
+                dt = F.BETA1 * h
+                run.rejections += 1
+                continue
+            dt = F.BETA2 * h if h <= F.GAMMA_DT * tau else h
+        yhat = new
+        t = t + h
+        n += 1
+        run.t.append(t)
+        run.dt.append(h)
+        run.window_of_step.append(w)
+        while w + 1 < len(rom.windows) and t >= rom.windows[w].T_end:
+            w += 1
+            yhat = switch_window(rom, w, yhat)
+    run.w = w
+    run.yhat = yhat
+    return run
+
+
+def final_lift(rom: ROM, run: ROMRun):
+    win = rom.windows[run.w]
+    return tuple(lift_full(win, f, run.yhat[f]) for f in range(3))
+
+
+def relative_errors(fom_final: tuple, rom_final: tuple):
+    """Per-field ||y - y~||_2 / ||y||_2 at the final time (eq. relerrors), order (x, v, e)."""
+    return tuple(float(np.linalg.norm(a - b) / np.linalg.norm(a)) for a, b in zip(fom_final, rom_final))

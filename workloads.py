@@ -1,0 +1,135 @@
+"""Seeded synthetic workload definitions shared by the tests, smoke() and bench.py.
+
+This module holds only parameters and random draws: mesh sizes, domains,
+physical constants, time horizons, window and basis settings and the
+parameter samples of batched instances.  It contains none of the method's
+arithmetic, so both the oracle and the GPU path can be fed from it without
+sharing any computation.
+
+The benchmark problems are the paper's analytic initial-value problems
+(Sec. 6.1): there is no dataset behind them, only the mesh files of the
+original code, which are uniform boxes and are generated here.  Random
+parameters come from NumPy's PCG64 seeded with 210411404; instance i takes
+the i-th draw of each listed distribution, in the order listed.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+SEED = 210411404
+
+TAYLOR_GREEN = "taylor_green"
+SEDOV = "sedov"
+GRESHO = "gresho"
+PROBLEM_IDS = {TAYLOR_GREEN: 1, SEDOV: 2, GRESHO: 3}
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    problem: str
+    dim: int
+    nel: tuple
+    lo: tuple
+    hi: tuple
+    gamma: float
+    use_av: bool
+    cfl: float
+    t_final: float
+    fixed_dt: float = 0.0  # 0 = adaptive step control
+    n_windows: int = 1
+    window_mode: str = "samples"  # "samples" (by snapshot count) or "physical"
+    energy_frac: float = 0.9999
+    n_fixed: tuple = ()  # fixed POD dims (x, v, e); empty = energy criterion
+    n_max: int = 0  # cap on POD dims (0 = none)
+    lam: tuple = (2.0, 2.0)  # oversampling factors for F.1 and F^T.v
+    amp: float = 1.0
+    p_bg: float = 3.0 + 4.0 * np.log(2.0)
+    energy: float = 0.25
+    params: tuple = field(default_factory=tuple)  # per-instance dicts for batches
+
+    @property
+    def n_nodes(self) -> int:
+        return int(np.prod([2 * n + 1 for n in self.nel[: self.dim]]))
+
+    @property
+    def NV(self) -> int:
+        return self.dim * self.n_nodes
+
+    @property
+    def NE(self) -> int:
+        return (2 ** self.dim) * int(np.prod(self.nel[: self.dim]))
+
+    @property
+    def n_elem(self) -> int:
+        return int(np.prod(self.nel[: self.dim]))
+
+
+def tg2d(n: int = 8) -> Workload:
+    """2D Taylor-Green on [0,1]^2, fixed dt = 1e-3 to t = 0.1, one window, dims 6/6/6."""
+    return Workload("tg2d", TAYLOR_GREEN, 2, (n, n), (0.0, 0.0), (1.0, 1.0), 5.0 / 3.0, True, 0.5, 0.1,
+                    fixed_dt=1e-3, n_windows=1, n_fixed=(6, 6, 6))
+
+
+def sedov2d(n: int = 64, t_final: float = 0.8, n_windows: int = 10) -> Workload:
+    """2D Sedov blast on [0,1.2]^2, energy 0.25 in the origin element, adaptive dt."""
+    return Workload("sedov2d", SEDOV, 2, (n, n), (0.0, 0.0), (1.2, 1.2), 1.4, True, 0.5, t_final,
+                    n_windows=n_windows, window_mode="samples", energy=0.25)
+
+
+def gresho2d(n: int = 48, t_final: float = 0.1) -> Workload:
+    """2D Gresho vortex on [-1/2,1/2]^2, no artificial viscosity."""
+    return Workload("gresho2d", GRESHO, 2, (n, n), (-0.5, -0.5), (0.5, 0.5), 5.0 / 3.0, False, 0.5, t_final)
+
+
+def tg3d(n: int = 24, t_final: float = 0.05) -> Workload:
+    return Workload("tg3d", TAYLOR_GREEN, 3, (n, n, n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), 5.0 / 3.0, True, 0.1,
+                    t_final, n_fixed=(20, 20, 20))
+
+
+def sedov3d(n: int = 32, t_final: float = 0.8) -> Workload:
+    return Workload("sedov3d", SEDOV, 3, (n, n, n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), 1.4, True, 0.5, t_final,
+                    n_windows=20, energy=0.25)
+
+
+def rng(seed: int = SEED) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def gresho_batch(n_inst: int = 256, n: int = 48, t_final: float = 0.1, seed: int = SEED) -> Workload:
+    """Batched Gresho instances: A ~ U[0.5,1.5], P ~ U[3,7], dims ~ U{8..40}, windows ~ U{1..8}."""
+    g = rng(seed)
+    amps = g.uniform(0.5, 1.5, n_inst)
+    pbgs = g.uniform(3.0, 7.0, n_inst)
+    dims = g.integers(8, 41, n_inst)
+    wins = g.integers(1, 9, n_inst)
+    params = tuple(dict(amp=float(a), p_bg=float(p), n=int(d), n_windows=int(w))
+                   for a, p, d, w in zip(amps, pbgs, dims, wins))
+    return replace(gresho2d(n, t_final), name="gresho2d_batch", window_mode="physical", params=params)
+
+
+def sedov_energies(n_inst: int = 64, seed: int = SEED) -> np.ndarray:
+    return rng(seed).uniform(0.2, 0.3, n_inst)
+
+
+def random_state(wl: Workload, seed: int, scale: float = 0.02):
+    """A smooth-ish perturbed state for single-call parity tests.
+
+    Positions are the nodes displaced by a small random field (keeping every
+    element valid), velocities and energies are random with the problem's
+    magnitudes.  Returns (x, v, e, v_c) as float64 arrays in the solver's
+    layouts (component-major kinematic, element-major thermodynamic).
+    """
+    g = rng(seed)
+    d = wl.dim
+    axes = [np.linspace(wl.lo[c], wl.hi[c], 2 * wl.nel[c] + 1) for c in range(d)]
+    grids = np.meshgrid(*axes, indexing="ij")
+    X = np.stack([gr.transpose(tuple(reversed(range(d)))).ravel() for gr in grids], axis=0)  # (d, nn)
+    h = np.array([(wl.hi[c] - wl.lo[c]) / wl.nel[c] for c in range(d)])
+    x = (X + scale * h[:, None] * g.uniform(-1, 1, X.shape)).ravel()
+    v = g.normal(0.0, 1.0, d * X.shape[1])
+    e = g.uniform(0.5, 2.0, wl.NE)
+    vc = g.normal(0.0, 1.0, d * X.shape[1])
+    return x, v, e, vc
