@@ -1,0 +1,294 @@
+/*
+ * lagrom.h -- C ABI of the MI355X library for hyper-reduced Lagrangian
+ * hydrodynamics (Copeland, Cheung, Huynh, Choi, "Reduced order models for
+ * Lagrangian hydrodynamics", arXiv 2104.11404).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory   Arrays marked (dev) are device pointers owned by the caller; the
+ *          library never frees or reallocates them.  Arrays marked (host)
+ *          are host pointers.  Matrices are column-major with an explicit
+ *          leading dimension.  Scratch memory comes from a caller-provided
+ *          workspace whose size is given by the matching *_workspace_size
+ *          query; hot calls (fom_force, rom_step) never allocate.
+ * Streams  Every call takes a hipStream_t and is asynchronous on it unless
+ *          its comment says it synchronises.
+ * Layout   Uniform Cartesian mesh of nel[0] x nel[1] (x nel[2]) elements.
+ *          Kinematic (Q2, continuous) vectors of length N_V = d * N_nodes are
+ *          component-major: entry c * N_nodes + node, node = gx + Nx (gy + Ny gz),
+ *          Nx = 2 nel[0] + 1.  Thermodynamic (Q1, discontinuous) vectors of
+ *          length N_E = 2^d * N_elem are element-major: entry K * 2^d + j,
+ *          K = ex + nel[0] (ey + nel[1] ez), local j lexicographic, x fastest.
+ * Errors   Every int-returning call returns LH_OK (0) or a negative
+ *          lh_status.  Conditions detected inside kernels (tangled element,
+ *          non-finite value) are latched in a device status word of the
+ *          problem and reported by the next call that synchronises, or by
+ *          lh_status_read.  lh_last_error() returns a thread-local message
+ *          describing the most recent failure.  No C++ exception crosses
+ *          this interface.
+ * Threads  Handles are immutable after creation and may be shared by
+ *          several streams for read-only calls.
+ */
+#ifndef LAGROM_H
+#define LAGROM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum lh_status {
+    LH_OK = 0,
+    LH_EINVAL = -1,       /* invalid argument or size                        */
+    LH_EWORKSPACE = -2,   /* workspace smaller than the query returned       */
+    LH_EDEVICE = -3,      /* a HIP runtime call failed                       */
+    LH_ETANGLED = -4,     /* det J <= 0 at some quadrature point             */
+    LH_ENONFINITE = -5,   /* NaN or Inf in a state or result                 */
+    LH_EDTCOLLAPSE = -6,  /* step size fell below the minimum                */
+    LH_ERANK = -7         /* Z^T Phi_F numerically rank deficient            */
+};
+
+/* Device status word bits (lh_status_read returns them OR-ed). */
+enum { LH_FLAG_TANGLED = 1, LH_FLAG_NONFINITE = 2, LH_FLAG_DTCOLLAPSE = 4 };
+
+enum lh_problem_kind { LH_TAYLOR_GREEN = 1, LH_SEDOV = 2, LH_GRESHO = 3 };
+
+/* Problem description (Sec. 2 and Sec. 6.1 of the paper).  Q2-Q1 elements,
+ * 4 Gauss-Legendre points per direction, rho0 = 1, wall boundary conditions
+ * v.n = 0 on every face of the box. */
+typedef struct {
+    int32_t dim;        /* 2 or 3                                           */
+    int32_t nel[3];     /* elements per direction (nel[2] ignored in 2D)    */
+    double lo[3];       /* box lower corner                                 */
+    double hi[3];       /* box upper corner                                 */
+    int32_t kind;       /* lh_problem_kind: selects the initial condition   */
+    int32_t use_av;     /* artificial viscosity on (1) / off (0)            */
+    double gamma;       /* adiabatic index of the ideal gas (eq. EOS)       */
+    double cfl;         /* alpha of eq. adaptive-timestep                   */
+    double amp;         /* Taylor-Green / Gresho velocity amplitude         */
+    double p_bg;        /* Gresho background pressure                       */
+    double energy;      /* Sedov deposited energy                           */
+} lh_problem_desc;
+
+typedef struct lh_problem lh_problem;
+
+/* Create a problem: validates the description, builds the reference-element
+ * tables and the per-axis inverse mass matrices, allocates the device status
+ * word.  Synchronises.  *out is owned by the caller (lh_problem_destroy). */
+int lh_problem_create(const lh_problem_desc* desc, lh_problem** out);
+void lh_problem_destroy(lh_problem* p);
+
+/* Sizes: N_V, N_E, number of elements and of Q2 nodes (all may be NULL). */
+int lh_problem_sizes(const lh_problem* p, int64_t* nv, int64_t* ne, int64_t* n_elem, int64_t* n_nodes);
+
+/* Initial state of the problem's benchmark (Sec. 6.1): node positions x,
+ * nodal velocities v (N_V each, dev) and energies e (N_E, dev) interpolated
+ * at the Q1 nodes.  Taylor-Green and Gresho fields scale with amp (velocity)
+ * and amp^2 (pressure perturbation); Gresho adds p_bg; Sedov puts
+ * energy / |K| on every dof of the element at the origin. */
+int lh_initial_state(const lh_problem* p, double* x, double* v, double* e, hipStream_t stream);
+
+/* ---------------------------------------------------------------- force */
+
+enum {
+    LH_F1 = 1,           /* compute F.1 (assembled, N_V)                     */
+    LH_FTV = 2,          /* compute F^T.v_c (N_E)                            */
+    LH_TAU = 4,          /* compute min over quadrature points of the step estimate */
+    LH_KEEP_STRESS = 8,  /* store the pulled-back stress of every qp in work  */
+    LH_USE_STRESS = 16,  /* take the stress stored by the previous KEEP call  */
+    LH_NO_BC = 32        /* do not zero the wall-constrained rows of F.1      */
+};
+
+/* Workspace bytes needed by fom_force for this problem (any ops). */
+size_t lh_fom_force_workspace_size(const lh_problem* p);
+
+/* The force matrix F(x, v, e) of eq. fom and its two contractions
+ * (eq. forceOneforceTv): F1 = F.1 and Ftv = F^T.v_c, plus
+ * tau_min = min over quadrature points of eq. adaptive-timestep.
+ *   F_{(a,c),j} = int sigma : grad(N_a e_c) phi_j dx,
+ *   sigma = -p I + mu eps(v),  p = (gamma - 1) rho e.
+ * x, v (N_V, dev), e (N_E, dev): state.  v_c (N_V, dev): velocity contracted
+ * with F^T (may equal v; NULL means v).  elems (dev, int32, n_elems) restricts
+ * the evaluation to a list of element ids in [0, N_elem) (out-of-range ids
+ * are skipped and set LH_FLAG_NONFINITE); n_elems < 0 evaluates every
+ * element and ignores elems; n_elems = 0 evaluates none.
+ * F1 (N_V, dev): overwritten entirely; rows of unlisted elements are zero
+ * and wall-constrained rows are zero unless LH_NO_BC.  Ftv (N_E, dev): the
+ * dofs of evaluated elements are written, others untouched.  tau_min (dev, 1
+ * double): overwritten with the minimum (+inf if no element is limiting).
+ * With LH_USE_STRESS only LH_FTV may be requested and x, v, e are ignored.
+ * A tangled element (det J <= 0) sets LH_FLAG_TANGLED in the status word. */
+int fom_force(const lh_problem* p, const double* x, const double* v, const double* e, const double* v_c,
+              const int32_t* elems, int32_t n_elems, uint32_t ops, double* F1, double* Ftv, double* tau_min,
+              void* work, size_t work_bytes, hipStream_t stream);
+
+/* Kinematic mass solve out = M_V^{-1} rhs with the wall-constrained rows
+ * eliminated (constrained entries of out are zero), and thermodynamic mass
+ * solve out = M_E^{-1} rhs (eq. fom).  rhs and out (dev) may alias. */
+int lh_mass_solve_v(const lh_problem* p, const double* rhs, double* out, hipStream_t stream);
+int lh_mass_solve_e(const lh_problem* p, const double* rhs, double* out, hipStream_t stream);
+
+/* Total energy 1/2 v^T M_V v + 1^T M_E e (host result).  Synchronises. */
+int lh_total_energy(const lh_problem* p, const double* v, const double* e, double* out, hipStream_t stream);
+
+/* ------------------------------------------------------------- FOM run */
+
+typedef struct {
+    double t_final;          /* integrate from t = 0 (x, v, e hold the initial state) */
+    double fixed_dt;         /* > 0: constant step, no rejection                   */
+    const double* dt_replay; /* (host) step sizes to replay, or NULL               */
+    int32_t n_replay;
+    int32_t max_steps;       /* hard cap on accepted steps                          */
+    /* snapshot storage (dev, column-major, ld N_V / N_E), stage and step
+     * states of every accepted step in order: column 2n = y_{n+1/2},
+     * column 2n+1 = y_{n+1}.  NULL disables recording. */
+    double* snap_x;
+    double* snap_v;
+    double* snap_e;
+    int32_t max_snap;
+    double* t_out;           /* (host, max_steps + 1) accepted times t_0 .. t_Nt  */
+    double* dt_out;          /* (host, max_steps) accepted step sizes             */
+} lh_fom_run_desc;
+
+typedef struct {
+    int32_t n_steps;
+    int32_t n_rejected;
+    int32_t n_snap;
+    int32_t status;
+} lh_fom_run_stats;
+
+/* Workspace bytes needed by lh_fom_run. */
+size_t lh_fom_run_workspace_size(const lh_problem* p);
+
+/* Full-order RK2-average integration (eq. RK2-avg) with the step control of
+ * Sec. 2.2.3 (reject when h >= tau, retry with 0.85 h; grow the next step to
+ * 1.02 h when h <= 0.8 tau; first step 0.85 tau(y_0); last step clipped to
+ * t_final).  x, v, e (dev) are advanced in place.  Synchronises once per
+ * step to read tau. */
+int lh_fom_run(const lh_problem* p, double* x, double* v, double* e, const lh_fom_run_desc* desc,
+               lh_fom_run_stats* stats, void* work, size_t work_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------ POD */
+
+size_t rom_build_basis_workspace_size(int64_t N, int32_t m);
+
+/* POD of a snapshot matrix (eq. SVD, eq. energy_criteria): S = U Sigma V^T,
+ * Phi = leading n columns of U, n the smallest dimension whose singular
+ * value sum reaches energy_frac of the total (or n_fixed when > 0), capped
+ * by n_max.  Computed as a Householder QR of S (FP64), a one-sided Jacobi
+ * SVD of the m x m triangular factor and Phi = Q U_R.  Columns are signed
+ * so that their largest-magnitude entry (first such row) is positive.
+ * S (dev, N x m, ldS >= N) is not modified.  Phi (dev, N x n_max, ldPhi).
+ * sigma (dev, m) receives all singular values in descending order.
+ * *n_out (host) receives n.  Synchronises (reads the singular values). */
+int rom_build_basis(const double* S, int64_t N, int32_t m, int64_t ldS, double energy_frac, int32_t n_fixed,
+                    int32_t n_max, double* Phi, int64_t ldPhi, double* sigma, int32_t* n_out, void* work,
+                    size_t work_bytes, hipStream_t stream);
+
+/* ----------------------------------------------------------------- DEIM */
+
+size_t rom_sample_deim_workspace_size(int64_t N, int32_t n, int32_t n_s);
+
+/* Oversampled greedy DEIM (Sec. 3.6) on the nonlinear-term basis U
+ * (dev, N x n, ld): n_s = min(N, n_s) row indices written to idx (dev,
+ * selection order) and the pseudo-inverse (Z^T U)^+ (dev, n x n_s,
+ * column-major, ld n) of eq. sol-ls-hyper.  Iteration k takes
+ * floor(n_s/n) + [k < n_s mod n] rows of largest quantised residual
+ * floor(|r_j| / max|r| * 2^40), ties to the smallest index.  Returns
+ * LH_ERANK when cond(Z^T U) > 1e12.  Synchronises (reads the condition). */
+int rom_sample_deim(const double* U, int64_t N, int32_t n, int64_t ld, int32_t n_s, int32_t* idx, double* pinv,
+                    void* work, size_t work_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------ ROM */
+
+/* One time window of one ROM instance (Sec. 4): bases, offsets, sampling
+ * and the DEIM pseudo-inverses of the SNS system (eq. rom-hr-sns).  All
+ * pointers (dev) are read during rom_create only. */
+typedef struct {
+    double t_end;                 /* T_w                                           */
+    int32_t n[3];                 /* n_x, n_v, n_e                                 */
+    const double* phi[3];         /* Phi_x (N_V x n_x), Phi_v (N_V x n_v), Phi_e (N_E x n_e), ld N */
+    const double* os[3];          /* offsets x_os, v_os (N_V), e_os (N_E)          */
+    const int32_t* z1;            /* sampled kinematic rows (n_s1)                 */
+    int32_t n_s1;
+    const int32_t* z2;            /* sampled thermodynamic rows (n_s2)             */
+    int32_t n_s2;
+    const double* a1;             /* (Z1^T M_V Phi_v)^+ : n_v x n_s1, ld n_v       */
+    const double* a2;             /* (Z2^T M_E Phi_e)^+ : n_e x n_s2, ld n_e       */
+} lh_window_desc;
+
+typedef struct {
+    int32_t n_windows;
+    const lh_window_desc* windows; /* (host) array of n_windows                   */
+    double t_final;
+} lh_instance_desc;
+
+#define LH_NMAX 64
+
+/* Per-instance online state (dev array of n_inst, written by rom_step). */
+typedef struct {
+    double t;
+    double dt;            /* step-size controller value                           */
+    int32_t w;            /* current window                                        */
+    int32_t status;       /* LH_FLAG_* bits                                        */
+    int32_t n_steps;      /* accepted steps                                        */
+    int32_t n_rejected;
+    int32_t n_force_evals;/* sampled-element force evaluations (elements x stages) */
+    int32_t done;
+    double yhat[3][LH_NMAX]; /* x^, v^, e^ of the current window                   */
+} lh_rom_state;
+
+typedef struct lh_rom lh_rom;
+
+enum { LH_FP32_LIFT = 1, LH_REPLAY_DT = 2, LH_FIXED_DT = 4 };
+
+/* Build the online data of n_inst instances sharing one problem: element
+ * closure of the sampled rows, element-local tiles of the sampled basis
+ * rows and offsets, B_xv = Phi_x^T Phi_v, b_x = Phi_x^T v_os and the window
+ * transition maps of eq. ic-tw.  Allocates device memory (not a hot call).
+ * Synchronises. */
+int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst, lh_rom** out,
+               hipStream_t stream);
+void rom_destroy(lh_rom* r);
+
+/* Initialise state[i] at t = 0: reduced coordinates Phi^T (y0 - os) of the
+ * first window from the initial state y0 = (x0, v0, e0) (dev arrays, one
+ * set per instance packed as x0[i*N_V], v0[i*N_V], e0[i*N_E]), dt from
+ * dt0 (> 0) or 0.85 tau(y~_0) when dt0 <= 0. */
+int rom_init_state(const lh_rom* r, const double* x0, const double* v0, const double* e0, double dt0,
+                   lh_rom_state* state, hipStream_t stream);
+
+/* Advance every instance with the RK2-average hyper-reduced scheme
+ * (eq. RK2-avg-rom-hr) and the step control of Sec. 2.2.3, for at most
+ * max_steps accepted steps or until its t_final.  One persistent launch:
+ * each instance is advanced by one workgroup, switching windows on device
+ * (eq. ic-tw).  flags: LH_REPLAY_DT uses dt_replay (dev, n_replay steps,
+ * shared by all instances), LH_FIXED_DT keeps state.dt fixed,
+ * LH_FP32_LIFT lifts and projects in FP32 (FP64 accumulation of the
+ * reduced state).  Asynchronous. */
+int rom_step(const lh_rom* r, lh_rom_state* state, int32_t max_steps, uint32_t flags, const double* dt_replay,
+             int32_t n_replay, hipStream_t stream);
+
+/* Lift the final state of instance i to full size: y = os + Phi y^ (dev
+ * outputs x (N_V), v (N_V), e (N_E)). */
+int rom_lift(const lh_rom* r, const lh_rom_state* state, int32_t inst, double* x, double* v, double* e,
+             hipStream_t stream);
+
+/* Number of sampled elements of (instance, window) (host query). */
+int rom_sampled_elements(const lh_rom* r, int32_t inst, int32_t window, int32_t* n_elems);
+
+/* ---------------------------------------------------------------- misc */
+
+/* Read (and clear) the problem's device status word.  Synchronises. */
+int lh_status_read(const lh_problem* p, int32_t* flags, hipStream_t stream);
+const char* lh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAGROM_H */

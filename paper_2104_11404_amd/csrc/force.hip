@@ -1,0 +1,335 @@
+// fom_force: the force matrix contractions F.1 and F^T.v_c of eq. fom /
+// eq. forceOneforceTv and the step estimate of eq. adaptive-timestep.
+//
+// Layout of the work: one thread per (element, quadrature point).  A block
+// of 256 threads holds 16 elements in 2D (16 qp each) or 4 elements in 3D
+// (one 64-lane wavefront per element).  Element node data are staged in LDS
+// with the x-row of every element loaded as contiguous runs, each thread
+// evaluates the pulled-back stress of its quadrature point, and the
+// per-element contractions (sums over quadrature points) are read back from
+// LDS.  F.1 is assembled without atomics: element-local rows go to the
+// workspace and a second kernel gathers every node's (at most 2^d) element
+// contributions in a fixed order, so results are bitwise reproducible.
+#include "internal.hpp"
+
+namespace lh {
+
+struct ForceArgs {
+    RefTab T;
+    ForceConst fc;
+    int nex, ney, nez;
+    int nnx, nny;
+    int64_t n_nodes;
+    const double* x;
+    const double* v;
+    const double* e;
+    const double* vc;
+    const int32_t* elems;
+    int32_t n_work;  // elements to evaluate
+    int64_t n_elem;
+    uint32_t ops;
+    double* f1_loc;  // (n_elem, NK, DIM) element-local F.1
+    double* ftv;
+    double* stress;  // (n_elem, NQ, DIM, DIM) kept / used stress
+    double* tau;
+    int32_t* status;
+};
+
+template <int DIM>
+struct FCfg {
+    static constexpr int EPB = DIM == 2 ? 16 : 4;  // elements per 256-thread block
+};
+
+template <int DIM>
+__global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
+    constexpr int NQ = ElemDims<DIM>::NQ;
+    constexpr int NK = ElemDims<DIM>::NK;
+    constexpr int NT = ElemDims<DIM>::NT;
+    constexpr int EPB = FCfg<DIM>::EPB;
+    constexpr int DD = DIM * DIM;
+    __shared__ double s_x[EPB][NK * DIM];
+    __shared__ double s_v[EPB][NK * DIM];
+    __shared__ double s_vc[EPB][NK * DIM];
+    __shared__ double s_e[EPB][NT];
+    __shared__ double s_sig[EPB][NQ][DD];
+    __shared__ double s_s[EPB][NQ];
+    __shared__ int s_elem[EPB];
+    __shared__ double s_tau[256];
+
+    const int tid = threadIdx.x;
+    const bool use_stress = (A.ops & LH_USE_STRESS) != 0;
+    const bool want_f1 = (A.ops & LH_F1) && !use_stress;
+    const bool want_ftv = (A.ops & LH_FTV) != 0;
+    const bool want_tau = (A.ops & LH_TAU) && !use_stress;
+    if (tid < EPB) {
+        const int64_t g = (int64_t)blockIdx.x * EPB + tid;
+        int K = g < A.n_work ? (A.elems ? A.elems[g] : (int)g) : -1;  // elems == NULL: every element
+        if (g < A.n_work && (K < 0 || K >= A.n_elem)) {  // out-of-range list entry: skipped and reported
+            atomicOr(A.status, LH_FLAG_NONFINITE);
+            K = -1;
+        }
+        s_elem[tid] = K;
+    }
+    __syncthreads();
+    // stage node data: component-major, element-slot, local node (x fastest)
+    for (int t = tid; t < DIM * EPB * NK; t += 256) {
+        const int c = t / (EPB * NK);
+        const int r = t % (EPB * NK);
+        const int s = r / NK;
+        const int a = r % NK;
+        const int K = s_elem[s];
+        if (K < 0) continue;
+        const int ex = K % A.nex, ey = (K / A.nex) % A.ney, ez = DIM == 3 ? K / (A.nex * A.ney) : 0;
+        const int64_t node = elem_node<DIM>(ex, ey, ez, a, A.nnx, A.nny) + (int64_t)c * A.n_nodes;
+        if (!use_stress) {
+            s_x[s][a * DIM + c] = A.x[node];
+            s_v[s][a * DIM + c] = A.v[node];
+        }
+        if (want_ftv) s_vc[s][a * DIM + c] = A.vc[node];
+    }
+    for (int t = tid; t < EPB * NT; t += 256) {
+        const int s = t / NT;
+        const int K = s_elem[s];
+        if (K >= 0 && !use_stress) s_e[s][t % NT] = A.e[(int64_t)K * NT + t % NT];
+    }
+    __syncthreads();
+
+    const int s = tid / NQ;
+    const int q = tid % NQ;
+    const int K = s_elem[s];
+    double tau = INFINITY;
+    if (K >= 0) {
+        double sig[DIM][DIM];
+        if (use_stress) {
+            const double* src = A.stress + ((int64_t)K * NQ + q) * DD;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) sig[c][i] = src[c * DIM + i];
+        } else {
+            const int fl = qp_stress<DIM>(A.T, A.fc, q, s_x[s], s_v[s], s_e[s], sig, tau);
+            if (fl) atomicOr(A.status, fl);
+            if (A.ops & LH_KEEP_STRESS) {
+                double* dst = A.stress + ((int64_t)K * NQ + q) * DD;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) dst[c * DIM + i] = sig[c][i];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) s_sig[s][q][c * DIM + i] = sig[c][i];
+        if (want_ftv) {
+            // sigma~ : (sum_a v_c,a (x) grad_xi N_a)
+            int qx, qy, qz;
+            q_coords<DIM>(q, qx, qy, qz);
+            double acc = 0.0;
+            for (int a = 0; a < NK; ++a) {
+                int ax, ay, az;
+                a_coords<DIM>(a, ax, ay, az);
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) {
+                    const double g = dshape(A.T, qx, qy, qz, ax, ay, az, i, DIM);
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) acc += sig[c][i] * s_vc[s][a * DIM + c] * g;
+                }
+            }
+            s_s[s][q] = acc;
+        }
+    }
+    if (want_tau) {
+        s_tau[tid] = tau;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) s_tau[tid] = fmin(s_tau[tid], s_tau[tid + w]);
+            __syncthreads();
+        }
+        if (tid == 0 && s_tau[0] < INFINITY) atomic_min_pos_double(A.tau, s_tau[0]);
+    }
+    __syncthreads();
+    if (want_f1) {
+        for (int t = tid; t < EPB * NK * DIM; t += 256) {
+            const int ss = t / (NK * DIM);
+            const int r = t % (NK * DIM);
+            const int a = r / DIM;
+            const int c = r % DIM;
+            const int KK = s_elem[ss];
+            if (KK < 0) continue;
+            int ax, ay, az;
+            a_coords<DIM>(a, ax, ay, az);
+            double acc = 0.0;
+            for (int qq = 0; qq < NQ; ++qq) {
+                int qx, qy, qz;
+                q_coords<DIM>(qq, qx, qy, qz);
+#pragma unroll
+                for (int i = 0; i < DIM; ++i)
+                    acc += s_sig[ss][qq][c * DIM + i] * dshape(A.T, qx, qy, qz, ax, ay, az, i, DIM);
+            }
+            A.f1_loc[((int64_t)KK * NK + a) * DIM + c] = acc;
+        }
+    }
+    if (want_ftv) {
+        for (int t = tid; t < EPB * NT; t += 256) {
+            const int ss = t / NT;
+            const int j = t % NT;
+            const int KK = s_elem[ss];
+            if (KK < 0) continue;
+            double acc = 0.0;
+            for (int qq = 0; qq < NQ; ++qq) {
+                int qx, qy, qz;
+                q_coords<DIM>(qq, qx, qy, qz);
+                acc += tshape<DIM>(A.T, qx, qy, qz, j) * s_s[ss][qq];
+            }
+            A.ftv[(int64_t)KK * NT + j] = acc;
+        }
+    }
+}
+
+// F1[c, node] = sum over the elements containing the node (fixed order) of
+// their local row; wall-constrained rows zeroed unless no_bc.
+template <int DIM>
+__global__ void gather_f1_kernel(const double* __restrict__ f1_loc, double* __restrict__ F1, int nex, int ney,
+                                 int nez, int nnx, int nny, int nnz, int64_t n_nodes, int no_bc) {
+    constexpr int NK = ElemDims<DIM>::NK;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= n_nodes * DIM) return;
+    const int c = (int)(tid / n_nodes);
+    const int64_t node = tid % n_nodes;
+    const int g[3] = {(int)(node % nnx), (int)((node / nnx) % nny), DIM == 3 ? (int)(node / ((int64_t)nnx * nny)) : 0};
+    const int nn[3] = {nnx, nny, nnz};
+    const int ne[3] = {nex, ney, nez};
+    if (!no_bc && (g[c] == 0 || g[c] == nn[c] - 1)) {
+        F1[tid] = 0.0;
+        return;
+    }
+    // candidate elements per axis: g odd -> one; g even -> g/2-1 and g/2 (clipped)
+    int lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        if (k >= DIM) {
+            lo[k] = hi[k] = 0;
+            continue;
+        }
+        if (g[k] & 1) {
+            lo[k] = hi[k] = g[k] >> 1;
+        } else {
+            lo[k] = (g[k] >> 1) - 1;
+            hi[k] = g[k] >> 1;
+            if (lo[k] < 0) lo[k] = 0;
+            if (hi[k] > ne[k] - 1) hi[k] = ne[k] - 1;
+        }
+    }
+    double acc = 0.0;
+    for (int ez = lo[2]; ez <= hi[2]; ++ez)
+        for (int ey = lo[1]; ey <= hi[1]; ++ey)
+            for (int ex = lo[0]; ex <= hi[0]; ++ex) {
+                const int64_t K = ex + (int64_t)nex * (ey + (int64_t)ney * ez);
+                const int a = (g[0] - 2 * ex) + 3 * (g[1] - 2 * ey) + (DIM == 3 ? 9 * (g[2] - 2 * ez) : 0);
+                acc += f1_loc[(K * NK + a) * DIM + c];
+            }
+    F1[tid] = acc;
+}
+
+__global__ void fill_kernel(double* p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+static size_t f1_loc_bytes(const lh_problem* p) {
+    const int nk = p->dim == 3 ? 27 : 9;
+    return sizeof(double) * (size_t)p->n_elem * nk * p->dim;
+}
+
+static size_t stress_bytes(const lh_problem* p) {
+    const int nq = p->dim == 3 ? 64 : 16;
+    return sizeof(double) * (size_t)p->n_elem * nq * p->dim * p->dim;
+}
+
+}  // namespace lh
+
+extern "C" {
+
+size_t lh_fom_force_workspace_size(const lh_problem* p) {
+    if (!p) return 0;
+    return lh::f1_loc_bytes(p) + lh::stress_bytes(p) + 256;
+}
+
+int fom_force(const lh_problem* p, const double* x, const double* v, const double* e, const double* v_c,
+              const int32_t* elems, int32_t n_elems, uint32_t ops, double* F1, double* Ftv, double* tau_min,
+              void* work, size_t work_bytes, hipStream_t stream) {
+    using namespace lh;
+    LH_REQUIRE(p, "fom_force: null problem");
+    LH_REQUIRE(work_bytes >= lh_fom_force_workspace_size(p) && work, "fom_force: workspace too small");
+    const bool use_stress = (ops & LH_USE_STRESS) != 0;
+    LH_REQUIRE(!use_stress || (ops & ~(uint32_t)(LH_USE_STRESS | LH_FTV | LH_NO_BC)) == 0,
+               "fom_force: LH_USE_STRESS allows only LH_FTV");
+    LH_REQUIRE(use_stress || (x && v && e), "fom_force: null state");
+    LH_REQUIRE(!(ops & LH_F1) || F1, "fom_force: F1 requested without output");
+    LH_REQUIRE(!(ops & LH_FTV) || Ftv, "fom_force: Ftv requested without output");
+    LH_REQUIRE(!(ops & LH_TAU) || tau_min, "fom_force: tau requested without output");
+    LH_REQUIRE(n_elems <= p->n_elem, "fom_force: more listed elements than the mesh has");
+    LH_REQUIRE(n_elems <= 0 || elems, "fom_force: element list missing");
+    const bool all = n_elems < 0;
+    if (all) elems = nullptr;
+    if (ops & LH_FTV) {
+        if (!v_c) v_c = v;
+        LH_REQUIRE(v_c, "fom_force: contraction velocity missing");
+    }
+    char* w = static_cast<char*>(work);
+    ForceArgs A;
+    A.T = p->tab;
+    A.fc = p->fc;
+    A.nex = p->nel[0];
+    A.ney = p->nel[1];
+    A.nez = p->nel[2];
+    A.nnx = p->nn[0];
+    A.nny = p->nn[1];
+    A.n_nodes = p->n_nodes;
+    A.x = x;
+    A.v = v;
+    A.e = e;
+    A.vc = v_c;
+    A.elems = elems;
+    A.n_work = all ? (int32_t)p->n_elem : n_elems;
+    A.n_elem = p->n_elem;
+    A.ops = ops;
+    A.f1_loc = reinterpret_cast<double*>(w);
+    A.stress = reinterpret_cast<double*>(w + f1_loc_bytes(p));
+    A.ftv = Ftv;
+    A.tau = tau_min;
+    A.status = p->d_status;
+    const bool want_f1 = (ops & LH_F1) && !use_stress;
+    if (want_f1 && !all) {
+        const int64_t n = (int64_t)(f1_loc_bytes(p) / sizeof(double));
+        hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, A.f1_loc, n, 0.0);
+    }
+    if ((ops & LH_TAU) && !use_stress)
+        hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, stream, tau_min, (int64_t)1, (double)INFINITY);
+    if (A.n_work > 0) {
+        if (p->dim == 2) {
+            const unsigned blocks = (unsigned)((A.n_work + FCfg<2>::EPB - 1) / FCfg<2>::EPB);
+            hipLaunchKernelGGL(force_kernel<2>, dim3(blocks), dim3(256), 0, stream, A);
+        } else {
+            const unsigned blocks = (unsigned)((A.n_work + FCfg<3>::EPB - 1) / FCfg<3>::EPB);
+            hipLaunchKernelGGL(force_kernel<3>, dim3(blocks), dim3(256), 0, stream, A);
+        }
+        int rc = launch_check("force_kernel");
+        if (rc) return rc;
+    }
+    if (want_f1) {
+        const int64_t n = p->n_nodes * p->dim;
+        const unsigned blocks = (unsigned)((n + 255) / 256);
+        const int no_bc = (ops & LH_NO_BC) ? 1 : 0;
+        if (p->dim == 2)
+            hipLaunchKernelGGL(gather_f1_kernel<2>, dim3(blocks), dim3(256), 0, stream, A.f1_loc, F1, p->nel[0],
+                               p->nel[1], 1, p->nn[0], p->nn[1], 1, p->n_nodes, no_bc);
+        else
+            hipLaunchKernelGGL(gather_f1_kernel<3>, dim3(blocks), dim3(256), 0, stream, A.f1_loc, F1, p->nel[0],
+                               p->nel[1], p->nel[2], p->nn[0], p->nn[1], p->nn[2], p->n_nodes, no_bc);
+        return launch_check("gather_f1_kernel");
+    }
+    return LH_OK;
+}
+
+}  // extern "C"

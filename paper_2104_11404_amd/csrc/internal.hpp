@@ -1,0 +1,347 @@
+// Internal declarations shared by the HIP translation units of liblagrom.
+//
+// Reference element [0,1]^d.  Q2 kinematic basis: 1D Lagrange polynomials on
+// the nodes {0, 1/2, 1}; Q1 thermodynamic basis: 1D Lagrange polynomials on
+// the two Gauss-Legendre points 1/2 -+ sqrt(3)/6; quadrature: tensor
+// Gauss-Legendre with 4 points per direction.  Tensor-product values are
+// formed on the fly from the 1D tables, which travel as a kernel argument.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+
+#include "../../include/lagrom.h"
+
+namespace lh {
+
+constexpr int NQ1 = 4;  // quadrature points per direction
+
+// 1D tables at the 4 Gauss-Legendre points of [0,1].
+struct RefTab {
+    double B[NQ1][3];  // Q2 values
+    double D[NQ1][3];  // Q2 derivatives
+    double T[NQ1][2];  // Q1 values
+    double W[NQ1];     // weights
+};
+
+template <int DIM>
+struct ElemDims {
+    static constexpr int NQ = DIM == 2 ? 16 : 64;  // quadrature points
+    static constexpr int NK = DIM == 2 ? 9 : 27;   // Q2 nodes
+    static constexpr int NT = DIM == 2 ? 4 : 8;    // Q1 dofs
+};
+
+// Physical constants of the force evaluation.
+struct ForceConst {
+    double gamma;
+    double cfl;
+    double detJ0;  // det of the (uniform) initial element map; rho0 = 1
+    int use_av;
+};
+
+// Constants of the artificial viscosity and of the step-size estimate.
+constexpr double AV_Q1 = 0.5;
+constexpr double AV_Q2 = 2.0;
+constexpr double ALPHA_MU = 2.5;
+constexpr double ORDER_K = 2.0;
+
+}  // namespace lh
+
+// Host-side problem object.
+struct lh_problem {
+    lh_problem_desc desc;
+    int dim;
+    int nel[3];
+    int nn[3];  // nodes per direction (2 nel + 1)
+    int64_t n_nodes, NV, NE, n_elem;
+    double h[3];
+    lh::RefTab tab;
+    lh::ForceConst fc;
+    double me_diag[8];  // thermodynamic mass of each local dof of an element (diagonal)
+    double* d_minv[3];     // per axis, inverse 1D kinematic mass (row-major nn x nn)
+    double* d_minv_bc[3];  // same with the wall rows/columns eliminated
+    int32_t* d_status;
+    int device;
+    struct lh_problem_extra* ex;  // mass-solve scratch and reduction buffers
+};
+
+namespace lh {
+
+// thread-local error message of the C ABI
+void set_error(const std::string& msg);
+
+#define LH_HIP_CHECK(call)                                                                  \
+    do {                                                                                    \
+        hipError_t _e = (call);                                                             \
+        if (_e != hipSuccess) {                                                             \
+            ::lh::set_error(std::string(#call) + ": " + hipGetErrorString(_e));              \
+            return LH_EDEVICE;                                                              \
+        }                                                                                   \
+    } while (0)
+
+#define LH_REQUIRE(cond, msg)              \
+    do {                                   \
+        if (!(cond)) {                     \
+            ::lh::set_error(msg);          \
+            return LH_EINVAL;              \
+        }                                  \
+    } while (0)
+
+inline int launch_check(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string(what) + ": " + hipGetErrorString(e));
+        return LH_EDEVICE;
+    }
+    return LH_OK;
+}
+
+// ------------------------------------------------------------------ device helpers
+
+__device__ __forceinline__ double dshape(const RefTab& T, int qx, int qy, int qz, int ax, int ay, int az,
+                                         int i, int dim) {
+    // d N_a / d xi_i at (qx, qy, qz)
+    double v = (i == 0 ? T.D[qx][ax] : T.B[qx][ax]) * (i == 1 ? T.D[qy][ay] : T.B[qy][ay]);
+    if (dim == 3) v *= (i == 2 ? T.D[qz][az] : T.B[qz][az]);
+    return v;
+}
+
+template <int DIM>
+__device__ __forceinline__ void q_coords(int q, int& qx, int& qy, int& qz) {
+    qx = q & 3;
+    qy = (q >> 2) & 3;
+    qz = DIM == 3 ? (q >> 4) : 0;
+}
+
+template <int DIM>
+__device__ __forceinline__ void a_coords(int a, int& ax, int& ay, int& az) {
+    ax = a % 3;
+    ay = (a / 3) % 3;
+    az = DIM == 3 ? a / 9 : 0;
+}
+
+template <int DIM>
+__device__ __forceinline__ double qweight(const RefTab& T, int qx, int qy, int qz) {
+    double w = T.W[qx] * T.W[qy];
+    if (DIM == 3) w *= T.W[qz];
+    return w;
+}
+
+template <int DIM>
+__device__ __forceinline__ double tshape(const RefTab& T, int qx, int qy, int qz, int j) {
+    double v = T.T[qx][j & 1] * T.T[qy][(j >> 1) & 1];
+    if (DIM == 3) v *= T.T[qz][(j >> 2) & 1];
+    return v;
+}
+
+// Smallest eigenvalue of a symmetric 3x3 matrix by cyclic Jacobi rotations,
+// and the eigenvalues sorted ascending in lam[].
+__device__ inline void sym3_eig(double a[3][3], double lam[3]) {
+    for (int sweep = 0; sweep < 8; ++sweep) {
+        double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+        double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+        if (off <= 1e-34 * dia || off == 0.0) break;
+        for (int pq = 0; pq < 3; ++pq) {
+            const int p = pq == 2 ? 1 : 0;
+            const int q = pq == 0 ? 1 : 2;
+            const double apq = a[p][q];
+            if (apq == 0.0) continue;
+            const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
+            const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            const double c = 1.0 / sqrt(t * t + 1.0);
+            const double s = t * c;
+            a[p][p] -= t * apq;
+            a[q][q] += t * apq;
+            a[p][q] = a[q][p] = 0.0;
+            const int r = 3 - p - q;
+            const double arp = a[r][p], arq = a[r][q];
+            a[r][p] = a[p][r] = c * arp - s * arq;
+            a[r][q] = a[q][r] = s * arp + c * arq;
+        }
+    }
+    double l0 = a[0][0], l1 = a[1][1], l2 = a[2][2], tmp;
+    if (l0 > l1) { tmp = l0; l0 = l1; l1 = tmp; }
+    if (l1 > l2) { tmp = l1; l1 = l2; l2 = tmp; }
+    if (l0 > l1) { tmp = l0; l0 = l1; l1 = tmp; }
+    lam[0] = l0;
+    lam[1] = l1;
+    lam[2] = l2;
+}
+
+// Pulled-back stress sigma~ = w det J sigma J^{-T} and the step estimate at
+// one quadrature point, from the element-local node positions xe[a*DIM+c],
+// velocities ve[...] and energies ee[j].  Returns status flag bits.
+template <int DIM>
+__device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, int q, const double* xe, const double* ve,
+                                const double* ee, double sig_t[DIM][DIM], double& tau) {
+    constexpr int NK = ElemDims<DIM>::NK;
+    constexpr int NT = ElemDims<DIM>::NT;
+    int qx, qy, qz;
+    q_coords<DIM>(q, qx, qy, qz);
+    double J[DIM][DIM], G[DIM][DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) J[c][i] = G[c][i] = 0.0;
+    for (int a = 0; a < NK; ++a) {
+        int ax, ay, az;
+        a_coords<DIM>(a, ax, ay, az);
+        double g[DIM];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) g[i] = dshape(T, qx, qy, qz, ax, ay, az, i, DIM);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const double xa = xe[a * DIM + c];
+            const double va = ve[a * DIM + c];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+                J[c][i] += xa * g[i];
+                G[c][i] += va * g[i];
+            }
+        }
+    }
+    int flags = 0;
+    double det, Jinv[DIM][DIM];
+    if (DIM == 2) {
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const double id = 1.0 / det;
+        Jinv[0][0] = J[1][1] * id;
+        Jinv[0][1] = -J[0][1] * id;
+        Jinv[1][0] = -J[1][0] * id;
+        Jinv[1][1] = J[0][0] * id;
+    } else {
+        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        const double id = 1.0 / det;
+        double* Ji = &Jinv[0][0];
+        Ji[0 * DIM + 0] = c00 * id;
+        Ji[1 * DIM + 0] = c01 * id;
+        Ji[2 * DIM + 0] = c02 * id;
+        Ji[0 * DIM + 1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+        Ji[1 * DIM + 1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+        Ji[2 * DIM + 1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+        Ji[0 * DIM + 2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+        Ji[1 * DIM + 2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+        Ji[2 * DIM + 2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    }
+    if (!(det > 0.0)) flags |= LH_FLAG_TANGLED;
+    const double w = qweight<DIM>(T, qx, qy, qz);
+    const double cq = w * fc.detJ0;
+    const double rho = cq / (w * det);
+    double eq = 0.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) eq += ee[j] * tshape<DIM>(T, qx, qy, qz, j);
+    const double gm = fc.gamma;
+    const double p = (gm - 1.0) * rho * eq;
+    const double cs = sqrt(fmax(gm * (gm - 1.0) * eq, 0.0));
+    // smallest singular value of J: |det J| / (product of the larger ones)
+    double hmin;
+    {
+        double M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                double s = 0.0;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) s += J[c][i] * J[c][k];
+                M[i][k] = s;
+            }
+        if (DIM == 2) {
+            const double m = 0.5 * (M[0][0] + M[1][1]);
+            const double d = 0.5 * (M[0][0] - M[1][1]);
+            const double lmax = m + sqrt(d * d + M[0][1] * M[0][1]);
+            hmin = fabs(det) / sqrt(lmax) / ORDER_K;
+        } else {
+            double lam[3];
+            sym3_eig(M, lam);
+            hmin = fabs(det) / sqrt(lam[2] * lam[1]) / ORDER_K;
+        }
+    }
+    double sig[DIM][DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) sig[c][k] = c == k ? -p : 0.0;
+    double mu = 0.0;
+    if (fc.use_av) {
+        double eps[DIM][DIM], gv[DIM][DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) s += G[c][i] * Jinv[i][k];
+                gv[c][k] = s;
+            }
+        double tr = 0.0, nrm2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                eps[c][k] = 0.5 * (gv[c][k] + gv[k][c]);
+                nrm2 += eps[c][k] * eps[c][k];
+            }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) tr += eps[c][c];
+        double lmin;
+        if (DIM == 2) {
+            const double m = 0.5 * (eps[0][0] + eps[1][1]);
+            const double d = 0.5 * (eps[0][0] - eps[1][1]);
+            lmin = m - sqrt(d * d + eps[0][1] * eps[0][1]);
+        } else {
+            double a3[3][3], lam[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) a3[c][k] = eps[c % DIM][k % DIM];
+            sym3_eig(a3, lam);
+            lmin = lam[0];
+        }
+        const double ell = hmin;
+        const double psi0 = fmax(0.0, -tr) / (sqrt(nrm2) + 1e-8 * cs / ell + 1e-300);
+        mu = rho * ell * ell * AV_Q2 * fmax(0.0, -lmin) + rho * ell * AV_Q1 * cs * psi0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) sig[c][k] += mu * eps[c][k];
+    }
+    const double wd = w * det;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) s += sig[c][k] * Jinv[i][k];
+            sig_t[c][i] = wd * s;
+            if (!isfinite(sig_t[c][i])) flags |= LH_FLAG_NONFINITE;
+        }
+    const double denom = cs / hmin + ALPHA_MU * mu / (rho * hmin * hmin);
+    tau = denom > 0.0 ? fc.cfl / denom : INFINITY;
+    if (isnan(tau)) flags |= LH_FLAG_NONFINITE;
+    return flags;
+}
+
+// Global node id of local node a of element (ex, ey, ez).
+template <int DIM>
+__device__ __forceinline__ int64_t elem_node(int ex, int ey, int ez, int a, int nnx, int nny) {
+    int ax, ay, az;
+    a_coords<DIM>(a, ax, ay, az);
+    int64_t id = (int64_t)(2 * ex + ax) + (int64_t)nnx * (2 * ey + ay);
+    if (DIM == 3) id += (int64_t)nnx * nny * (2 * ez + az);
+    return id;
+}
+
+__device__ __forceinline__ void atomic_min_pos_double(double* addr, double val) {
+    // non-negative doubles order like their bit patterns
+    atomicMin(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(val));
+}
+
+}  // namespace lh

@@ -1,0 +1,483 @@
+// Problem set-up: reference tables, initial conditions, mass matrices.
+//
+// The kinematic mass matrix M_V = I_d (x) M with M_ab = int rho0 N_a N_b
+// (Sec. 2.1) is, on a uniform Cartesian box with rho0 = 1, the Kronecker
+// product of 1D Q2 mass matrices; wall conditions v.n = 0 remove the first
+// and last node of the axis normal to the wall for that component.  Its
+// inverse is therefore the Kronecker product of small dense 1D inverses,
+// which is how lh_mass_solve_v applies it.  The thermodynamic mass matrix of
+// the Gauss-point Q1 basis is diagonal (the 4-point rule integrates the
+// products exactly and the Lagrange basis at Gauss points is orthogonal).
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace lh {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+static void lagrange(const double* nodes, int n, double x, double* val, double* der) {
+    for (int i = 0; i < n; ++i) {
+        double denom = 1.0, v = 1.0, d = 0.0;
+        for (int m = 0; m < n; ++m)
+            if (m != i) denom *= nodes[i] - nodes[m];
+        for (int m = 0; m < n; ++m)
+            if (m != i) v *= x - nodes[m];
+        for (int skip = 0; skip < n; ++skip) {
+            if (skip == i) continue;
+            double t = 1.0;
+            for (int m = 0; m < n; ++m)
+                if (m != i && m != skip) t *= x - nodes[m];
+            d += t;
+        }
+        val[i] = v / denom;
+        if (der) der[i] = d / denom;
+    }
+}
+
+static RefTab make_tables() {
+    RefTab T;
+    const double s = std::sqrt(6.0 / 5.0);
+    const double t1 = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * s), t2 = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * s);
+    const double w1 = (18.0 + std::sqrt(30.0)) / 36.0, w2 = (18.0 - std::sqrt(30.0)) / 36.0;
+    const double xq[4] = {0.5 * (1.0 - t2), 0.5 * (1.0 - t1), 0.5 * (1.0 + t1), 0.5 * (1.0 + t2)};
+    const double wq[4] = {0.5 * w2, 0.5 * w1, 0.5 * w1, 0.5 * w2};
+    const double k2[3] = {0.0, 0.5, 1.0};
+    const double g = std::sqrt(3.0) / 6.0;
+    const double k1[2] = {0.5 - g, 0.5 + g};
+    for (int q = 0; q < 4; ++q) {
+        lagrange(k2, 3, xq[q], T.B[q], T.D[q]);
+        lagrange(k1, 2, xq[q], T.T[q], nullptr);
+        T.W[q] = wq[q];
+    }
+    return T;
+}
+
+// Gauss-Jordan inverse with partial pivoting of a small dense matrix (row-major).
+static bool invert(std::vector<double>& A, int n) {
+    std::vector<double> I(n * n, 0.0);
+    for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+        if (A[piv * n + c] == 0.0) return false;
+        if (piv != c)
+            for (int k = 0; k < n; ++k) {
+                std::swap(A[c * n + k], A[piv * n + k]);
+                std::swap(I[c * n + k], I[piv * n + k]);
+            }
+        const double d = 1.0 / A[c * n + c];
+        for (int k = 0; k < n; ++k) {
+            A[c * n + k] *= d;
+            I[c * n + k] *= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double f = A[r * n + c];
+            if (f == 0.0) continue;
+            for (int k = 0; k < n; ++k) {
+                A[r * n + k] -= f * A[c * n + k];
+                I[r * n + k] -= f * I[c * n + k];
+            }
+        }
+    }
+    A.swap(I);
+    return true;
+}
+
+// ------------------------------------------------------------- kernels
+
+__global__ void initial_state_kernel(lh_problem_desc d, int dim, int nnx, int nny, int nnz, int64_t n_nodes,
+                                     int64_t n_elem, double hx, double hy, double hz, double* x, double* v,
+                                     double* e) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double pi = 3.14159265358979323846;
+    const double A = d.amp;
+    if (tid < n_nodes) {
+        const int gx = (int)(tid % nnx);
+        const int gy = (int)((tid / nnx) % nny);
+        const int gz = dim == 3 ? (int)(tid / ((int64_t)nnx * nny)) : 0;
+        const double X = d.lo[0] + gx * (0.5 * hx);
+        const double Y = d.lo[1] + gy * (0.5 * hy);
+        const double Z = dim == 3 ? d.lo[2] + gz * (0.5 * hz) : 0.0;
+        x[tid] = X;
+        x[n_nodes + tid] = Y;
+        if (dim == 3) x[2 * n_nodes + tid] = Z;
+        double vx = 0.0, vy = 0.0, vz = 0.0;
+        if (d.kind == LH_TAYLOR_GREEN) {
+            if (dim == 2) {
+                vx = A * sin(pi * X) * cos(pi * Y);
+                vy = -A * cos(pi * X) * sin(pi * Y);
+            } else {
+                vx = A * sin(pi * X) * cos(pi * Y) * cos(pi * Z);
+                vy = -A * cos(pi * X) * sin(pi * Y) * cos(pi * Z);
+            }
+        } else if (d.kind == LH_GRESHO) {
+            const double r = sqrt(X * X + Y * Y);
+            const double vphi = r < 0.2 ? 5.0 * r : (r < 0.4 ? 2.0 - 5.0 * r : 0.0);
+            if (r > 0.0) {
+                vx = -A * vphi * Y / r;
+                vy = A * vphi * X / r;
+            }
+        }
+        v[tid] = vx;
+        v[n_nodes + tid] = vy;
+        if (dim == 3) v[2 * n_nodes + tid] = vz;
+    }
+    const int nt = dim == 3 ? 8 : 4;
+    if (tid < n_elem * nt) {
+        const int64_t K = tid / nt;
+        const int j = (int)(tid % nt);
+        const int nex = d.nel[0], ney = d.nel[1];
+        const int ex = (int)(K % nex), ey = (int)((K / nex) % ney), ez = dim == 3 ? (int)(K / ((int64_t)nex * ney)) : 0;
+        const double g = sqrt(3.0) / 6.0;
+        const double gj[2] = {0.5 - g, 0.5 + g};
+        const double X = d.lo[0] + hx * (ex + gj[j & 1]);
+        const double Y = d.lo[1] + hy * (ey + gj[(j >> 1) & 1]);
+        const double Z = dim == 3 ? d.lo[2] + hz * (ez + gj[(j >> 2) & 1]) : 0.0;
+        const double rho0 = 1.0;
+        double p = 0.0;
+        double ev;
+        if (d.kind == LH_SEDOV) {
+            const double vol = hx * hy * (dim == 3 ? hz : 1.0);
+            ev = K == 0 ? d.energy / (rho0 * vol) : 0.0;
+        } else {
+            if (d.kind == LH_TAYLOR_GREEN) {
+                if (dim == 2)
+                    p = 1.0 + A * A * (cos(2 * pi * X) + cos(2 * pi * Y)) / 4.0;
+                else
+                    p = 100.0 + A * A * ((cos(2 * pi * X) + cos(2 * pi * Y)) * (cos(2 * pi * Z) + 2.0) - 2.0) / 16.0;
+            } else {  // Gresho, with the r^2 term of the middle branch
+                const double r = sqrt(X * X + Y * Y);
+                const double ln2 = log(2.0);
+                double pg;
+                if (r < 0.2)
+                    pg = 5.0 + 12.5 * r * r;
+                else if (r < 0.4)
+                    pg = 9.0 - 4.0 * log(0.2) + 12.5 * r * r - 20.0 * r + 4.0 * log(r);
+                else
+                    pg = 3.0 + 4.0 * ln2;
+                p = d.p_bg + A * A * (pg - (3.0 + 4.0 * ln2));
+            }
+            ev = p / ((d.gamma - 1.0) * rho0);
+        }
+        e[tid] = ev;
+    }
+}
+
+// out[idx] = sum_k M[i][k] in[base + k*stride] along one axis of a tensor grid.
+__global__ void apply_axis_kernel(const double* __restrict__ in, double* __restrict__ out,
+                                  const double* __restrict__ M, int n, int64_t stride, int64_t total) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int i = (int)((idx / stride) % n);
+    const int64_t base = idx - (int64_t)i * stride;
+    const double* row = M + (int64_t)i * n;
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += row[k] * in[base + (int64_t)k * stride];
+    out[idx] = s;
+}
+
+__global__ void diag_scale_kernel(const double* in, double* out, const double* __restrict__ dinv, int nt,
+                                  int64_t n) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) out[idx] = in[idx] * dinv[idx % nt];
+}
+
+__global__ void dot_partial_kernel(const double* a, const double* b, int64_t n, double* partial) {
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += a[i] * b[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+__global__ void weighted_sum_partial_kernel(const double* e, int64_t n, const double* __restrict__ wloc, int nt,
+                                            double* partial) {
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += e[i] * wloc[i % nt];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+}  // namespace lh
+
+// Device state a problem keeps for its mass solves and reductions.  The
+// scratch is shared by every call on the problem, so the calls that use it
+// (mass solves, total energy) hold the mutex; they must still not overlap on
+// two streams of the device.
+struct lh_problem_extra {
+    double* d_m[3];     // forward 1D mass matrices
+    double* d_tmp;      // 3 * N_nodes scratch for tensor applications
+    double* d_medinv;   // 8 entries: inverse thermodynamic mass per local dof
+    double* d_mediag;   // 8 entries
+    double* d_partial;  // reduction partials
+    std::mutex mtx;
+};
+typedef lh_problem_extra ProblemExtra;
+
+static ProblemExtra* extra_of(const lh_problem* p) { return p->ex; }
+
+extern "C" {
+
+const char* lh_last_error(void) { return lh::g_err.c_str(); }
+
+int lh_problem_create(const lh_problem_desc* desc, lh_problem** out) {
+    using namespace lh;
+    LH_REQUIRE(desc && out, "lh_problem_create: null argument");
+    LH_REQUIRE(desc->dim == 2 || desc->dim == 3, "lh_problem_create: dim must be 2 or 3");
+    for (int c = 0; c < desc->dim; ++c) {
+        LH_REQUIRE(desc->nel[c] >= 1 && desc->nel[c] <= 4096, "lh_problem_create: nel out of range");
+        LH_REQUIRE(desc->hi[c] > desc->lo[c], "lh_problem_create: empty box");
+    }
+    LH_REQUIRE(desc->kind >= LH_TAYLOR_GREEN && desc->kind <= LH_GRESHO, "lh_problem_create: unknown kind");
+    LH_REQUIRE(desc->gamma > 1.0, "lh_problem_create: gamma must exceed 1");
+    LH_REQUIRE(desc->cfl > 0.0, "lh_problem_create: cfl must be positive");
+    LH_REQUIRE(!(desc->kind == LH_GRESHO && desc->dim != 2), "lh_problem_create: Gresho is two-dimensional");
+    lh_problem* p = new lh_problem();
+    ProblemExtra* ex = new ProblemExtra();
+    p->ex = ex;
+    p->desc = *desc;
+    p->dim = desc->dim;
+    p->n_nodes = 1;
+    p->n_elem = 1;
+    for (int c = 0; c < 3; ++c) {
+        p->nel[c] = c < p->dim ? desc->nel[c] : 1;
+        p->nn[c] = c < p->dim ? 2 * desc->nel[c] + 1 : 1;
+        p->h[c] = c < p->dim ? (desc->hi[c] - desc->lo[c]) / desc->nel[c] : 1.0;
+        p->n_nodes *= p->nn[c];
+        p->n_elem *= p->nel[c];
+    }
+    p->NV = p->dim * p->n_nodes;
+    p->NE = (p->dim == 3 ? 8 : 4) * p->n_elem;
+    p->tab = make_tables();
+    double detJ0 = 1.0;
+    for (int c = 0; c < p->dim; ++c) detJ0 *= p->h[c];
+    p->fc.gamma = desc->gamma;
+    p->fc.cfl = desc->cfl;
+    p->fc.detJ0 = detJ0;
+    p->fc.use_av = desc->use_av;
+    // thermodynamic mass (diagonal): sum_q rho0 detJ0 w_q phi_j(q)^2
+    const int nt = p->dim == 3 ? 8 : 4;
+    const int nq = p->dim == 3 ? 64 : 16;
+    double medinv[8];
+    for (int j = 0; j < nt; ++j) {
+        double s = 0.0;
+        for (int q = 0; q < nq; ++q) {
+            const int qx = q & 3, qy = (q >> 2) & 3, qz = q >> 4;
+            double ph = p->tab.T[qx][j & 1] * p->tab.T[qy][(j >> 1) & 1];
+            double w = p->tab.W[qx] * p->tab.W[qy];
+            if (p->dim == 3) {
+                ph *= p->tab.T[qz][(j >> 2) & 1];
+                w *= p->tab.W[qz];
+            }
+            s += w * detJ0 * ph * ph;
+        }
+        p->me_diag[j] = s;
+        medinv[j] = 1.0 / s;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        delete ex;
+        delete p;
+        set_error("lh_problem_create: no HIP device");
+        return LH_EDEVICE;
+    }
+    p->device = dev;
+    auto fail = [&](const char* what) {
+        set_error(std::string("lh_problem_create: ") + what);
+        lh_problem_destroy(p);
+        return LH_EDEVICE;
+    };
+    for (int c = 0; c < 3; ++c) {
+        p->d_minv[c] = p->d_minv_bc[c] = nullptr;
+        ex->d_m[c] = nullptr;
+    }
+    ex->d_tmp = ex->d_medinv = ex->d_mediag = ex->d_partial = nullptr;
+    p->d_status = nullptr;
+    for (int c = 0; c < p->dim; ++c) {
+        const int n = p->nn[c];
+        std::vector<double> M(n * n, 0.0);
+        for (int k = 0; k < p->nel[c]; ++k)
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    double s = 0.0;
+                    for (int q = 0; q < 4; ++q) s += p->tab.W[q] * p->tab.B[q][i] * p->tab.B[q][j];
+                    M[(2 * k + i) * n + (2 * k + j)] += p->h[c] * s;
+                }
+        std::vector<double> Minv = M, Mbc = M;
+        if (!invert(Minv, n)) return fail("singular 1D mass matrix");
+        for (int k = 0; k < n; ++k) {
+            Mbc[0 * n + k] = Mbc[k * n + 0] = 0.0;
+            Mbc[(n - 1) * n + k] = Mbc[k * n + (n - 1)] = 0.0;
+        }
+        Mbc[0] = 1.0;
+        Mbc[(n - 1) * n + (n - 1)] = 1.0;
+        if (!invert(Mbc, n)) return fail("singular 1D mass matrix");
+        // wall rows of the eliminated inverse act on zeroed right-hand sides; zero them
+        for (int k = 0; k < n; ++k) {
+            Mbc[0 * n + k] = Mbc[k * n + 0] = 0.0;
+            Mbc[(n - 1) * n + k] = Mbc[k * n + (n - 1)] = 0.0;
+        }
+        const size_t bytes = sizeof(double) * n * n;
+        if (hipMalloc(&p->d_minv[c], bytes) != hipSuccess || hipMalloc(&p->d_minv_bc[c], bytes) != hipSuccess ||
+            hipMalloc(&ex->d_m[c], bytes) != hipSuccess)
+            return fail("hipMalloc");
+        if (hipMemcpy(p->d_minv[c], Minv.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(p->d_minv_bc[c], Mbc.data(), bytes, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(ex->d_m[c], M.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return fail("hipMemcpy");
+    }
+    if (hipMalloc(&ex->d_tmp, sizeof(double) * 3 * p->n_nodes) != hipSuccess ||
+        hipMalloc(&ex->d_medinv, sizeof(double) * 8) != hipSuccess ||
+        hipMalloc(&ex->d_mediag, sizeof(double) * 8) != hipSuccess ||
+        hipMalloc(&ex->d_partial, sizeof(double) * 1024) != hipSuccess ||
+        hipMalloc(&p->d_status, sizeof(int32_t)) != hipSuccess)
+        return fail("hipMalloc");
+    if (hipMemcpy(ex->d_medinv, medinv, sizeof(double) * nt, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ex->d_mediag, p->me_diag, sizeof(double) * nt, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(p->d_status, 0, sizeof(int32_t)) != hipSuccess)
+        return fail("hipMemcpy");
+    *out = p;
+    return LH_OK;
+}
+
+void lh_problem_destroy(lh_problem* p) {
+    if (!p) return;
+    ProblemExtra* ex = extra_of(p);
+    for (int c = 0; c < 3; ++c) {
+        if (p->d_minv[c]) (void)hipFree(p->d_minv[c]);
+        if (p->d_minv_bc[c]) (void)hipFree(p->d_minv_bc[c]);
+        if (ex->d_m[c]) (void)hipFree(ex->d_m[c]);
+    }
+    if (ex->d_tmp) (void)hipFree(ex->d_tmp);
+    if (ex->d_medinv) (void)hipFree(ex->d_medinv);
+    if (ex->d_mediag) (void)hipFree(ex->d_mediag);
+    if (ex->d_partial) (void)hipFree(ex->d_partial);
+    if (p->d_status) (void)hipFree(p->d_status);
+    delete ex;
+    delete p;
+}
+
+int lh_problem_sizes(const lh_problem* p, int64_t* nv, int64_t* ne, int64_t* n_elem, int64_t* n_nodes) {
+    LH_REQUIRE(p, "lh_problem_sizes: null problem");
+    if (nv) *nv = p->NV;
+    if (ne) *ne = p->NE;
+    if (n_elem) *n_elem = p->n_elem;
+    if (n_nodes) *n_nodes = p->n_nodes;
+    return LH_OK;
+}
+
+int lh_initial_state(const lh_problem* p, double* x, double* v, double* e, hipStream_t stream) {
+    using namespace lh;
+    LH_REQUIRE(p && x && v && e, "lh_initial_state: null argument");
+    const int64_t n = std::max<int64_t>(p->n_nodes, p->NE);
+    const int threads = 256;
+    const int64_t blocks = (n + threads - 1) / threads;
+    hipLaunchKernelGGL(initial_state_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, p->desc, p->dim,
+                       p->nn[0], p->nn[1], p->nn[2], p->n_nodes, p->n_elem, p->h[0], p->h[1], p->h[2], x, v, e);
+    return launch_check("initial_state_kernel");
+}
+
+// Apply the Kronecker product of per-axis matrices mats[axis] to one nodal field.
+static int tensor_apply(const lh_problem* p, double* const* mats, const double* in, double* out, double* tmp,
+                        hipStream_t stream) {
+    const int64_t total = p->n_nodes;
+    const int threads = 256;
+    const unsigned blocks = (unsigned)((total + threads - 1) / threads);
+    int64_t stride = 1;
+    const double* src = in;
+    for (int ax = 0; ax < p->dim; ++ax) {
+        // final axis writes to out; intermediate ones alternate in tmp halves
+        double* dst = (ax == p->dim - 1) ? out : tmp + (ax % 2) * total;
+        hipLaunchKernelGGL(lh::apply_axis_kernel, dim3(blocks), dim3(threads), 0, stream, src, dst, mats[ax],
+                           p->nn[ax], stride, total);
+        src = dst;
+        stride *= p->nn[ax];
+    }
+    return lh::launch_check("apply_axis_kernel");
+}
+
+int lh_mass_solve_v(const lh_problem* p, const double* rhs, double* out, hipStream_t stream) {
+    using namespace lh;
+    LH_REQUIRE(p && rhs && out, "lh_mass_solve_v: null argument");
+    ProblemExtra* ex = extra_of(p);
+    std::lock_guard<std::mutex> lock(ex->mtx);
+    for (int c = 0; c < p->dim; ++c) {
+        double* mats[3];
+        for (int ax = 0; ax < p->dim; ++ax) mats[ax] = ax == c ? p->d_minv_bc[ax] : p->d_minv[ax];
+        // rhs and out may alias: the first axis pass reads rhs before anything writes out
+        int rc = tensor_apply(p, mats, rhs + c * p->n_nodes, out + c * p->n_nodes, ex->d_tmp, stream);
+        if (rc) return rc;
+    }
+    return LH_OK;
+}
+
+int lh_mass_solve_e(const lh_problem* p, const double* rhs, double* out, hipStream_t stream) {
+    using namespace lh;
+    LH_REQUIRE(p && rhs && out, "lh_mass_solve_e: null argument");
+    ProblemExtra* ex = extra_of(p);
+    const int64_t n = p->NE;
+    const int threads = 256;
+    hipLaunchKernelGGL(diag_scale_kernel, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, stream,
+                       rhs, out, ex->d_medinv, p->dim == 3 ? 8 : 4, n);
+    return launch_check("diag_scale_kernel");
+}
+
+int lh_total_energy(const lh_problem* p, const double* v, const double* e, double* out, hipStream_t stream) {
+    using namespace lh;
+    LH_REQUIRE(p && v && e && out, "lh_total_energy: null argument");
+    ProblemExtra* ex = extra_of(p);
+    std::lock_guard<std::mutex> lock(ex->mtx);
+    double* Mv = ex->d_tmp + 2 * p->n_nodes;
+    double kin = 0.0;
+    const int nb = 256;
+    std::vector<double> part(nb);
+    for (int c = 0; c < p->dim; ++c) {
+        int rc = tensor_apply(p, ex->d_m, v + c * p->n_nodes, Mv, ex->d_tmp, stream);
+        if (rc) return rc;
+        hipLaunchKernelGGL(dot_partial_kernel, dim3(nb), dim3(256), 0, stream, v + c * p->n_nodes, Mv, p->n_nodes,
+                           ex->d_partial);
+        LH_HIP_CHECK(hipMemcpyAsync(part.data(), ex->d_partial, sizeof(double) * nb, hipMemcpyDeviceToHost, stream));
+        LH_HIP_CHECK(hipStreamSynchronize(stream));
+        for (int i = 0; i < nb; ++i) kin += part[i];
+    }
+    hipLaunchKernelGGL(weighted_sum_partial_kernel, dim3(nb), dim3(256), 0, stream, e, p->NE, ex->d_mediag,
+                       p->dim == 3 ? 8 : 4, ex->d_partial);
+    LH_HIP_CHECK(hipMemcpyAsync(part.data(), ex->d_partial, sizeof(double) * nb, hipMemcpyDeviceToHost, stream));
+    LH_HIP_CHECK(hipStreamSynchronize(stream));
+    double internal = 0.0;
+    for (int i = 0; i < nb; ++i) internal += part[i];
+    *out = 0.5 * kin + internal;
+    return LH_OK;
+}
+
+int lh_status_read(const lh_problem* p, int32_t* flags, hipStream_t stream) {
+    using namespace lh;
+    LH_REQUIRE(p && flags, "lh_status_read: null argument");
+    int32_t h = 0;
+    LH_HIP_CHECK(hipMemcpyAsync(&h, p->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    LH_HIP_CHECK(hipStreamSynchronize(stream));
+    LH_HIP_CHECK(hipMemsetAsync(p->d_status, 0, sizeof(int32_t), stream));
+    *flags = h;
+    return LH_OK;
+}
+
+}  // extern "C"

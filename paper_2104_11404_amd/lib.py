@@ -1,0 +1,279 @@
+"""ctypes binding of liblagrom (argument marshalling only).
+
+Every entry point of ``include/lagrom.h`` is exposed under the same name.
+Arrays are torch tensors on the current HIP device; their data pointers and
+the current stream are passed straight to the library.  There is no CPU
+fallback: if the library is missing or no GPU is visible, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+from .build import LIB_PATH
+
+LH_OK = 0
+LH_ERRORS = {-1: "LH_EINVAL", -2: "LH_EWORKSPACE", -3: "LH_EDEVICE", -4: "LH_ETANGLED", -5: "LH_ENONFINITE",
+             -6: "LH_EDTCOLLAPSE", -7: "LH_ERANK"}
+LH_F1, LH_FTV, LH_TAU, LH_KEEP_STRESS, LH_USE_STRESS, LH_NO_BC = 1, 2, 4, 8, 16, 32
+LH_FP32_LIFT, LH_REPLAY_DT, LH_FIXED_DT = 1, 2, 4
+LH_NMAX = 64
+KIND = {"taylor_green": 1, "sedov": 2, "gresho": 3}
+
+
+class LagromError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{LH_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nel", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("kind", C.c_int32), ("use_av", C.c_int32), ("gamma", C.c_double), ("cfl", C.c_double),
+                ("amp", C.c_double), ("p_bg", C.c_double), ("energy", C.c_double)]
+
+
+class FomRunDesc(C.Structure):
+    _fields_ = [("t_final", C.c_double), ("fixed_dt", C.c_double), ("dt_replay", C.POINTER(C.c_double)),
+                ("n_replay", C.c_int32), ("max_steps", C.c_int32), ("snap_x", C.c_void_p), ("snap_v", C.c_void_p),
+                ("snap_e", C.c_void_p), ("max_snap", C.c_int32), ("t_out", C.POINTER(C.c_double)),
+                ("dt_out", C.POINTER(C.c_double))]
+
+
+class FomRunStats(C.Structure):
+    _fields_ = [("n_steps", C.c_int32), ("n_rejected", C.c_int32), ("n_snap", C.c_int32), ("status", C.c_int32)]
+
+
+class WindowDesc(C.Structure):
+    _fields_ = [("t_end", C.c_double), ("n", C.c_int32 * 3), ("phi", C.c_void_p * 3), ("os", C.c_void_p * 3),
+                ("z1", C.c_void_p), ("n_s1", C.c_int32), ("z2", C.c_void_p), ("n_s2", C.c_int32),
+                ("a1", C.c_void_p), ("a2", C.c_void_p)]
+
+
+class InstanceDesc(C.Structure):
+    _fields_ = [("n_windows", C.c_int32), ("windows", C.POINTER(WindowDesc)), ("t_final", C.c_double)]
+
+
+class RomState(C.Structure):
+    _fields_ = [("t", C.c_double), ("dt", C.c_double), ("w", C.c_int32), ("status", C.c_int32),
+                ("n_steps", C.c_int32), ("n_rejected", C.c_int32), ("n_force_evals", C.c_int32),
+                ("done", C.c_int32), ("yhat", (C.c_double * LH_NMAX) * 3)]
+
+
+ROM_STATE_BYTES = C.sizeof(RomState)
+
+_VP, _I32, _I64, _U32, _D, _SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double, C.c_size_t
+
+_SIGNATURES = {
+    "lh_problem_create": (_I32, [C.POINTER(ProblemDesc), C.POINTER(_VP)]),
+    "lh_problem_destroy": (None, [_VP]),
+    "lh_problem_sizes": (_I32, [_VP, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)]),
+    "lh_initial_state": (_I32, [_VP, _VP, _VP, _VP, _VP]),
+    "lh_fom_force_workspace_size": (_SZ, [_VP]),
+    "fom_force": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _I32, _U32, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "lh_mass_solve_v": (_I32, [_VP, _VP, _VP, _VP]),
+    "lh_mass_solve_e": (_I32, [_VP, _VP, _VP, _VP]),
+    "lh_total_energy": (_I32, [_VP, _VP, _VP, C.POINTER(_D), _VP]),
+    "lh_fom_run_workspace_size": (_SZ, [_VP]),
+    "lh_fom_run": (_I32, [_VP, _VP, _VP, _VP, C.POINTER(FomRunDesc), C.POINTER(FomRunStats), _VP, _SZ, _VP]),
+    "rom_build_basis_workspace_size": (_SZ, [_I64, _I32]),
+    "rom_build_basis": (_I32, [_VP, _I64, _I32, _I64, _D, _I32, _I32, _VP, _I64, _VP, C.POINTER(_I32), _VP, _SZ,
+                               _VP]),
+    "rom_sample_deim_workspace_size": (_SZ, [_I64, _I32, _I32]),
+    "rom_sample_deim": (_I32, [_VP, _I64, _I32, _I64, _I32, _VP, _VP, _VP, _SZ, _VP]),
+    "rom_create": (_I32, [_VP, _I32, C.POINTER(InstanceDesc), C.POINTER(_VP), _VP]),
+    "rom_destroy": (None, [_VP]),
+    "rom_init_state": (_I32, [_VP, _VP, _VP, _VP, _D, _VP, _VP]),
+    "rom_step": (_I32, [_VP, _VP, _I32, _U32, _VP, _I32, _VP]),
+    "rom_lift": (_I32, [_VP, _VP, _I32, _VP, _VP, _VP, _VP]),
+    "rom_sampled_elements": (_I32, [_VP, _I32, _I32, C.POINTER(_I32)]),
+    "lh_status_read": (_I32, [_VP, C.POINTER(_I32), _VP]),
+    "lh_last_error": (C.c_char_p, []),
+}
+
+_LIB = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblagrom.so (once).  Raises if it is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"liblagrom.so not built at {path}; run __graft_entry__.build()")
+    so = C.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(so, name, None)
+        if fn is None:
+            continue  # reported by missing_symbols()
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = so
+    return so
+
+
+def exported_symbols() -> list:
+    return list(_SIGNATURES)
+
+
+def missing_symbols(path: str = LIB_PATH) -> list:
+    so = C.CDLL(path)
+    return [n for n in _SIGNATURES if getattr(so, n, None) is None]
+
+
+def _check(rc: int):
+    if rc != LH_OK:
+        raise LagromError(rc, load().lh_last_error().decode())
+
+
+def stream_handle():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+def _f64(n, dev="cuda"):
+    return torch.empty(int(n), dtype=torch.float64, device=dev)
+
+
+class Problem:
+    """A problem handle (mesh, material, initial condition kind)."""
+
+    def __init__(self, dim, nel, lo, hi, kind, gamma, use_av, cfl, amp=1.0, p_bg=0.0, energy=0.25):
+        lib = load()
+        d = ProblemDesc()
+        d.dim = dim
+        for c in range(3):
+            d.nel[c] = int(nel[c]) if c < dim else 1
+            d.lo[c] = float(lo[c]) if c < dim else 0.0
+            d.hi[c] = float(hi[c]) if c < dim else 1.0
+        d.kind = KIND[kind] if isinstance(kind, str) else int(kind)
+        d.use_av = int(bool(use_av))
+        d.gamma, d.cfl, d.amp, d.p_bg, d.energy = float(gamma), float(cfl), float(amp), float(p_bg), float(energy)
+        self.desc = d
+        h = C.c_void_p()
+        _check(lib.lh_problem_create(C.byref(d), C.byref(h)))
+        self.h = h
+        nv, ne, nel_, nn = _I64(), _I64(), _I64(), _I64()
+        _check(lib.lh_problem_sizes(h, C.byref(nv), C.byref(ne), C.byref(nel_), C.byref(nn)))
+        self.NV, self.NE, self.n_elem, self.n_nodes = nv.value, ne.value, nel_.value, nn.value
+        self.dim = dim
+        self._force_ws = torch.empty(int(lib.lh_fom_force_workspace_size(h)), dtype=torch.uint8, device="cuda")
+
+    @classmethod
+    def from_workload(cls, wl, **over):
+        kw = dict(amp=wl.amp, p_bg=wl.p_bg, energy=wl.energy)
+        kw.update(over)
+        return cls(wl.dim, wl.nel, wl.lo, wl.hi, wl.problem, wl.gamma, wl.use_av, wl.cfl, **kw)
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _LIB is not None:
+            _LIB.lh_problem_destroy(self.h)
+            self.h = None
+
+    def initial_state(self):
+        x, v, e = _f64(self.NV), _f64(self.NV), _f64(self.NE)
+        _check(load().lh_initial_state(self.h, ptr(x), ptr(v), ptr(e), stream_handle()))
+        return x, v, e
+
+    def fom_force(self, x, v, e, vc=None, elems=None, ops=LH_F1 | LH_FTV | LH_TAU, F1=None, Ftv=None, tau=None):
+        F1 = _f64(self.NV) if F1 is None and ops & LH_F1 else F1
+        Ftv = torch.zeros(self.NE, dtype=torch.float64, device="cuda") if Ftv is None and ops & LH_FTV else Ftv
+        tau = _f64(1) if tau is None and ops & LH_TAU else tau
+        n_el = -1 if elems is None else int(elems.numel())
+        ws = self._force_ws
+        el = None if elems is None or n_el == 0 else ptr(elems)
+        _check(load().fom_force(self.h, ptr(x), ptr(v), ptr(e), ptr(vc), el, n_el, ops, ptr(F1), ptr(Ftv),
+                                ptr(tau), ptr(ws), ws.numel(), stream_handle()))
+        return F1, Ftv, tau
+
+    def mass_solve_v(self, rhs, out=None):
+        out = torch.empty_like(rhs) if out is None else out
+        _check(load().lh_mass_solve_v(self.h, ptr(rhs), ptr(out), stream_handle()))
+        return out
+
+    def mass_solve_e(self, rhs, out=None):
+        out = torch.empty_like(rhs) if out is None else out
+        _check(load().lh_mass_solve_e(self.h, ptr(rhs), ptr(out), stream_handle()))
+        return out
+
+    def total_energy(self, v, e):
+        out = C.c_double()
+        _check(load().lh_total_energy(self.h, ptr(v), ptr(e), C.byref(out), stream_handle()))
+        return out.value
+
+    def status(self):
+        f = _I32()
+        _check(load().lh_status_read(self.h, C.byref(f), stream_handle()))
+        return f.value
+
+    def fom_run(self, x, v, e, t_final, fixed_dt=0.0, dt_replay=None, max_steps=200000, record=True,
+                max_snap=None):
+        """Advance (x, v, e) in place; returns dict with times, steps and snapshot matrices."""
+        lib = load()
+        ws = torch.empty(int(lib.lh_fom_run_workspace_size(self.h)), dtype=torch.uint8, device="cuda")
+        d = FomRunDesc()
+        d.t_final = float(t_final)
+        d.fixed_dt = float(fixed_dt)
+        rep = None
+        if dt_replay is not None:
+            rep = (C.c_double * len(dt_replay))(*[float(h) for h in dt_replay])
+            d.dt_replay = C.cast(rep, C.POINTER(C.c_double))
+            d.n_replay = len(dt_replay)
+            max_steps = min(max_steps, len(dt_replay))
+        d.max_steps = int(max_steps)
+        snaps = None
+        if record:
+            ms = int(max_snap if max_snap is not None else 2 * max_steps)
+            snaps = (torch.empty((ms, self.NV), dtype=torch.float64, device="cuda"),
+                     torch.empty((ms, self.NV), dtype=torch.float64, device="cuda"),
+                     torch.empty((ms, self.NE), dtype=torch.float64, device="cuda"))
+            d.snap_x, d.snap_v, d.snap_e = (s.data_ptr() for s in snaps)
+            d.max_snap = ms
+        t_out = (C.c_double * (max_steps + 1))()
+        dt_out = (C.c_double * max(1, max_steps))()
+        d.t_out = C.cast(t_out, C.POINTER(C.c_double))
+        d.dt_out = C.cast(dt_out, C.POINTER(C.c_double))
+        st = FomRunStats()
+        _check(lib.lh_fom_run(self.h, ptr(x), ptr(v), ptr(e), C.byref(d), C.byref(st), ptr(ws), ws.numel(),
+                              stream_handle()))
+        n = st.n_steps
+        out = dict(t=list(t_out[: n + 1]), dt=list(dt_out[:n]), n_steps=n, n_rejected=st.n_rejected,
+                   n_snap=st.n_snap)
+        if record:
+            out["snaps"] = tuple(s[: st.n_snap] for s in snaps)  # rows are snapshots
+        return out
+
+
+def rom_build_basis(S, energy_frac=0.9999, n_fixed=0, n_max=0):
+    """POD of S (N x m, column-major = a (m, N) row-major tensor).  Returns (Phi (n, N) rows, sigma, n)."""
+    lib = load()
+    m, N = S.shape
+    n_cap = n_max if n_max > 0 else (n_fixed if n_fixed > 0 else m)
+    n_cap = min(n_cap, m)
+    Phi = torch.zeros((n_cap, N), dtype=torch.float64, device="cuda")
+    sigma = _f64(m)
+    ws = torch.empty(int(lib.rom_build_basis_workspace_size(N, m)), dtype=torch.uint8, device="cuda")
+    n_out = _I32()
+    _check(lib.rom_build_basis(ptr(S), N, m, N, float(energy_frac), int(n_fixed), int(n_cap), ptr(Phi), N,
+                               ptr(sigma), C.byref(n_out), ptr(ws), ws.numel(), stream_handle()))
+    return Phi[: n_out.value], sigma, n_out.value
+
+
+def rom_sample_deim(U, n_s):
+    """U: (n, N) row-major tensor = N x n column-major basis.  Returns (idx int32 (n_s), pinv (n_s, n) rows)."""
+    lib = load()
+    n, N = U.shape
+    n_s = min(int(n_s), N)
+    idx = torch.empty(n_s, dtype=torch.int32, device="cuda")
+    pinv = torch.empty((n_s, n), dtype=torch.float64, device="cuda")  # column-major n x n_s
+    ws = torch.empty(int(lib.rom_sample_deim_workspace_size(N, n, n_s)), dtype=torch.uint8, device="cuda")
+    _check(lib.rom_sample_deim(ptr(U), N, n, N, n_s, ptr(idx), ptr(pinv), ptr(ws), ws.numel(), stream_handle()))
+    return idx, pinv
