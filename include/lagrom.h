@@ -256,11 +256,13 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
 void rom_destroy(lh_rom* r);
 
 /* Initialise state[i] at t = 0: reduced coordinates Phi^T (y0 - os) of the
- * first window from the initial state y0 = (x0, v0, e0) (dev arrays, one
- * set per instance packed as x0[i*N_V], v0[i*N_V], e0[i*N_E]), dt from
- * dt0 (> 0) or 0.85 tau(y~_0) when dt0 <= 0. */
-int rom_init_state(const lh_rom* r, const double* x0, const double* v0, const double* e0, double dt0,
-                   lh_rom_state* state, hipStream_t stream);
+ * first window (zero when the offsets are the initial state, Sec. 3.1) from
+ * the initial state y0 = (x0, v0, e0) (dev arrays, one set per instance
+ * packed as x0[i*N_V], v0[i*N_V], e0[i*N_E]); inst (host) is the array
+ * passed to rom_create.  dt = dt0 when dt0 > 0, otherwise the first rom_step
+ * call starts from 0.85 tau(y~_0). */
+int rom_init_state(const lh_rom* r, const lh_instance_desc* inst, const double* x0, const double* v0,
+                   const double* e0, double dt0, lh_rom_state* state, hipStream_t stream);
 
 /* Advance every instance with the RK2-average hyper-reduced scheme
  * (eq. RK2-avg-rom-hr) and the step control of Sec. 2.2.3, for at most
@@ -273,10 +275,13 @@ int rom_init_state(const lh_rom* r, const double* x0, const double* v0, const do
 int rom_step(const lh_rom* r, lh_rom_state* state, int32_t max_steps, uint32_t flags, const double* dt_replay,
              int32_t n_replay, hipStream_t stream);
 
-/* Lift the final state of instance i to full size: y = os + Phi y^ (dev
- * outputs x (N_V), v (N_V), e (N_E)). */
-int rom_lift(const lh_rom* r, const lh_rom_state* state, int32_t inst, double* x, double* v, double* e,
-             hipStream_t stream);
+/* Lift instance inst to full size in its current window w (read from the
+ * device state, so the call synchronises): y = os_w + Phi_w y^
+ * (eq. solrepresentation-tw).  inst_desc (host) is the description that was
+ * passed to rom_create for this instance; its bases and offsets must still
+ * be alive.  Outputs x, v (N_V, dev) and e (N_E, dev). */
+int rom_lift(const lh_rom* r, const lh_rom_state* state, int32_t inst, const lh_instance_desc* inst_desc,
+             double* x, double* v, double* e, hipStream_t stream);
 
 /* Number of sampled elements of (instance, window) (host query). */
 int rom_sampled_elements(const lh_rom* r, int32_t inst, int32_t window, int32_t* n_elems);

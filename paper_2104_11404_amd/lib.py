@@ -85,9 +85,9 @@ _SIGNATURES = {
     "rom_sample_deim": (_I32, [_VP, _I64, _I32, _I64, _I32, _VP, _VP, _VP, _SZ, _VP]),
     "rom_create": (_I32, [_VP, _I32, C.POINTER(InstanceDesc), C.POINTER(_VP), _VP]),
     "rom_destroy": (None, [_VP]),
-    "rom_init_state": (_I32, [_VP, _VP, _VP, _VP, _D, _VP, _VP]),
+    "rom_init_state": (_I32, [_VP, C.POINTER(InstanceDesc), _VP, _VP, _VP, _D, _VP, _VP]),
     "rom_step": (_I32, [_VP, _VP, _I32, _U32, _VP, _I32, _VP]),
-    "rom_lift": (_I32, [_VP, _VP, _I32, _VP, _VP, _VP, _VP]),
+    "rom_lift": (_I32, [_VP, _VP, _I32, C.POINTER(InstanceDesc), _VP, _VP, _VP, _VP]),
     "rom_sampled_elements": (_I32, [_VP, _I32, _I32, C.POINTER(_I32)]),
     "lh_status_read": (_I32, [_VP, C.POINTER(_I32), _VP]),
     "lh_last_error": (C.c_char_p, []),
@@ -277,3 +277,84 @@ def rom_sample_deim(U, n_s):
     ws = torch.empty(int(lib.rom_sample_deim_workspace_size(N, n, n_s)), dtype=torch.uint8, device="cuda")
     _check(lib.rom_sample_deim(ptr(U), N, n, N, n_s, ptr(idx), ptr(pinv), ptr(ws), ws.numel(), stream_handle()))
     return idx, pinv
+
+
+class Rom:
+    """Online ROM of one or more instances sharing a problem (rom_create / rom_step)."""
+
+    def __init__(self, problem: Problem, instances: list):
+        """instances: list of dicts {t_final, windows: [window dicts]}.
+
+        A window dict holds t_end, n (n_x, n_v, n_e), phi (3 tensors (n_f, N) = column-major N x n_f),
+        os (3 tensors of length N), z1, z2 (int32 tensors), a1 ((n_s1, n_v) = column-major n_v x n_s1), a2.
+        The tensors must stay alive as long as this object (rom_lift reads the bases).
+        """
+        lib = load()
+        self.problem = problem
+        self.instances = instances
+        self._keep = []
+        descs = (InstanceDesc * len(instances))()
+        for i, inst in enumerate(instances):
+            ws = (WindowDesc * len(inst["windows"]))()
+            for w, wd in enumerate(inst["windows"]):
+                d = ws[w]
+                d.t_end = float(wd["t_end"])
+                for f in range(3):
+                    d.n[f] = int(wd["phi"][f].shape[0])
+                    d.phi[f] = wd["phi"][f].data_ptr()
+                    d.os[f] = wd["os"][f].data_ptr()
+                d.z1, d.n_s1 = wd["z1"].data_ptr(), int(wd["z1"].numel())
+                d.z2, d.n_s2 = wd["z2"].data_ptr(), int(wd["z2"].numel())
+                d.a1, d.a2 = wd["a1"].data_ptr(), wd["a2"].data_ptr()
+            self._keep.append(ws)
+            descs[i].n_windows = len(inst["windows"])
+            descs[i].windows = C.cast(ws, C.POINTER(WindowDesc))
+            descs[i].t_final = float(inst["t_final"])
+        self.descs = descs
+        h = C.c_void_p()
+        _check(lib.rom_create(problem.h, len(instances), descs, C.byref(h), stream_handle()))
+        self.h = h
+        self.n_inst = len(instances)
+        self.state = torch.zeros((self.n_inst, ROM_STATE_BYTES), dtype=torch.uint8, device="cuda")
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _LIB is not None:
+            _LIB.rom_destroy(self.h)
+            self.h = None
+
+    def init_state(self, x0, v0, e0, dt0=0.0):
+        _check(load().rom_init_state(self.h, self.descs, ptr(x0), ptr(v0), ptr(e0), float(dt0), ptr(self.state),
+                                     stream_handle()))
+
+    def step(self, max_steps=1 << 30, flags=0, dt_replay=None):
+        n_rep = 0 if dt_replay is None else int(dt_replay.numel())
+        _check(load().rom_step(self.h, ptr(self.state), int(max_steps), int(flags), ptr(dt_replay), n_rep,
+                               stream_handle()))
+
+    def states(self):
+        raw = self.state.cpu().numpy().tobytes()
+        out = []
+        for i in range(self.n_inst):
+            st = RomState.from_buffer_copy(raw[i * ROM_STATE_BYTES:(i + 1) * ROM_STATE_BYTES])
+            out.append(st)
+        return out
+
+    def coords(self, i):
+        """Reduced coordinates (x^, v^, e^) of instance i in its current window, as numpy arrays."""
+        import numpy as np
+
+        st = self.states()[i]
+        wd = self.instances[i]["windows"][st.w]
+        return tuple(np.array(st.yhat[f][: wd["phi"][f].shape[0]]) for f in range(3))
+
+    def lift(self, i):
+        P = self.problem
+        x, v, e = _f64(P.NV), _f64(P.NV), _f64(P.NE)
+        _check(load().rom_lift(self.h, ptr(self.state), int(i), C.byref(self.descs[i]), ptr(x), ptr(v), ptr(e),
+                               stream_handle()))
+        return x, v, e
+
+    def sampled_elements(self, i, w):
+        n = _I32()
+        _check(load().rom_sampled_elements(self.h, int(i), int(w), C.byref(n)))
+        return n.value
