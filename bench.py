@@ -1,0 +1,237 @@
+#!/usr/bin/env python
+"""Benchmark of the online hyper-reduced ROM on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): 2D Sedov
+blast on [0, 1.2]^2, 64 x 64 Q2-Q1 mesh, gamma = 1.4, rho = 1, v = 0, energy
+0.25 in the origin element, CFL-limited adaptive steps to t = 0.8, 10 time
+windows by number of samples, POD dimensions from the 99.99 % singular-value
+sum, oversampled DEIM with lambda = 6 (SNS bases), FP64.
+
+Untimed set-up: the GPU FOM generates the snapshots, then POD, SNS and DEIM
+build the per-window ROM, all with the library's kernels.  One timed "step"
+is one whole online ROM run (t = 0 to 0.8 through all windows: both RK2
+stages per step, step control with rejection, window changes) in a single
+persistent launch, with everything already resident in HBM.  The metric is
+ROM steps per second (accepted steps); sampled force evaluations per second
+(elements x stages) is reported beside it.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def rom_step_bytes(inst, st_counts, dim=2):
+    """Algorithmic bytes one ROM step attempt streams: sampled basis tiles, offsets and reduced operators.
+
+    Per stage: the x, v, e tiles and offsets of every sampled element (pass A), the v tile of every
+    owner of a sampled energy dof (pass B), A1 and A2, B_xv.  FP64.
+    """
+    nk = 9 if dim == 2 else 27
+    nt = 4 if dim == 2 else 8
+    nkd = nk * dim
+    out = []
+    for w, (wd, n_el, n_own) in enumerate(st_counts):
+        nx, nv, ne = (int(p.shape[0]) for p in wd["phi"])
+        ns1, ns2 = int(wd["z1"].numel()), int(wd["z2"].numel())
+        per_stage = 8 * (n_el * (nkd * (nx + nv) + nt * ne + 2 * nkd + nt) + n_own * nkd * nv
+                         + nv * ns1 + ne * ns2 + nx * nv)
+        out.append(2 * per_stage)
+    return out
+
+
+def cpu_baseline(wl, dims, evals_per_step, seconds: float = 12.0, n_pre: int = 24):
+    """The oracle's ROM step, timed on the host on a bounded sample of the same problem.
+
+    The oracle FOM runs the first n_pre steps; one window is built from them with the given
+    POD dimensions and the workload's oversampling, and the oracle's rom_step is timed over
+    repeated passes of that window (replayed step sizes).  Its cost is dominated by the
+    sampled force evaluations, so the measured sampled force evaluations per second are
+    converted to ROM steps per second at the full workload's evaluations per step.
+    """
+    import numpy as np
+
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import fom as F
+    from oracle import rom as R
+    from oracle.problems import initial_state
+    from tests.oracle_adapter import oracle_problem
+
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        op = F.build_operator(oracle_problem(wl))
+        tr = F.run_fom(op, wl.t_final, max_steps=n_pre)
+        y0 = initial_state(op.prob)
+        dims = tuple(min(int(d), n_pre) for d in dims)
+        rom = R.build_rom(op, [tr], [y0], [tr.t[-1]], n_fixed=dims, lam=wl.lam)
+        win = rom.windows[0]
+        n = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            y = R.initial_coords(rom, y0)
+            for h in tr.dt:
+                y, _, _ = R.rom_step(op, win, *y, h)
+                n += 1
+        el = time.perf_counter() - t0
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    evals = 2 * len(win.elems) * n
+    value = evals / el / evals_per_step
+    return dict(value=value, unit="ROM steps/s", cores=1, kind="oracle",
+                sample=(f"oracle SNS-DEIM ROM step (FP64 NumPy, 1 thread) on the same 64x64 Sedov problem: one "
+                        f"window from a {n_pre}-step oracle FOM prefix, dims {tuple(win.dims)}, lambda {wl.lam}, "
+                        f"{len(win.elems)} sampled elements; {n} steps in {el:.1f} s = {n / el:.1f} steps/s, "
+                        f"{evals / el:.0f} sampled force evals/s, scaled to {evals_per_step:.0f} evals per step "
+                        f"of the full workload"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp32", action="store_true", help="FP32 lift/projection (FP64 force and reduced state)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, help="also run a plain device copy of this many MiB")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (instances and elements would "
+              "shard across GPUs with no communication; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as Wl
+    from paper_2104_11404_amd import lib, pipeline
+
+    torch.cuda.set_device(0)
+    wl = Wl.sedov2d()
+    P = lib.Problem.from_workload(wl)
+    t_setup = time.perf_counter()
+    traj = pipeline.fom_trajectory(P, wl.t_final)
+    torch.cuda.synchronize()
+    t_fom = time.perf_counter() - t_setup
+    n_t = traj["n_steps"]
+    n_sample = 2 * math.ceil(n_t / wl.n_windows)
+    T = pipeline.windows_by_samples([traj["t"]], n_sample)
+    print(f"[bench] GPU FOM: {n_t} steps ({traj['n_rejected']} rejected) in {t_fom:.2f} s; "
+          f"{len(T)} windows of {n_sample} snapshots", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    inst = pipeline.build_offline(P, [traj], T, traj["y0"], energy_frac=wl.energy_frac, n_max=64, lam=wl.lam,
+                                  t_final=wl.t_final)
+    torch.cuda.synchronize()
+    t_offline = time.perf_counter() - t1
+    print(f"[bench] offline POD/SNS/DEIM in {t_offline:.2f} s; dims "
+          f"{[[int(p.shape[0]) for p in wd['phi']] for wd in inst['windows']]}", file=sys.stderr, flush=True)
+    rom = lib.Rom(P, [inst])
+    flags = lib.LH_FP32_LIFT if args.fp32 else 0
+
+    # accuracy run (also the first warm-up)
+    rom.init_state(*traj["y0"])
+    rom.step(flags=flags)
+    st = rom.states()[0]
+    lifted = rom.lift(0)
+    errs = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(lifted, traj["y_final"])]
+
+    stream = torch.cuda.current_stream()
+    for _ in range(max(0, args.warmup - 1)):
+        rom.init_state(*traj["y0"])
+        rom.step(flags=flags)
+    torch.cuda.synchronize()
+    k_starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    k_ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        rom.init_state(*traj["y0"])
+        k_starts[i].record(stream)
+        rom.step(flags=flags)
+        k_ends[i].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in zip(k_starts, k_ends)]
+    st = rom.states()[0]
+    rom_steps = st.n_steps * args.steps
+    evals = st.n_force_evals * args.steps
+    value = rom_steps / elapsed
+
+    # roofline of the dominant kernel (rom_step_kernel, one launch per run)
+    n_el = [rom.sampled_elements(0, w) for w in range(len(inst["windows"]))]
+    n_own = [len(set((wd["z2"].cpu().numpy() // 4).tolist())) for wd in inst["windows"]]
+    per_attempt = rom_step_bytes(inst, list(zip(inst["windows"], n_el, n_own)))
+    # attempts per window are not tracked on device; apportion accepted+rejected attempts by window length
+    attempts = st.n_steps + st.n_rejected
+    bytes_per_launch = attempts * sum(per_attempt) / len(per_attempt)
+    avg_kernel_s = sum(kern_ms) / len(kern_ms) / 1e3
+    achieved = bytes_per_launch / avg_kernel_s / 1e9
+
+    calib = None
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        calib = dict(copy_bytes_read=4 * n, copy_bytes_written=4 * n)
+
+    dims = [[int(p.shape[0]) for p in wd["phi"]] for wd in inst["windows"]]
+    out = {
+        "metric": "ROM steps/s and sampled force evals/s vs plain DEIM ROM at equal rel. error",
+        "value": value,
+        "unit": "ROM steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-lift/f64" if args.fp32 else "f64",
+        "data": "synthetic (analytic Sedov initial state; snapshots from the GPU FOM)",
+        "config": {
+            "workload": f"sedov2d_64x64_q2q1_t0.8_10windows_sns_deim_lambda{wl.lam[0]:g}",
+            "mesh": [64, 64], "N_V": P.NV, "N_E": P.NE, "t_final": wl.t_final,
+            "fom_steps": n_t, "windows": len(T), "rom_steps_per_run": st.n_steps,
+            "rom_rejections_per_run": st.n_rejected, "dims_per_window": dims,
+            "sampled_elements_per_window": n_el, "energy_frac": wl.energy_frac, "lambda": list(wl.lam),
+        },
+        "sampled_force_evals_per_s": evals / elapsed,
+        "rel_error_vs_fom": {"x": errs[0], "v": errs[1], "e": errs[2]},
+        "roofline": {
+            "kernel": "rom_step_kernel",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_launch": bytes_per_launch,
+            "avg_kernel_ms": avg_kernel_s * 1e3,
+        },
+        "setup_s": {"fom": t_fom, "offline_pod_sns_deim": t_offline},
+    }
+    if calib:
+        out["copy_calibration"] = calib
+    if not args.no_cpu_baseline:
+        med = [int(sorted(d[f] for d in dims)[len(dims) // 2]) for f in range(3)]
+        out["cpu_baseline"] = cpu_baseline(wl, med, st.n_force_evals / st.n_steps, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

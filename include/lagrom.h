@@ -53,7 +53,7 @@ enum lh_status {
 };
 
 /* Device status word bits (lh_status_read returns them OR-ed). */
-enum { LH_FLAG_TANGLED = 1, LH_FLAG_NONFINITE = 2, LH_FLAG_DTCOLLAPSE = 4 };
+enum { LH_FLAG_TANGLED = 1, LH_FLAG_NONFINITE = 2, LH_FLAG_DTCOLLAPSE = 4, LH_FLAG_TIMEOUT = 8 };
 
 enum lh_problem_kind { LH_TAYLOR_GREEN = 1, LH_SEDOV = 2, LH_GRESHO = 3 };
 
@@ -285,6 +285,47 @@ int rom_lift(const lh_rom* r, const lh_rom_state* state, int32_t inst, const lh_
 
 /* Number of sampled elements of (instance, window) (host query). */
 int rom_sampled_elements(const lh_rom* r, int32_t inst, int32_t window, int32_t* n_elems);
+
+/* Workgroups that advance each instance in rom_step (host query).  rom_create
+ * chooses it so that every workgroup's share of a window (basis tiles,
+ * offsets, DEIM columns) fits in LDS, within one co-resident workgroup per
+ * compute unit; batches with as many instances as compute units use 1.
+ * With more than one, the launch is cooperative and the workgroups of an
+ * instance meet at a barrier after every pass; a barrier that does not
+ * complete within a few seconds sets LH_FLAG_TIMEOUT and ends the launch. */
+int rom_workgroups_per_instance(const lh_rom* r, int32_t* G);
+
+/* ------------------------------------------------------ offline helpers */
+
+/* Snapshot deviations (Sec. 3.4): out[:, j] = snaps[:, j] - os for j < m.
+ * snaps (dev, N x m, ld), os (dev, N), out (dev, N x m, ldo); out may be a
+ * column block of a larger matrix holding several parameters' snapshots. */
+int lh_snapshot_deviation(const double* snaps, int64_t N, int32_t m, int64_t ld, const double* os, double* out,
+                          int64_t ldo, hipStream_t stream);
+
+/* SNS nonlinear bases (Sec. 3.5): out = M_V in with the wall rows and
+ * columns eliminated and identity on the wall rows (the form whose inverse
+ * lh_mass_solve_v applies), and out = M_E in.  One column (N_V resp. N_E,
+ * dev); in and out must differ for the kinematic apply. */
+int lh_mass_apply_v(const lh_problem* p, const double* in, double* out, hipStream_t stream);
+int lh_mass_apply_e(const lh_problem* p, const double* in, double* out, hipStream_t stream);
+
+/* Window end points by number of samples (eq. sample_window), host only.
+ * t_lists[k] (host, n_steps[k] + 1 accepted times from 0) per parameter k;
+ * n_sample snapshots per window counted with the intermediate RK stage (two
+ * per step); T_w = min over parameters of the time n_sample/2 steps after
+ * the first step reaching T_{w-1}; the last window ends at the latest final
+ * time.  T_out (host, max_windows), *n_windows (host). */
+int lh_windows_by_samples(int32_t n_params, const double* const* t_lists, const int32_t* n_steps, int32_t n_sample,
+                          double* T_out, int32_t max_windows, int32_t* n_windows);
+
+/* Column range of each window's snapshot matrix (eq. window_sample) in the
+ * snapshot array written by lh_fom_run (column 2n = stage state of step n+1,
+ * column 2n+1 = step state n+1): the step state at the window's start (none
+ * for the first window, whose start is the offset), then the stage and step
+ * states of every step up to the first one reaching T_w.  Host only. */
+int lh_window_columns(const double* t, int32_t n_steps, const double* T, int32_t n_windows, int32_t* first_col,
+                      int32_t* n_cols);
 
 /* ---------------------------------------------------------------- misc */
 

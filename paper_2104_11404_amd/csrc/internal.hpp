@@ -11,6 +11,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "../../include/lagrom.h"
@@ -66,6 +67,19 @@ struct lh_problem {
     int32_t* d_status;
     int device;
     struct lh_problem_extra* ex;  // mass-solve scratch and reduction buffers
+};
+
+// Device state a problem keeps for its mass solves and reductions.  The
+// scratch is shared by every call on the problem, so the calls that use it
+// (mass solves and applications, total energy) hold the mutex; they must
+// still not overlap on two streams of the device.
+struct lh_problem_extra {
+    double* d_m[3];     // forward 1D mass matrices
+    double* d_tmp;      // 3 * N_nodes scratch for tensor applications
+    double* d_medinv;   // 8 entries: inverse thermodynamic mass per local dof
+    double* d_mediag;   // 8 entries
+    double* d_partial;  // reduction partials
+    std::mutex mtx;
 };
 
 namespace lh {
@@ -205,7 +219,7 @@ __device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, int q, co
     }
     int flags = 0;
     double det, Jinv[DIM][DIM];
-    if (DIM == 2) {
+    if constexpr (DIM == 2) {
         det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
         const double id = 1.0 / det;
         Jinv[0][0] = J[1][1] * id;
@@ -252,7 +266,7 @@ __device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, int q, co
                 for (int c = 0; c < DIM; ++c) s += J[c][i] * J[c][k];
                 M[i][k] = s;
             }
-        if (DIM == 2) {
+        if constexpr (DIM == 2) {
             const double m = 0.5 * (M[0][0] + M[1][1]);
             const double d = 0.5 * (M[0][0] - M[1][1]);
             const double lmax = m + sqrt(d * d + M[0][1] * M[0][1]);
@@ -291,7 +305,7 @@ __device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, int q, co
 #pragma unroll
         for (int c = 0; c < DIM; ++c) tr += eps[c][c];
         double lmin;
-        if (DIM == 2) {
+        if constexpr (DIM == 2) {
             const double m = 0.5 * (eps[0][0] + eps[1][1]);
             const double d = 0.5 * (eps[0][0] - eps[1][1]);
             lmin = m - sqrt(d * d + eps[0][1] * eps[0][1]);

@@ -1,0 +1,159 @@
+// Offline helpers of the ROM construction: snapshot deviations, the SNS
+// nonlinear bases Phi_F1 = M_V Phi_v and Phi_Ftv = M_E Phi_e (Sec. 3.5), and
+// the placement of time windows (Sec. 4.4) with the column ranges of the
+// per-window snapshot matrices (eq. window_sample).
+#include <algorithm>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace lh {
+namespace off {
+
+// out[:, j] = snaps[:, j] - os
+__global__ void deviation_kernel(const double* snaps, int64_t N, int m, int64_t ld, const double* os, double* out,
+                                 int64_t ldo) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i < N && j < m) out[(int64_t)j * ldo + i] = snaps[(int64_t)j * ld + i] - os[i];
+}
+
+// copy with the wall-constrained entries of component comp zeroed (zero_bc)
+// or restored from src (restore)
+__global__ void bc_rows_kernel(const double* src, double* dst, int64_t n_nodes, int nnx, int nny, int nnz, int dim,
+                               int restore) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_nodes * dim) return;
+    const int c = (int)(t / n_nodes);
+    const int64_t node = t % n_nodes;
+    const int g = c == 0 ? (int)(node % nnx) : c == 1 ? (int)((node / nnx) % nny) : (int)(node / ((int64_t)nnx * nny));
+    const int nlast = (c == 0 ? nnx : c == 1 ? nny : nnz) - 1;
+    const bool wall = g == 0 || g == nlast;
+    if (restore) {
+        if (wall) dst[t] = src[t];
+    } else {
+        dst[t] = wall ? 0.0 : src[t];
+    }
+}
+
+__global__ void apply_axis_fwd_kernel(const double* __restrict__ in, double* __restrict__ out,
+                                      const double* __restrict__ M, int n, int64_t stride, int64_t total) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int i = (int)((idx / stride) % n);
+    const int64_t base = idx - (int64_t)i * stride;
+    const double* row = M + (int64_t)i * n;
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += row[k] * in[base + (int64_t)k * stride];
+    out[idx] = s;
+}
+
+__global__ void diag_mul_kernel(const double* in, double* out, const double* __restrict__ d, int nt, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i] * d[i % nt];
+}
+
+}  // namespace off
+}  // namespace lh
+
+extern "C" {
+
+int lh_snapshot_deviation(const double* snaps, int64_t N, int32_t m, int64_t ld, const double* os, double* out,
+                          int64_t ldo, hipStream_t s) {
+    using namespace lh;
+    LH_REQUIRE(snaps && os && out && N > 0 && m >= 0 && ld >= N && ldo >= N, "lh_snapshot_deviation: bad arguments");
+    if (m == 0) return LH_OK;
+    hipLaunchKernelGGL(off::deviation_kernel, dim3((unsigned)((N + 255) / 256), m), dim3(256), 0, s, snaps, N, m, ld,
+                       os, out, ldo);
+    return launch_check("deviation_kernel");
+}
+
+int lh_windows_by_samples(int32_t n_params, const double* const* t_lists, const int32_t* n_steps, int32_t n_sample,
+                          double* T_out, int32_t max_windows, int32_t* n_windows) {
+    using namespace lh;
+    LH_REQUIRE(n_params >= 1 && t_lists && n_steps && T_out && n_windows && n_sample >= 2 && max_windows >= 1,
+               "lh_windows_by_samples: bad arguments");
+    const int steps = n_sample / 2;  // two snapshots (stage and step state) per step
+    double t_final = 0.0;
+    for (int k = 0; k < n_params; ++k) {
+        LH_REQUIRE(n_steps[k] >= 1 && t_lists[k], "lh_windows_by_samples: empty trajectory");
+        t_final = std::max(t_final, t_lists[k][n_steps[k]]);
+    }
+    int nw = 0;
+    double Tprev = 0.0;
+    while (Tprev < t_final) {
+        double Tw = INFINITY;
+        for (int k = 0; k < n_params; ++k) {
+            const double* t = t_lists[k];
+            int s = 0;
+            while (s < n_steps[k] && t[s] < Tprev) ++s;  // first step reaching T_{w-1}
+            const int idx = s + steps;
+            Tw = std::min(Tw, idx <= n_steps[k] ? t[idx] : t[n_steps[k]]);
+        }
+        if (!(Tw > Tprev)) Tw = t_final;
+        LH_REQUIRE(nw < max_windows, "lh_windows_by_samples: more windows than max_windows");
+        T_out[nw++] = Tw;
+        Tprev = Tw;
+    }
+    *n_windows = nw;
+    return LH_OK;
+}
+
+int lh_window_columns(const double* t, int32_t n_steps, const double* T, int32_t n_windows, int32_t* first_col,
+                      int32_t* n_cols) {
+    using namespace lh;
+    LH_REQUIRE(t && T && first_col && n_cols && n_steps >= 1 && n_windows >= 1, "lh_window_columns: bad arguments");
+    int s_prev = 0;
+    for (int w = 0; w < n_windows; ++w) {
+        int s = 0;
+        while (s < n_steps && t[s] < T[w]) ++s;
+        // previous step state (column 2 s_prev - 1) unless s_prev = 0, then stage/step pairs
+        first_col[w] = s_prev > 0 ? 2 * s_prev - 1 : 0;
+        n_cols[w] = 2 * (s - s_prev) + (s_prev > 0 ? 1 : 0);
+        s_prev = s;
+    }
+    return LH_OK;
+}
+
+int lh_mass_apply_v(const lh_problem* p, const double* in, double* out, hipStream_t s) {
+    using namespace lh;
+    LH_REQUIRE(p && in && out && in != out, "lh_mass_apply_v: bad arguments");
+    lh_problem_extra* ex = p->ex;
+    std::lock_guard<std::mutex> lock(ex->mtx);
+    const int64_t n = p->n_nodes;
+    double* zin = ex->d_tmp + 2 * n;  // third scratch slot
+    const unsigned blocks = (unsigned)((n * p->dim + 255) / 256);
+    // M_V with wall rows and columns eliminated and identity on the wall rows
+    hipLaunchKernelGGL(off::bc_rows_kernel, dim3(blocks), dim3(256), 0, s, in, out, n, p->nn[0], p->nn[1], p->nn[2],
+                       p->dim, 0);
+    for (int c = 0; c < p->dim; ++c) {
+        const unsigned nb = (unsigned)((n + 255) / 256);
+        // copy component c of the zeroed input into the spare slot, then apply axis by axis
+        hipLaunchKernelGGL(off::apply_axis_fwd_kernel, dim3(nb), dim3(256), 0, s, out + c * n, zin, ex->d_m[0],
+                           p->nn[0], (int64_t)1, n);
+        const double* src = zin;
+        int64_t stride = p->nn[0];
+        for (int ax = 1; ax < p->dim; ++ax) {
+            double* dst = (ax == p->dim - 1) ? out + c * n : ex->d_tmp + ((ax - 1) % 2) * n;
+            hipLaunchKernelGGL(off::apply_axis_fwd_kernel, dim3(nb), dim3(256), 0, s, src, dst, ex->d_m[ax], p->nn[ax],
+                               stride, n);
+            src = dst;
+            stride *= p->nn[ax];
+        }
+    }
+    hipLaunchKernelGGL(off::bc_rows_kernel, dim3(blocks), dim3(256), 0, s, in, out, n, p->nn[0], p->nn[1], p->nn[2],
+                       p->dim, 1);
+    return launch_check("lh_mass_apply_v");
+}
+
+int lh_mass_apply_e(const lh_problem* p, const double* in, double* out, hipStream_t s) {
+    using namespace lh;
+    LH_REQUIRE(p && in && out, "lh_mass_apply_e: bad arguments");
+    const lh_problem_extra* ex = p->ex;
+    const int64_t n = p->NE;
+    hipLaunchKernelGGL(off::diag_mul_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out,
+                       ex->d_mediag, p->dim == 3 ? 8 : 4, n);
+    return launch_check("lh_mass_apply_e");
+}
+
+}  // extern "C"

@@ -125,7 +125,7 @@ __global__ void extract_r_kernel(const double* A, int64_t N, int m, const double
 
 // One round of the round-robin one-sided Jacobi sweep on the columns of W.
 __global__ void __launch_bounds__(256) jacobi_round_kernel(double* W, int m, int M, int round, double tol,
-                                                          int* rotated) {
+                                                          double negl, int* rotated) {
     __shared__ double sh[256];
     const int i = blockIdx.x;
     int p, q;
@@ -149,7 +149,8 @@ __global__ void __launch_bounds__(256) jacobi_round_kernel(double* W, int m, int
     a = block_sum(a, sh);
     b = block_sum(b, sh);
     g = block_sum(g, sh);
-    if (g == 0.0 || a == 0.0 || b == 0.0 || fabs(g) <= tol * sqrt(a) * sqrt(b)) return;
+    // columns below the rounding level of R carry no information: leave them alone
+    if (g == 0.0 || a <= negl || b <= negl || fabs(g) <= tol * sqrt(a) * sqrt(b)) return;
     const double zeta = (b - a) / (2.0 * g);
     const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
     const double c = 1.0 / sqrt(1.0 + t * t);
@@ -361,12 +362,23 @@ int rom_build_basis(const double* S, int64_t N, int32_t m, int64_t ldS, double e
     hipLaunchKernelGGL(extract_r_kernel, dim3((m + 255) / 256, m), dim3(256), 0, s, w.A, N, m, w.beta, w.W);
     // one-sided Jacobi sweeps until a whole sweep rotates nothing
     const int M = m + (m & 1);
-    const double tol = 2.220446049250313e-16 * std::max(m, 16);
+    const double tol = 1e-13;
+    double negl;
+    {
+        hipLaunchKernelGGL(col_norm_kernel, dim3(m), dim3(256), 0, s, w.W, m, w.sig_raw);
+        std::vector<double> cn(m);
+        LH_HIP_CHECK(hipMemcpyAsync(cn.data(), w.sig_raw, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+        LH_HIP_CHECK(hipStreamSynchronize(s));
+        double fro2 = 0.0;
+        for (double c : cn) fro2 += c * c;
+        negl = 1e-30 * fro2;  // column norm below 1e-15 ||R||_F
+    }
     bool converged = m == 1;
-    for (int sweep = 0; sweep < 60 && !converged; ++sweep) {
+    for (int sweep = 0; sweep < 80 && !converged; ++sweep) {
         LH_HIP_CHECK(hipMemsetAsync(w.rotated, 0, sizeof(int), s));
         for (int r = 0; r < M - 1; ++r)
-            hipLaunchKernelGGL(jacobi_round_kernel, dim3(M / 2), dim3(256), 0, s, w.W, m, M, r, tol, w.rotated);
+            hipLaunchKernelGGL(jacobi_round_kernel, dim3(M / 2), dim3(256), 0, s, w.W, m, M, r, tol, negl,
+                               w.rotated);
         int hrot = 0;
         LH_HIP_CHECK(hipMemcpyAsync(&hrot, w.rotated, sizeof(int), hipMemcpyDeviceToHost, s));
         LH_HIP_CHECK(hipStreamSynchronize(s));

@@ -219,18 +219,6 @@ __global__ void weighted_sum_partial_kernel(const double* e, int64_t n, const do
 
 }  // namespace lh
 
-// Device state a problem keeps for its mass solves and reductions.  The
-// scratch is shared by every call on the problem, so the calls that use it
-// (mass solves, total energy) hold the mutex; they must still not overlap on
-// two streams of the device.
-struct lh_problem_extra {
-    double* d_m[3];     // forward 1D mass matrices
-    double* d_tmp;      // 3 * N_nodes scratch for tensor applications
-    double* d_medinv;   // 8 entries: inverse thermodynamic mass per local dof
-    double* d_mediag;   // 8 entries
-    double* d_partial;  // reduction partials
-    std::mutex mtx;
-};
 typedef lh_problem_extra ProblemExtra;
 
 static ProblemExtra* extra_of(const lh_problem* p) { return p->ex; }

@@ -7,23 +7,30 @@
 // owner of a sampled thermodynamic dof) the rows of Phi_x, Phi_v, Phi_e and
 // of the offsets that the element touches, stored [element][basis
 // column][local row] so that lanes walking the local rows read contiguous
-// memory.  The lift is then computed only at those dofs, as the method
-// prescribes.
+// memory.  The lift is computed only at those dofs, as the method prescribes.
 //
-// rom_step runs one persistent workgroup per instance for the whole time
-// loop (both RK stages, step-size control with rejection, window changes),
-// so hundreds of instances with different dimensions and window counts share
-// one launch.  Per stage:
-//   pass A  lift (x, v, e) at the sampled elements, pulled-back stress of
-//           every quadrature point (kept in scratch), element-local F.1,
-//           then the sampled rows of F.1 as fixed-order sums over the
-//           elements around each node, and F^1 = A1 (F.1)_Z;
-//   pass B  lift the contraction velocity at the owners of sampled energy
-//           dofs, F^T.v_c there from the kept stress, F^tv = A2 (F^T.v_c)_Z;
-// and the reduced updates v^ -= dt F^1, e^ += dt F^tv, x^ += dt (b_x + B_xv v^c).
-// All reductions run in a fixed order, so results are bitwise reproducible.
+// rom_step is one persistent launch for the whole time loop (both RK stages,
+// step-size control with rejection, window changes).  Each instance is
+// advanced by G workgroups; workgroup g owns a contiguous range of the
+// instance's sampled elements in every window and, when they fit, keeps
+// their basis tiles, offsets and the columns of A1 = (Z1^T M_V Phi_v)^+ and
+// A2 = (Z2^T M_E Phi_e)^+ that its elements feed resident in LDS for the
+// whole window.  Per stage:
+//   pass A  lift (x, v, e) at its elements, pulled-back stress of every
+//           quadrature point (kept), the element-local entries of F.1 at the
+//           sampled rows, and the workgroup's share of F^1 = A1 (F.1)_Z
+//           (F.1 at a sampled node is the sum of its elements' entries, and
+//           the projection is linear, so shares add up);
+//   pass B  lift the contraction velocity at its owners of sampled energy
+//           dofs, F^T.v_c there from the kept stress, its share of F^tv;
+// after each pass the shares (and the step estimate) of the G workgroups are
+// combined through a per-instance barrier in a fixed order, so every
+// workgroup applies identical reduced updates v^ -= dt F^1, e^ += dt F^tv,
+// x^ += dt (b_x + B_xv v^c) and takes identical step-control decisions.
+// Results are bitwise reproducible.  Batches of many instances use G = 1.
 #include <algorithm>
 #include <cstddef>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <set>
@@ -37,21 +44,29 @@ namespace rom {
 constexpr double BETA1 = 0.85;
 constexpr double BETA2 = 1.02;
 constexpr double GAMMA_DT = 0.8;
+constexpr int BLK = 256;
+constexpr int PSTRIDE = LH_NMAX + 2;  // one share: LH_NMAX coefficients, step estimate, status bits
+
+// What one workgroup owns in one window.
+struct WgView {
+    int s0, ns;       // first closure slot, number of slots
+    int nkin;         // sampled kinematic entries (slot, dof, A1 column) of its elements
+    int nown;         // its owners of sampled energy dofs
+    int nth;          // sampled energy entries (owner, dof, A2 column)
+    const int* kin;   // 3 ints per entry; slot relative to s0
+    const int* own;   // [nown] slots relative to s0
+    const int* th;    // 3 ints per entry; owner index into own[]
+    int res_bytes64;  // resident bytes with FP64 tiles
+    int res_bytes32;  // resident bytes with FP32 tiles
+};
 
 struct WinDev {
     double t_end;
-    int n[3];      // n_x, n_v, n_e
-    int n_el;      // sampled elements (closure)
-    int n_own;     // closure elements owning a sampled energy dof
-    int ns1, ns2;
-    const int* elem;        // [n_el]
+    int n[3];  // n_x, n_v, n_e
+    int n_el;
     const double* tile[3];  // [n_el][n_f][rows_f]
     const float* tile32[3];
     const double* os_loc[3];  // [n_el][rows_f]
-    const int* c1_ptr;        // [ns1+1] contributors of each sampled kinematic row
-    const int* c1_idx;        // slot * NKD + local kinematic dof
-    const int* own;           // [n_own] closure slot of each owner
-    const int* z2_loc;        // [ns2] owner index * NT + local dof
     const double* A1;         // n_v x ns1
     const double* A2;         // n_e x ns2
     const float* A1f;
@@ -60,64 +75,80 @@ struct WinDev {
     const double* bx;   // n_x
     const double* T[3];  // from the previous window: n_f^w x n_f^{w-1}
     const double* c[3];
+    const WgView* views;  // [G]
 };
 
 struct InstDev {
     int n_windows;
     const WinDev* win;
     double t_final;
-    double* sig;     // [max n_el][NQ][D*D]
-    double* f1_loc;  // [max n_el][NKD]
-    double* ftv_loc; // [max n_own][NT]
-    double* fz1;     // [max ns1]
-    double* fz2;     // [max ns2]
+    double* part;  // [2][G][PSTRIDE] shares exchanged after every pass
+    int* flag;     // [G] sequence number of the last share each workgroup published
+    double* sig;   // [max n_el][NQ][D*D] kept stress when it is not resident
 };
 
 struct RomArgs {
     RefTab T;
     ForceConst fc;
-    int nex, ney;
-    int nnx, nny;
     const InstDev* inst;
     lh_rom_state* state;
     int n_inst;
+    int G;
     int max_steps;
     uint32_t flags;
     const double* dt_replay;
     int n_replay;
+    int nkin_max, nth_max;  // sizes of the entry-value arrays in LDS
 };
 
 template <int DIM>
 struct Cfg {
-    static constexpr int BLK = DIM == 2 ? 1024 : 512;
-    static constexpr int EC = BLK / ElemDims<DIM>::NQ;  // elements per chunk
-    static constexpr int NKD = ElemDims<DIM>::NK * DIM;
-    static constexpr int NT = ElemDims<DIM>::NT;
     static constexpr int NQ = ElemDims<DIM>::NQ;
+    static constexpr int NK = ElemDims<DIM>::NK;
+    static constexpr int NT = ElemDims<DIM>::NT;
+    static constexpr int NKD = NK * DIM;
+    static constexpr int DD = DIM * DIM;
+    static constexpr int EC = BLK / NQ;  // elements per chunk (one thread per quadrature point)
+};
+
+// Pointers to one workgroup's data in one window, in LDS or in global memory.
+template <class TT>
+struct Local {
+    const TT* tile[3];    // [ns][n_f][rows_f]
+    const double* os[3];  // [ns][rows_f]
+    const TT* a1;         // resident: [nkin][n_v]; global: A1 (index by column)
+    const TT* a2;
+    bool res;
+    double* sig;         // [ns][NQ][DD]
+    const double* Bxv;   // n_x x n_v
+    const double* bx;    // n_x
+};
+
+struct Shared {
+    double y[3][LH_NMAX];
+    double yh[3][LH_NMAX];
+    double yn[3][LH_NMAX];
+    double vc[LH_NMAX];
+    double f1h[LH_NMAX];
+    double ftvh[LH_NMAX];
+    double tmp[LH_NMAX];
+    double red[BLK];
+    double comb[2];  // combined step estimate and status bits
 };
 
 template <int DIM>
-struct Smem {
+struct NodeBuf {
     double x[Cfg<DIM>::EC][Cfg<DIM>::NKD];
     double v[Cfg<DIM>::EC][Cfg<DIM>::NKD];
     double e[Cfg<DIM>::EC][Cfg<DIM>::NT];
     double s[Cfg<DIM>::EC][Cfg<DIM>::NQ];
-    double red[Cfg<DIM>::BLK];
-    double y[3][LH_NMAX];   // current reduced coordinates
-    double yh[3][LH_NMAX];  // stage coordinates
-    double yn[3][LH_NMAX];  // new coordinates
-    double vc[LH_NMAX];     // contraction velocity coordinates
-    double f1h[LH_NMAX];
-    double ftvh[LH_NMAX];
-    double tmp[LH_NMAX];
 };
 
-template <int DIM>
 __device__ double block_min(double v, double* red) {
     const int tid = threadIdx.x;
     red[tid] = v;
     __syncthreads();
-    for (int w = Cfg<DIM>::BLK / 2; w > 0; w >>= 1) {
+    for (int w = BLK / 2; w > 0; w >>= 1) {
         if (tid < w) red[tid] = fmin(red[tid], red[tid + w]);
         __syncthreads();
     }
@@ -126,81 +157,95 @@ __device__ double block_min(double v, double* red) {
     return r;
 }
 
-// out[i] = sum_r A[i + r*n] z[r] for i < n, computed by 16-lane groups in a fixed order.
-template <int DIM, bool F32>
-__device__ void project(const double* A, const float* Af, int n, int ns, const double* z, double* out) {
-    const int g = threadIdx.x / 16, l = threadIdx.x % 16;
-    const int groups = Cfg<DIM>::BLK / 16;
-    for (int i0 = 0; i0 < n; i0 += groups) {
-        const int i = i0 + g;
-        double acc = 0.0;
-        float accf = 0.0f;
-        if (i < n) {
-            for (int r = l; r < ns; r += 16) {
-                if (F32)
-                    accf += Af[(int64_t)r * n + i] * (float)z[r];
-                else
-                    acc += A[(int64_t)r * n + i] * z[r];
+// Publish this workgroup's share of the current pass and wait for the other
+// G - 1 workgroups of the instance.  The share is released (device-scope
+// fence) before the workgroup's sequence number is stored; thread t < G then
+// waits for workgroup t's number to reach `target`, so the wait costs one
+// round trip per poll and no read-modify-write.  The shares are then read
+// with device-coherent loads (share_load), which never return a stale cached
+// copy, so no cache invalidation is needed on the reading side.  A wait that
+// does not end within a bounded spin reports LH_FLAG_TIMEOUT, so every wave
+// exits.
+__device__ void sync_shares(int* flag, int G, int g, int target, int* status) {
+    __syncthreads();
+    if (G == 1) return;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_store(&flag[g], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if ((int)threadIdx.x < G) {
+        int it = 0;
+        typedef const __attribute__((address_space(1))) int gi32;
+        while (__hip_atomic_load((gi32*)&flag[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target < 0) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++it > (1 << 22)) {
+                atomicOr(status, LH_FLAG_TIMEOUT);
+                break;
             }
         }
-        double val = F32 ? (double)accf : acc;
-        // butterfly within the 16-lane group (same order on every lane)
-        for (int off = 8; off > 0; off >>= 1) val += __shfl_xor(val, off, 16);
-        if (i < n && l == 0) out[i] = val;
     }
     __syncthreads();
 }
 
-// Lift field rows of one chunk into LDS: out[slot][row] = os + sum_k tile[slot][k][row] y[k].
-template <int DIM, bool F32>
-__device__ __forceinline__ double lift_one(const WinDev& W, int f, int slot, int row, int rows, const double* y) {
-    const int n = W.n[f];
-    double acc = W.os_loc[f][(int64_t)slot * rows + row];
-    if (F32) {
-        const float* tp = W.tile32[f] + (int64_t)slot * n * rows + row;
-        float a = 0.0f;
-        for (int k = 0; k < n; ++k) a += tp[(int64_t)k * rows] * (float)y[k];
-        acc += (double)a;
-    } else {
-        const double* tp = W.tile[f] + (int64_t)slot * n * rows + row;
-        for (int k = 0; k < n; ++k) acc += tp[(int64_t)k * rows] * y[k];
-    }
-    return acc;
+// The pointer is taken as global memory explicitly: on a generic pointer the
+// compiler waits for every outstanding access before each such load, which
+// serialises them.
+__device__ __forceinline__ double share_load(const double* p) {
+    typedef const __attribute__((address_space(1))) unsigned long long gu64;
+    const unsigned long long b = __hip_atomic_load((gu64*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)b);
 }
 
-// Pass A: stress at every quadrature point of the sampled elements for the
-// state y = (x^, v^, e^), sampled rows of F.1 and their projection F^1.
-// Returns the minimum step estimate.
-template <int DIM, bool F32>
-__device__ double pass_a(const RomArgs& A, const WinDev& W, const InstDev& I, Smem<DIM>& S, const double* yx,
-                         const double* yv, const double* ye, int* status) {
-    constexpr int EC = Cfg<DIM>::EC, NKD = Cfg<DIM>::NKD, NT = Cfg<DIM>::NT, NQ = Cfg<DIM>::NQ;
-    constexpr int BLK = Cfg<DIM>::BLK;
+// os + sum_k tile[k*rows + row] y[k]
+template <class TT>
+__device__ __forceinline__ double lift_row(const TT* tp, const double* os, int n, int rows, const double* y) {
+    TT a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int k = 0;
+    for (; k + 3 < n; k += 4) {
+        a0 += tp[(k + 0) * rows] * (TT)y[k + 0];
+        a1 += tp[(k + 1) * rows] * (TT)y[k + 1];
+        a2 += tp[(k + 2) * rows] * (TT)y[k + 2];
+        a3 += tp[(k + 3) * rows] * (TT)y[k + 3];
+    }
+    for (; k < n; ++k) a0 += tp[k * rows] * (TT)y[k];
+    return *os + (double)((a0 + a1) + (a2 + a3));
+}
+
+// Pass A for one workgroup: kept stress, entries of F.1 at the sampled rows,
+// the share of F^1 and the minimum step estimate (written to `share`).
+template <int DIM, class TT>
+__device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const Local<TT>& L, NodeBuf<DIM>& B,
+                       Shared& S, double* fe, const double* yx, const double* yv, const double* ye, double* share,
+                       int* status) {
+    constexpr int EC = Cfg<DIM>::EC, NKD = Cfg<DIM>::NKD, NT = Cfg<DIM>::NT, NQ = Cfg<DIM>::NQ, DD = Cfg<DIM>::DD;
     const int tid = threadIdx.x;
     double tau = INFINITY;
-    for (int c0 = 0; c0 < W.n_el; c0 += EC) {
-        const int ne = min(EC, W.n_el - c0);
+    for (int c0 = 0; c0 < V.ns; c0 += EC) {
+        const int ne = min(EC, V.ns - c0);
         for (int t = tid; t < ne * (2 * NKD + NT); t += BLK) {
-            const int slot = t / (2 * NKD + NT);
+            const int sl = t / (2 * NKD + NT);
             const int r = t % (2 * NKD + NT);
+            const int slot = c0 + sl;
             if (r < NKD)
-                S.x[slot][r] = lift_one<DIM, F32>(W, 0, c0 + slot, r, NKD, yx);
+                B.x[sl][r] = lift_row(L.tile[0] + (int64_t)slot * W.n[0] * NKD + r, L.os[0] + slot * NKD + r, W.n[0],
+                                      NKD, yx);
             else if (r < 2 * NKD)
-                S.v[slot][r - NKD] = lift_one<DIM, F32>(W, 1, c0 + slot, r - NKD, NKD, yv);
+                B.v[sl][r - NKD] = lift_row(L.tile[1] + (int64_t)slot * W.n[1] * NKD + (r - NKD),
+                                            L.os[1] + slot * NKD + (r - NKD), W.n[1], NKD, yv);
             else
-                S.e[slot][r - 2 * NKD] = lift_one<DIM, F32>(W, 2, c0 + slot, r - 2 * NKD, NT, ye);
+                B.e[sl][r - 2 * NKD] = lift_row(L.tile[2] + (int64_t)slot * W.n[2] * NT + (r - 2 * NKD),
+                                                L.os[2] + slot * NT + (r - 2 * NKD), W.n[2], NT, ye);
         }
         __syncthreads();
         {
-            const int slot = tid / NQ, q = tid % NQ;
-            if (slot < ne) {
+            const int sl = tid / NQ, q = tid % NQ;
+            if (sl < ne) {
                 double sig[DIM][DIM];
                 double tq;
-                // local node order of the lift is (a, c) component-minor, as qp_stress expects
-                const int fl = qp_stress<DIM>(A.T, A.fc, q, S.x[slot], S.v[slot], S.e[slot], sig, tq);
+                const int fl = qp_stress<DIM>(A.T, A.fc, q, B.x[sl], B.v[sl], B.e[sl], sig, tq);
                 if (fl) atomicOr(status, fl);
                 tau = fmin(tau, tq);
-                double* dst = I.sig + ((int64_t)(c0 + slot) * NQ + q) * DIM * DIM;
+                double* dst = L.sig + ((int64_t)(c0 + sl) * NQ + q) * DD;
 #pragma unroll
                 for (int c = 0; c < DIM; ++c)
 #pragma unroll
@@ -208,128 +253,290 @@ __device__ double pass_a(const RomArgs& A, const WinDev& W, const InstDev& I, Sm
             }
         }
         __syncthreads();
-        for (int t = tid; t < ne * NKD; t += BLK) {
-            const int slot = t / NKD, r = t % NKD;
-            const int a = r / DIM, c = r % DIM;
-            int ax, ay, az;
-            a_coords<DIM>(a, ax, ay, az);
-            const double* sg = I.sig + (int64_t)(c0 + slot) * NQ * DIM * DIM;
-            double acc = 0.0;
-            for (int q = 0; q < NQ; ++q) {
-                int qx, qy, qz;
-                q_coords<DIM>(q, qx, qy, qz);
-#pragma unroll
-                for (int i = 0; i < DIM; ++i) acc += sg[q * DIM * DIM + c * DIM + i] * dshape(A.T, qx, qy, qz, ax, ay, az, i, DIM);
-            }
-            I.f1_loc[(int64_t)(c0 + slot) * NKD + r] = acc;
-        }
     }
-    __syncthreads();
-    for (int r = tid; r < W.ns1; r += BLK) {
+    // F.1 entries of this workgroup's elements at the sampled rows
+    for (int e = tid; e < V.nkin; e += BLK) {
+        const int slot = V.kin[3 * e], dof = V.kin[3 * e + 1];
+        const int a = dof / DIM, c = dof % DIM;
+        int ax, ay, az;
+        a_coords<DIM>(a, ax, ay, az);
+        const double* sg = L.sig + (int64_t)slot * NQ * DD;
         double acc = 0.0;
-        for (int k = W.c1_ptr[r]; k < W.c1_ptr[r + 1]; ++k) acc += I.f1_loc[W.c1_idx[k]];
-        I.fz1[r] = acc;
+        for (int q = 0; q < NQ; ++q) {
+            int qx, qy, qz;
+            q_coords<DIM>(q, qx, qy, qz);
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) acc += sg[q * DD + c * DIM + i] * dshape(A.T, qx, qy, qz, ax, ay, az, i, DIM);
+        }
+        fe[e] = acc;
     }
     __syncthreads();
-    project<DIM, F32>(W.A1, W.A1f, W.n[1], W.ns1, I.fz1, S.f1h);
-    return block_min<DIM>(tau, S.red);
+    const int nv = W.n[1];
+    for (int i = tid; i < nv; i += BLK) {
+        TT acc = 0;
+        for (int e = 0; e < V.nkin; ++e) {
+            const TT a = L.res ? L.a1[(int64_t)e * nv + i] : L.a1[(int64_t)V.kin[3 * e + 2] * nv + i];
+            acc += a * (TT)fe[e];
+        }
+        share[i] = (double)acc;
+    }
+    const double tmin = block_min(tau, S.red);
+    if (tid == 0) {
+        share[LH_NMAX] = tmin;
+        share[LH_NMAX + 1] = (double)*status;
+    }
 }
 
-// Pass B: F^tv = A2 (F^T v_c)_Z with the stress kept by the last pass A.
-template <int DIM, bool F32>
-__device__ void pass_b(const RomArgs& A, const WinDev& W, const InstDev& I, Smem<DIM>& S, const double* yvc) {
-    constexpr int EC = Cfg<DIM>::EC, NKD = Cfg<DIM>::NKD, NT = Cfg<DIM>::NT, NQ = Cfg<DIM>::NQ;
-    constexpr int BLK = Cfg<DIM>::BLK;
+// Pass B for one workgroup: F^T.v_c at its sampled energy dofs and its share of F^tv.
+template <int DIM, class TT>
+__device__ void pass_b(const RomArgs& A, const WinDev& W, const WgView& V, const Local<TT>& L, NodeBuf<DIM>& B,
+                       double* te, const double* yvc, double* share, const int* status) {
+    constexpr int EC = Cfg<DIM>::EC, NKD = Cfg<DIM>::NKD, NK = Cfg<DIM>::NK, NQ = Cfg<DIM>::NQ, DD = Cfg<DIM>::DD;
     const int tid = threadIdx.x;
-    for (int c0 = 0; c0 < W.n_own; c0 += EC) {
-        const int ne = min(EC, W.n_own - c0);
+    for (int c0 = 0; c0 < V.nown; c0 += EC) {
+        const int ne = min(EC, V.nown - c0);
         for (int t = tid; t < ne * NKD; t += BLK) {
             const int o = t / NKD, r = t % NKD;
-            S.v[o][r] = lift_one<DIM, F32>(W, 1, W.own[c0 + o], r, NKD, yvc);
+            const int slot = V.own[c0 + o];
+            B.v[o][r] = lift_row(L.tile[1] + (int64_t)slot * W.n[1] * NKD + r, L.os[1] + slot * NKD + r, W.n[1], NKD,
+                                 yvc);
         }
         __syncthreads();
         {
             const int o = tid / NQ, q = tid % NQ;
             if (o < ne) {
-                const double* sg = I.sig + ((int64_t)W.own[c0 + o] * NQ + q) * DIM * DIM;
+                const double* sg = L.sig + ((int64_t)V.own[c0 + o] * NQ + q) * DD;
                 int qx, qy, qz;
                 q_coords<DIM>(q, qx, qy, qz);
                 double acc = 0.0;
-                for (int a = 0; a < Cfg<DIM>::NKD / DIM; ++a) {
+                for (int a = 0; a < NK; ++a) {
                     int ax, ay, az;
                     a_coords<DIM>(a, ax, ay, az);
 #pragma unroll
                     for (int i = 0; i < DIM; ++i) {
                         const double g = dshape(A.T, qx, qy, qz, ax, ay, az, i, DIM);
 #pragma unroll
-                        for (int c = 0; c < DIM; ++c) acc += sg[c * DIM + i] * S.v[o][a * DIM + c] * g;
+                        for (int c = 0; c < DIM; ++c) acc += sg[c * DIM + i] * B.v[o][a * DIM + c] * g;
                     }
                 }
-                S.s[o][q] = acc;
+                B.s[o][q] = acc;
             }
         }
         __syncthreads();
-        for (int t = tid; t < ne * NT; t += BLK) {
-            const int o = t / NT, j = t % NT;
+        for (int e = tid; e < V.nth; e += BLK) {
+            const int oi = V.th[3 * e];
+            if (oi < c0 || oi >= c0 + ne) continue;
+            const int j = V.th[3 * e + 1];
             double acc = 0.0;
             for (int q = 0; q < NQ; ++q) {
                 int qx, qy, qz;
                 q_coords<DIM>(q, qx, qy, qz);
-                acc += tshape<DIM>(A.T, qx, qy, qz, j) * S.s[o][q];
+                acc += tshape<DIM>(A.T, qx, qy, qz, j) * B.s[oi - c0][q];
             }
-            I.ftv_loc[(int64_t)(c0 + o) * NT + j] = acc;
+            te[e] = acc;
         }
         __syncthreads();
     }
-    for (int r = tid; r < W.ns2; r += BLK) I.fz2[r] = I.ftv_loc[W.z2_loc[r]];
-    __syncthreads();
-    project<DIM, F32>(W.A2, W.A2f, W.n[2], W.ns2, I.fz2, S.ftvh);
+    const int ne_ = W.n[2];
+    for (int i = tid; i < ne_; i += BLK) {
+        TT acc = 0;
+        for (int e = 0; e < V.nth; ++e) {
+            const TT a = L.res ? L.a2[(int64_t)e * ne_ + i] : L.a2[(int64_t)V.th[3 * e + 2] * ne_ + i];
+            acc += a * (TT)te[e];
+        }
+        share[i] = (double)acc;
+    }
+    if (tid == 0) {
+        share[LH_NMAX] = INFINITY;
+        share[LH_NMAX + 1] = (double)*status;
+    }
 }
 
-// out = base + s * (b_x + B_xv vv)  over n_x entries
-template <int DIM>
-__device__ void x_update(const WinDev& W, const double* base, double s, const double* vv, double* out) {
-    for (int i = threadIdx.x; i < W.n[0]; i += Cfg<DIM>::BLK) {
-        double acc = W.bx[i];
-        for (int j = 0; j < W.n[1]; ++j) acc += W.Bxv[(int64_t)j * W.n[0] + i] * vv[j];
+__device__ __forceinline__ double comb_op(int kind, double a, double b) {
+    if (kind == 0) return a + b;
+    if (kind == 1) return fmin(a, b);
+    return (double)((int)a | (int)b);
+}
+
+// Combine the G shares of a pass: coefficients 0..n-1 are summed into out,
+// the step estimates reduced by min (returned), the status bits or-ed into
+// *status.  Thread (c, b) folds column c of the shares of workgroups
+// 8b .. 8b+7 in registers (eight independent loads in flight) into
+// stage[b * (n + 2) + c]; thread c then folds those ceil(G / 8) partial
+// results in order of b.  The order of the operations is fixed, so every
+// workgroup obtains bit-identical values.
+__device__ double combine(const double* part, int G, int n, double* out, int* status, Shared& S,
+                          double* stage) {
+    const int C = n + 2;
+    const int NB = (G + 7) >> 3;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < C * NB; t += BLK) {
+        const int c = t % C;
+        const int b = t / C;
+        const int kind = c < n ? 0 : c - n + 1;
+        const int m = min(8, G - 8 * b);
+        const double* src = part + (int64_t)(8 * b) * PSTRIDE + (c < n ? c : LH_NMAX + (c - n));
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = share_load(src + (int64_t)min(j, m - 1) * PSTRIDE);
+        double acc = v[0];
+#pragma unroll
+        for (int j = 1; j < 8; ++j)
+            if (j < m) acc = comb_op(kind, acc, v[j]);
+        stage[t] = acc;
+    }
+    __syncthreads();
+    if (tid < C) {
+        const int kind = tid < n ? 0 : tid - n + 1;
+        double acc = stage[tid];
+        for (int b = 1; b < NB; ++b) acc = comb_op(kind, acc, stage[b * C + tid]);
+        if (tid < n)
+            out[tid] = acc;
+        else
+            S.comb[tid - n] = acc;
+    }
+    __syncthreads();
+    const double t = S.comb[0];
+    const int st = (int)S.comb[1];
+    if (tid == 0 && st) atomicOr(status, st);
+    __syncthreads();
+    return t;
+}
+
+// Make the workgroup's window data resident in LDS (or point at global memory).
+template <int DIM, class TT>
+__device__ void load_local(const WinDev& W, const WgView& V, const InstDev& I, bool res, char* dyn, Local<TT>& L) {
+    constexpr int NKD = Cfg<DIM>::NKD, NT = Cfg<DIM>::NT, NQ = Cfg<DIM>::NQ, DD = Cfg<DIM>::DD;
+    const int rows[3] = {NKD, NKD, NT};
+    const TT* gt[3];
+    const TT* ga1;
+    const TT* ga2;
+    if (sizeof(TT) == 4) {
+        for (int f = 0; f < 3; ++f) gt[f] = reinterpret_cast<const TT*>(W.tile32[f]);
+        ga1 = reinterpret_cast<const TT*>(W.A1f);
+        ga2 = reinterpret_cast<const TT*>(W.A2f);
+    } else {
+        for (int f = 0; f < 3; ++f) gt[f] = reinterpret_cast<const TT*>(W.tile[f]);
+        ga1 = reinterpret_cast<const TT*>(W.A1);
+        ga2 = reinterpret_cast<const TT*>(W.A2);
+    }
+    L.res = res;
+    __syncthreads();  // nobody still reads the previous window's resident data
+    if (!res) {
+        for (int f = 0; f < 3; ++f) {
+            L.tile[f] = gt[f] + (int64_t)V.s0 * W.n[f] * rows[f];
+            L.os[f] = W.os_loc[f] + (int64_t)V.s0 * rows[f];
+        }
+        L.a1 = ga1;
+        L.a2 = ga2;
+        L.Bxv = W.Bxv;
+        L.bx = W.bx;
+        L.sig = I.sig + (int64_t)V.s0 * NQ * DD;
+        return;
+    }
+    // layout: sig (double) | os x, v, e (double) | tiles x, v, e (TT) | a1 | a2 (TT)
+    double* sig = reinterpret_cast<double*>(dyn);
+    double* os = sig + (int64_t)V.ns * NQ * DD;
+    TT* t = reinterpret_cast<TT*>(os + (int64_t)V.ns * (2 * NKD + NT));
+    L.sig = sig;
+    for (int f = 0; f < 3; ++f) {
+        double* od = os + (f == 0 ? 0 : f == 1 ? (int64_t)V.ns * NKD : (int64_t)V.ns * 2 * NKD);
+        const double* og = W.os_loc[f] + (int64_t)V.s0 * rows[f];
+        for (int k = threadIdx.x; k < V.ns * rows[f]; k += BLK) od[k] = og[k];
+        L.os[f] = od;
+        const int64_t cnt = (int64_t)V.ns * W.n[f] * rows[f];
+        const TT* src = gt[f] + (int64_t)V.s0 * W.n[f] * rows[f];
+        for (int64_t k = threadIdx.x; k < cnt; k += BLK) t[k] = src[k];
+        L.tile[f] = t;
+        t += cnt;
+    }
+    TT* a1 = t;
+    for (int k = threadIdx.x; k < V.nkin * W.n[1]; k += BLK) {
+        const int e = k / W.n[1], i = k % W.n[1];
+        a1[k] = ga1[(int64_t)V.kin[3 * e + 2] * W.n[1] + i];
+    }
+    TT* a2 = a1 + (int64_t)V.nkin * W.n[1];
+    for (int k = threadIdx.x; k < V.nth * W.n[2]; k += BLK) {
+        const int e = k / W.n[2], i = k % W.n[2];
+        a2[k] = ga2[(int64_t)V.th[3 * e + 2] * W.n[2] + i];
+    }
+    L.a1 = a1;
+    L.a2 = a2;
+    // B_xv and b_x (FP64) after the DEIM columns, 8-byte aligned
+    uintptr_t bp = reinterpret_cast<uintptr_t>(a2 + (int64_t)V.nth * W.n[2]);
+    double* bxv = reinterpret_cast<double*>((bp + 7) & ~(uintptr_t)7);
+    for (int k = threadIdx.x; k < W.n[0] * W.n[1]; k += BLK) bxv[k] = W.Bxv[k];
+    double* bx = bxv + W.n[0] * W.n[1];
+    for (int k = threadIdx.x; k < W.n[0]; k += BLK) bx[k] = W.bx[k];
+    L.Bxv = bxv;
+    L.bx = bx;
+    __syncthreads();
+}
+
+// out = base + s * (b_x + B_xv vv)
+template <class TT>
+__device__ void x_update(const WinDev& W, const Local<TT>& L, const double* base, double s, const double* vv,
+                         double* out) {
+    for (int i = threadIdx.x; i < W.n[0]; i += BLK) {
+        double acc = L.bx[i];
+        for (int j = 0; j < W.n[1]; ++j) acc += L.Bxv[(int64_t)j * W.n[0] + i] * vv[j];
         out[i] = base[i] + s * acc;
     }
 }
 
-template <int DIM, bool F32>
-__global__ void __launch_bounds__(Cfg<DIM>::BLK) rom_step_kernel(RomArgs A) {
-    __shared__ Smem<DIM> S;
+template <int DIM, class TT, bool RES>
+__global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
+    extern __shared__ double dyn_raw[];
+    __shared__ NodeBuf<DIM> B;
+    __shared__ Shared S;
     __shared__ lh_rom_state st;
-    __shared__ int s_status;
+    __shared__ int s_status, s_base;
     const int tid = threadIdx.x;
-    const int ii = blockIdx.x;
+    const int ii = blockIdx.x / A.G;
+    const int g = blockIdx.x % A.G;
     if (ii >= A.n_inst) return;
-    const InstDev I = A.inst[ii];
+    const InstDev& I = A.inst[ii];
+    double* fe = dyn_raw;
+    double* te = fe + A.nkin_max;
+    double* stage = te + A.nth_max;  // ceil(G / 8) x PSTRIDE partial results of combine
+    char* dyn = reinterpret_cast<char*>(stage + (int64_t)((A.G + 7) / 8) * PSTRIDE);
     if (tid == 0) {
         st = A.state[ii];
         s_status = 0;
+        s_base = __hip_atomic_load(&I.flag[g], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
     if (st.done) return;
     for (int f = 0; f < 3; ++f)
-        for (int k = tid; k < LH_NMAX; k += Cfg<DIM>::BLK) S.y[f][k] = st.yhat[f][k];
-    __syncthreads();
+        for (int k = tid; k < LH_NMAX; k += BLK) S.y[f][k] = st.yhat[f][k];
     const bool replay = (A.flags & LH_REPLAY_DT) != 0;
     const bool fixed = (A.flags & LH_FIXED_DT) != 0;
     const bool adaptive = !replay && !fixed;
     int w = st.w;
     double t = st.t, dt = st.dt;
     int n_steps = st.n_steps, n_rej = st.n_rejected, evals = st.n_force_evals;
+    int phase = 0;
+    Local<TT> L;
+    load_local<DIM, TT>(I.win[w], I.win[w].views[g], I, RES, dyn, L);
+    double* const part0 = I.part + (int64_t)g * PSTRIDE;                     // my share, even phases
+    double* const part1 = I.part + ((int64_t)A.G + g) * PSTRIDE;             // my share, odd phases
+    const double* const all0 = I.part;                                       // every share, even phases
+    const double* const all1 = I.part + (int64_t)A.G * PSTRIDE;              // every share, odd phases
     bool done = false;
     if (adaptive && !(dt > 0.0)) {
         const WinDev& W = I.win[w];
-        const double tau0 = pass_a<DIM, F32>(A, W, I, S, S.y[0], S.y[1], S.y[2], &s_status);
+        pass_a<DIM, TT>(A, W, W.views[g], L, B, S, fe, S.y[0], S.y[1], S.y[2], (phase & 1) ? part1 : part0,
+                        &s_status);
+        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status);
+        const double tau0 = combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage);
+        ++phase;
         evals += W.n_el;
         dt = BETA1 * tau0;
     }
     int accepted = 0;
     while (!done && accepted < A.max_steps) {
         const WinDev& W = I.win[w];
+        const WgView& V = W.views[g];
         double h;
         if (replay) {
             if (n_steps >= A.n_replay) {
@@ -347,27 +554,43 @@ __global__ void __launch_bounds__(Cfg<DIM>::BLK) rom_step_kernel(RomArgs A) {
             break;
         }
         // ---- stage 1 at y_n
-        const double tau1 = pass_a<DIM, F32>(A, W, I, S, S.y[0], S.y[1], S.y[2], &s_status);
-        for (int i = tid; i < W.n[1]; i += Cfg<DIM>::BLK) S.yh[1][i] = S.y[1][i] - 0.5 * h * S.f1h[i];
+        pass_a<DIM, TT>(A, W, V, L, B, S, fe, S.y[0], S.y[1], S.y[2], (phase & 1) ? part1 : part0, &s_status);
+        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status);
+        const double tau1 = combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage);
+        ++phase;
+        for (int i = tid; i < W.n[1]; i += BLK) S.yh[1][i] = S.y[1][i] - 0.5 * h * S.f1h[i];
         __syncthreads();
-        pass_b<DIM, F32>(A, W, I, S, S.yh[1]);
-        for (int i = tid; i < W.n[2]; i += Cfg<DIM>::BLK) S.yh[2][i] = S.y[2][i] + 0.5 * h * S.ftvh[i];
-        x_update<DIM>(W, S.y[0], 0.5 * h, S.yh[1], S.yh[0]);
+        pass_b<DIM, TT>(A, W, V, L, B, te, S.yh[1], (phase & 1) ? part1 : part0, &s_status);
+        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status);
+        combine((phase & 1) ? all1 : all0, A.G, W.n[2], S.ftvh, &s_status, S, stage);
+        ++phase;
+        for (int i = tid; i < W.n[2]; i += BLK) S.yh[2][i] = S.y[2][i] + 0.5 * h * S.ftvh[i];
+        x_update(W, L, S.y[0], 0.5 * h, S.yh[1], S.yh[0]);
         __syncthreads();
         // ---- stage 2 at y_{n+1/2}
-        const double tau2 = pass_a<DIM, F32>(A, W, I, S, S.yh[0], S.yh[1], S.yh[2], &s_status);
-        for (int i = tid; i < W.n[1]; i += Cfg<DIM>::BLK) {
+        pass_a<DIM, TT>(A, W, V, L, B, S, fe, S.yh[0], S.yh[1], S.yh[2], (phase & 1) ? part1 : part0, &s_status);
+        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status);
+        const double tau2 = combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage);
+        ++phase;
+        for (int i = tid; i < W.n[1]; i += BLK) {
             const double vn = S.y[1][i] - h * S.f1h[i];
             S.yn[1][i] = vn;
             S.vc[i] = 0.5 * (S.y[1][i] + vn);
         }
         __syncthreads();
-        pass_b<DIM, F32>(A, W, I, S, S.vc);
-        for (int i = tid; i < W.n[2]; i += Cfg<DIM>::BLK) S.yn[2][i] = S.y[2][i] + h * S.ftvh[i];
-        x_update<DIM>(W, S.y[0], h, S.vc, S.yn[0]);
+        pass_b<DIM, TT>(A, W, V, L, B, te, S.vc, (phase & 1) ? part1 : part0, &s_status);
+        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status);
+        combine((phase & 1) ? all1 : all0, A.G, W.n[2], S.ftvh, &s_status, S, stage);
+        ++phase;
+        for (int i = tid; i < W.n[2]; i += BLK) S.yn[2][i] = S.y[2][i] + h * S.ftvh[i];
+        x_update(W, L, S.y[0], h, S.vc, S.yn[0]);
         __syncthreads();
         evals += 2 * W.n_el;
         const double tau = fmin(tau1, tau2);
+        if (s_status & (LH_FLAG_TANGLED | LH_FLAG_NONFINITE | LH_FLAG_TIMEOUT)) {
+            done = true;
+            break;
+        }
         if (adaptive && h >= tau) {
             dt = BETA1 * h;
             ++n_rej;
@@ -375,35 +598,38 @@ __global__ void __launch_bounds__(Cfg<DIM>::BLK) rom_step_kernel(RomArgs A) {
         }
         if (adaptive) dt = h <= GAMMA_DT * tau ? BETA2 * h : h;
         for (int f = 0; f < 3; ++f)
-            for (int i = tid; i < W.n[f]; i += Cfg<DIM>::BLK) S.y[f][i] = S.yn[f][i];
+            for (int i = tid; i < W.n[f]; i += BLK) S.y[f][i] = S.yn[f][i];
         __syncthreads();
         t = t + h;
         ++n_steps;
         ++accepted;
         // window change (eq. ic-tw): y^w = T_w y^{w-1} + c_w
+        bool moved = false;
         while (w + 1 < I.n_windows && t >= I.win[w].t_end) {
             const WinDev& Wn = I.win[w + 1];
             const WinDev& Wo = I.win[w];
             for (int f = 0; f < 3; ++f) {
-                for (int i = tid; i < Wn.n[f]; i += Cfg<DIM>::BLK) {
+                for (int i = tid; i < Wn.n[f]; i += BLK) {
                     double acc = Wn.c[f][i];
                     for (int j = 0; j < Wo.n[f]; ++j) acc += Wn.T[f][(int64_t)j * Wn.n[f] + i] * S.y[f][j];
                     S.tmp[i] = acc;
                 }
                 __syncthreads();
-                for (int i = tid; i < LH_NMAX; i += Cfg<DIM>::BLK) S.y[f][i] = i < Wn.n[f] ? S.tmp[i] : 0.0;
+                for (int i = tid; i < LH_NMAX; i += BLK) S.y[f][i] = i < Wn.n[f] ? S.tmp[i] : 0.0;
                 __syncthreads();
             }
             ++w;
+            moved = true;
         }
+        if (moved) load_local<DIM, TT>(I.win[w], I.win[w].views[g], I, RES, dyn, L);
         if (replay)
             done = n_steps >= A.n_replay;
         else
             done = !(I.t_final - t > 1e-12 * I.t_final);
-        if (s_status & (LH_FLAG_TANGLED | LH_FLAG_NONFINITE)) done = true;
         __syncthreads();
     }
     __syncthreads();
+    if (g != 0) return;
     if (tid == 0) {
         st.t = t;
         st.dt = dt;
@@ -415,7 +641,7 @@ __global__ void __launch_bounds__(Cfg<DIM>::BLK) rom_step_kernel(RomArgs A) {
         st.done = done ? 1 : 0;
     }
     for (int f = 0; f < 3; ++f)
-        for (int k = tid; k < LH_NMAX; k += Cfg<DIM>::BLK) st.yhat[f][k] = S.y[f][k];
+        for (int k = tid; k < LH_NMAX; k += BLK) st.yhat[f][k] = S.y[f][k];
     __syncthreads();
     if (tid == 0) A.state[ii] = st;
 }
@@ -451,7 +677,12 @@ __global__ void copy_kernel(const double* a, double* b, int64_t n) {
     if (t < n) b[t] = a[t];
 }
 
-// C[i + j*m] = sum_r P[r + i*ld] Q[r + j*ld]  (P^T Q over N rows), one block per entry
+__global__ void zero_int_kernel(int* p, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0;
+}
+
+// C[i + j*m] = sum_r P[r + i*ldp] Q[r + j*ldq]  (P^T Q over N rows), one block per entry
 __global__ void __launch_bounds__(256) gemm_tn_kernel(const double* P, const double* Q, int64_t N, int64_t ldp,
                                                      int64_t ldq, int m, double* C) {
     __shared__ double sh[256];
@@ -473,7 +704,7 @@ __global__ void sub_kernel(const double* a, const double* b, double* d, int64_t 
     if (t < n) d[t] = a[t] - b[t];
 }
 
-// y^ = Phi^T (y0 - os) per (instance, field, column); writes the state array
+// y^ = Phi^T (y0 - os), one block per basis column
 __global__ void __launch_bounds__(256) init_coords_kernel(const double* Phi, int64_t N, const double* y0,
                                                          const double* os, double* out) {
     __shared__ double sh[256];
@@ -489,6 +720,19 @@ __global__ void __launch_bounds__(256) init_coords_kernel(const double* Phi, int
     if (threadIdx.x == 0) out[k] = sh[0];
 }
 
+// zero every field of the online state, set the controller step
+__global__ void reset_state_kernel(lh_rom_state* st, int n, double dt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    lh_rom_state z;
+    z.t = 0.0;
+    z.dt = dt;
+    z.w = z.status = z.n_steps = z.n_rejected = z.n_force_evals = z.done = 0;
+    for (int f = 0; f < 3; ++f)
+        for (int k = 0; k < LH_NMAX; ++k) z.yhat[f][k] = 0.0;
+    st[i] = z;
+}
+
 // y = os + Phi y^
 __global__ void lift_full_kernel(const double* Phi, int64_t N, int n, const double* yhat, const double* os,
                                  double* y) {
@@ -499,6 +743,16 @@ __global__ void lift_full_kernel(const double* Phi, int64_t N, int n, const doub
     y[r] = acc;
 }
 
+// Host copy of the integer structure of one window (the partition into
+// workgroup views is built from it once G is known).
+struct HostWin {
+    int n_el;
+    int n[3];
+    std::vector<std::vector<std::pair<int, int>>> contrib;  // per sampled kinematic row: (slot, dof)
+    std::vector<int> own_slot;                              // owner index -> closure slot
+    std::vector<std::pair<int, int>> th;                    // per sampled energy row: (owner index, local dof)
+};
+
 }  // namespace rom
 }  // namespace lh
 
@@ -506,11 +760,14 @@ __global__ void lift_full_kernel(const double* Phi, int64_t N, int n, const doub
 struct lh_rom {
     const lh_problem* p;
     int n_inst;
+    int G;
+    int nkin_max, nth_max;
+    int res_max64, res_max32;
     std::vector<void*> allocs;
     lh::rom::InstDev* d_inst;
     std::vector<lh::rom::InstDev> h_inst;
     std::vector<std::vector<lh::rom::WinDev>> h_win;
-    std::vector<std::vector<int>> n_el;  // per instance, per window
+    std::vector<std::vector<lh::rom::HostWin>> h_struct;
 };
 
 namespace lh {
@@ -530,20 +787,21 @@ static int dev_alloc(lh_rom* R, T** out, size_t count) {
 }
 
 template <class T>
-static int upload(lh_rom* R, const std::vector<T>& h, const T** out, hipStream_t s) {
+static int upload(lh_rom* R, const std::vector<T>& h, const T** out) {
     T* d = nullptr;
     int rc = dev_alloc(R, &d, h.size());
     if (rc) return rc;
-    if (!h.empty()) LH_HIP_CHECK(hipMemcpyAsync(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, s));
+    // synchronous: the host vectors are temporaries of the caller
+    if (!h.empty()) LH_HIP_CHECK(hipMemcpy(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
     *out = d;
     return LH_OK;
 }
 
 static unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-// Build the device tables of one window.
+// Build the device tables of one window and its host structure.
 static int build_window(lh_rom* R, const lh_problem* p, const lh_window_desc& wd, const lh_window_desc* prev,
-                        WinDev& W, hipStream_t s) {
+                        WinDev& W, HostWin& H, hipStream_t s) {
     const int dim = p->dim;
     const int NK = dim == 3 ? 27 : 9, NT = dim == 3 ? 8 : 4, NKD = NK * dim;
     const int64_t NV = p->NV, NE = p->NE, nn = p->n_nodes;
@@ -551,24 +809,19 @@ static int build_window(lh_rom* R, const lh_problem* p, const lh_window_desc& wd
     for (int f = 0; f < 3; ++f) {
         LH_REQUIRE(wd.n[f] >= 1 && wd.n[f] <= LH_NMAX, "rom_create: basis dimension outside [1, 64]");
         LH_REQUIRE(wd.phi[f] && wd.os[f], "rom_create: null basis or offset");
-        W.n[f] = wd.n[f];
+        W.n[f] = H.n[f] = wd.n[f];
     }
     LH_REQUIRE(wd.n_s1 >= wd.n[1] && wd.n_s1 <= NV && wd.z1 && wd.a1, "rom_create: bad F.1 sampling");
     LH_REQUIRE(wd.n_s2 >= wd.n[2] && wd.n_s2 <= NE && wd.z2 && wd.a2, "rom_create: bad F^T.v sampling");
-    W.ns1 = wd.n_s1;
-    W.ns2 = wd.n_s2;
     std::vector<int32_t> z1(wd.n_s1), z2(wd.n_s2);
     LH_HIP_CHECK(hipMemcpyAsync(z1.data(), wd.z1, sizeof(int32_t) * wd.n_s1, hipMemcpyDeviceToHost, s));
     LH_HIP_CHECK(hipMemcpyAsync(z2.data(), wd.z2, sizeof(int32_t) * wd.n_s2, hipMemcpyDeviceToHost, s));
     LH_HIP_CHECK(hipStreamSynchronize(s));
     // closure: elements around each sampled kinematic node, owners of sampled energy dofs
     std::set<int> els;
-    std::vector<int> z1_node(wd.n_s1), z1_comp(wd.n_s1);
     for (int r = 0; r < wd.n_s1; ++r) {
         LH_REQUIRE(z1[r] >= 0 && z1[r] < NV, "rom_create: F.1 sample index out of range");
         const int64_t node = z1[r] % nn;
-        z1_node[r] = (int)node;
-        z1_comp[r] = (int)(z1[r] / nn);
         const int g[3] = {(int)(node % p->nn[0]), (int)((node / p->nn[0]) % p->nn[1]),
                           dim == 3 ? (int)(node / ((int64_t)p->nn[0] * p->nn[1])) : 0};
         int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
@@ -590,11 +843,12 @@ static int build_window(lh_rom* R, const lh_problem* p, const lh_window_desc& wd
     }
     std::vector<int> elem(els.begin(), els.end());
     const int n_el = (int)elem.size();
-    W.n_el = n_el;
+    W.n_el = H.n_el = n_el;
     std::map<int, int> slot_of;
     for (int i = 0; i < n_el; ++i) slot_of[elem[i]] = i;
     // global rows of every element-local dof
     std::vector<int64_t> growk((size_t)n_el * NKD), growt((size_t)n_el * NT);
+    std::map<int64_t, std::vector<std::pair<int, int>>> where;  // kinematic row -> (slot, dof)
     for (int sl = 0; sl < n_el; ++sl) {
         const int K = elem[sl];
         const int ex = K % p->nel[0], ey = (K / p->nel[0]) % p->nel[1], ez = dim == 3 ? K / (p->nel[0] * p->nel[1]) : 0;
@@ -602,53 +856,45 @@ static int build_window(lh_rom* R, const lh_problem* p, const lh_window_desc& wd
             const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
             int64_t node = (2 * ex + ax) + (int64_t)p->nn[0] * (2 * ey + ay);
             if (dim == 3) node += (int64_t)p->nn[0] * p->nn[1] * (2 * ez + az);
-            for (int c = 0; c < dim; ++c) growk[(size_t)sl * NKD + a * dim + c] = c * nn + node;
+            for (int c = 0; c < dim; ++c) {
+                growk[(size_t)sl * NKD + a * dim + c] = c * nn + node;
+                where[c * nn + node].push_back({sl, a * dim + c});
+            }
         }
         for (int j = 0; j < NT; ++j) growt[(size_t)sl * NT + j] = (int64_t)K * NT + j;
     }
     // contributors of each sampled kinematic row (none for wall-constrained rows: F.1 is zero there)
-    std::vector<int> c1_ptr(wd.n_s1 + 1, 0), c1_idx;
+    H.contrib.assign(wd.n_s1, {});
     for (int r = 0; r < wd.n_s1; ++r) {
-        const int64_t node = z1_node[r];
-        const int c = z1_comp[r];
+        const int64_t node = z1[r] % nn;
+        const int c = (int)(z1[r] / nn);
         const int gc = c == 0 ? (int)(node % p->nn[0]) : c == 1 ? (int)((node / p->nn[0]) % p->nn[1])
                                                                 : (int)(node / ((int64_t)p->nn[0] * p->nn[1]));
         const bool wall = gc == 0 || gc == p->nn[c] - 1;
-        if (!wall)
-            for (int sl = 0; sl < n_el; ++sl)
-                for (int a = 0; a < NK; ++a)
-                    if (growk[(size_t)sl * NKD + a * dim + c] == z1[r]) c1_idx.push_back(sl * NKD + a * dim + c);
-        c1_ptr[r + 1] = (int)c1_idx.size();
+        if (!wall) H.contrib[r] = where[z1[r]];
     }
     // owners of sampled energy dofs
-    std::vector<int> own, z2_loc(wd.n_s2);
     std::map<int, int> own_of;
+    H.own_slot.clear();
+    H.th.assign(wd.n_s2, {0, 0});
     for (int r = 0; r < wd.n_s2; ++r) {
         const int K = z2[r] / NT;
         auto it = own_of.find(K);
         int oi;
         if (it == own_of.end()) {
-            oi = (int)own.size();
+            oi = (int)H.own_slot.size();
             own_of[K] = oi;
-            own.push_back(slot_of[K]);
+            H.own_slot.push_back(slot_of[K]);
         } else {
             oi = it->second;
         }
-        z2_loc[r] = oi * NT + z2[r] % NT;
+        H.th[r] = {oi, z2[r] % NT};
     }
-    W.n_own = (int)own.size();
     int rc;
-    const int* d_elem;
-    if ((rc = upload(R, elem, &d_elem, s))) return rc;
-    W.elem = d_elem;
-    if ((rc = upload(R, c1_ptr, &W.c1_ptr, s))) return rc;
-    if ((rc = upload(R, c1_idx, &W.c1_idx, s))) return rc;
-    if ((rc = upload(R, own, &W.own, s))) return rc;
-    if ((rc = upload(R, z2_loc, &W.z2_loc, s))) return rc;
     const int64_t* d_growk;
     const int64_t* d_growt;
-    if ((rc = upload(R, growk, &d_growk, s))) return rc;
-    if ((rc = upload(R, growt, &d_growt, s))) return rc;
+    if ((rc = upload(R, growk, &d_growk))) return rc;
+    if ((rc = upload(R, growt, &d_growt))) return rc;
     for (int f = 0; f < 3; ++f) {
         const int rows = f == 2 ? NT : NKD;
         const int64_t* grow = f == 2 ? d_growt : d_growk;
@@ -710,8 +956,94 @@ static int build_window(lh_rom* R, const lh_problem* p, const lh_window_desc& wd
             W.c[f] = c;
         }
     }
+    W.views = nullptr;
     return launch_check("rom_create window tables");
 }
+
+// Resident LDS bytes of a view: kept stress, offsets (FP64), tiles and A columns (tb bytes per value).
+static int64_t resident_bytes(int dim, const HostWin& H, int ns, int nkin, int nth, int tb) {
+    const int NK = dim == 3 ? 27 : 9, NT = dim == 3 ? 8 : 4, NKD = NK * dim, NQ = dim == 3 ? 64 : 16;
+    int64_t b = 8LL * ns * NQ * dim * dim + 8LL * ns * (2 * NKD + NT);
+    b += (int64_t)tb * ns * (NKD * (H.n[0] + H.n[1]) + NT * H.n[2]);
+    b += (int64_t)tb * ((int64_t)nkin * H.n[1] + (int64_t)nth * H.n[2]);
+    b = ((b + 7) & ~7LL) + 8LL * ((int64_t)H.n[0] * H.n[1] + H.n[0]);  // B_xv, b_x
+    return (b + 15) & ~15LL;
+}
+
+// Split every window of an instance into G contiguous slot ranges and upload the views.
+static int build_views(lh_rom* R, int i, int G) {
+    const int dim = R->p->dim;
+    auto& wins = R->h_win[i];
+    auto& hs = R->h_struct[i];
+    for (size_t w = 0; w < wins.size(); ++w) {
+        const HostWin& H = hs[w];
+        std::vector<WgView> views(G);
+        const int per = (H.n_el + G - 1) / G;
+        for (int g = 0; g < G; ++g) {
+            WgView& V = views[g];
+            V.s0 = std::min(H.n_el, g * per);
+            V.ns = std::max(0, std::min(H.n_el, (g + 1) * per) - V.s0);
+            std::vector<int> kin, own, th;
+            for (size_t r = 0; r < H.contrib.size(); ++r)
+                for (auto& sd : H.contrib[r])
+                    if (sd.first >= V.s0 && sd.first < V.s0 + V.ns) {
+                        kin.push_back(sd.first - V.s0);
+                        kin.push_back(sd.second);
+                        kin.push_back((int)r);
+                    }
+            std::map<int, int> local_owner;
+            for (size_t o = 0; o < H.own_slot.size(); ++o) {
+                const int sl = H.own_slot[o];
+                if (sl >= V.s0 && sl < V.s0 + V.ns) {
+                    local_owner[(int)o] = (int)own.size();
+                    own.push_back(sl - V.s0);
+                }
+            }
+            for (size_t r = 0; r < H.th.size(); ++r) {
+                auto it = local_owner.find(H.th[r].first);
+                if (it == local_owner.end()) continue;
+                th.push_back(it->second);
+                th.push_back(H.th[r].second);
+                th.push_back((int)r);
+            }
+            V.nkin = (int)kin.size() / 3;
+            V.nown = (int)own.size();
+            V.nth = (int)th.size() / 3;
+            int rc;
+            if ((rc = upload(R, kin, &V.kin)) || (rc = upload(R, own, &V.own)) || (rc = upload(R, th, &V.th)))
+                return rc;
+            const int64_t b64 = resident_bytes(dim, H, V.ns, V.nkin, V.nth, 8);
+            const int64_t b32 = resident_bytes(dim, H, V.ns, V.nkin, V.nth, 4);
+            V.res_bytes64 = (int)std::min<int64_t>(b64, 1 << 30);
+            V.res_bytes32 = (int)std::min<int64_t>(b32, 1 << 30);
+            R->nkin_max = std::max(R->nkin_max, V.nkin);
+            R->nth_max = std::max(R->nth_max, V.nth);
+            R->res_max64 = std::max(R->res_max64, V.res_bytes64);
+            R->res_max32 = std::max(R->res_max32, V.res_bytes32);
+        }
+        const WgView* dv;
+        int rc = upload(R, views, &dv);
+        if (rc) return rc;
+        wins[w].views = dv;
+    }
+    return LH_OK;
+}
+
+static int lds_budget() {
+    int dev = 0, v = 65536;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    return v;
+}
+
+static int cu_count() {
+    int dev = 0, v = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+    return v;
+}
+
+constexpr int STATIC_LDS_RESERVE = 24 * 1024;  // node buffers, reduced vectors, state (bytes, upper bound)
+constexpr int MAX_G = 64;                      // workgroups per instance (bounds the share staging in LDS)
+constexpr int ELEMS_PER_WG = 8;                // default cap on sampled elements per workgroup
 
 }  // namespace rom
 }  // namespace lh
@@ -725,15 +1057,18 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
     lh_rom* R = new lh_rom();
     R->p = p;
     R->n_inst = n_inst;
+    R->G = 1;
+    R->nkin_max = R->nth_max = R->res_max64 = R->res_max32 = 0;
     R->h_inst.resize(n_inst);
     R->h_win.resize(n_inst);
-    R->n_el.resize(n_inst);
+    R->h_struct.resize(n_inst);
     const int dim = p->dim;
-    const int NK = dim == 3 ? 27 : 9, NT = dim == 3 ? 8 : 4, NQ = dim == 3 ? 64 : 16;
+    const int NQ = dim == 3 ? 64 : 16;
     auto fail = [&](int rc) {
         rom_destroy(R);
         return rc;
     };
+    int max_el = 0;
     for (int i = 0; i < n_inst; ++i) {
         const lh_instance_desc& d = inst[i];
         if (d.n_windows < 1 || !d.windows || !(d.t_final > 0.0)) {
@@ -741,32 +1076,51 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
             return fail(LH_EINVAL);
         }
         R->h_win[i].resize(d.n_windows);
-        int max_el = 0, max_own = 0, max_ns1 = 0, max_ns2 = 0;
+        R->h_struct[i].resize(d.n_windows);
         for (int w = 0; w < d.n_windows; ++w) {
-            int rc = build_window(R, p, d.windows[w], w > 0 ? &d.windows[w - 1] : nullptr, R->h_win[i][w], s);
+            int rc = build_window(R, p, d.windows[w], w > 0 ? &d.windows[w - 1] : nullptr, R->h_win[i][w],
+                                  R->h_struct[i][w], s);
             if (rc) return fail(rc);
-            const WinDev& W = R->h_win[i][w];
-            max_el = std::max(max_el, W.n_el);
-            max_own = std::max(max_own, W.n_own);
-            max_ns1 = std::max(max_ns1, W.ns1);
-            max_ns2 = std::max(max_ns2, W.ns2);
-            R->n_el[i].push_back(W.n_el);
+            max_el = std::max(max_el, R->h_win[i][w].n_el);
         }
+    }
+    // workgroups per instance: enough that every workgroup's window data fits in LDS, within
+    // what can be co-resident (one workgroup per compute unit)
+    const int budget = lds_budget() - STATIC_LDS_RESERVE - 8 * (MAX_G / 8) * PSTRIDE;
+    const int max_g = std::max(1, std::min(MAX_G, cu_count() / n_inst));
+    int G = 1;
+    if (max_g > 1) {
+        int64_t worst_per_elem = 0;
+        for (int i = 0; i < n_inst; ++i)
+            for (auto& H : R->h_struct[i])
+                worst_per_elem = std::max<int64_t>(worst_per_elem, resident_bytes(dim, H, 1, 0, 0, 8) +
+                                                              8LL * (H.n[1] * 4 + H.n[2]));
+        // at most ELEMS_PER_WG elements per workgroup: fewer workgroups make each pass longer, more
+        // make the share exchange longer
+        int per_wg = std::max<int64_t>(1, std::min<int64_t>(ELEMS_PER_WG, (int64_t)(0.8 * budget) /
+                                                                            std::max<int64_t>(1, worst_per_elem)));
+        if (const char* env = std::getenv("LAGROM_ELEMS_PER_WG")) per_wg = std::max(1, std::atoi(env));
+        G = std::min(max_g, std::max(1, (max_el + per_wg - 1) / per_wg));
+    }
+    R->G = G;
+    for (int i = 0; i < n_inst; ++i) {
+        int rc = build_views(R, i, G);
+        if (rc) return fail(rc);
         InstDev& I = R->h_inst[i];
-        I.n_windows = d.n_windows;
-        I.t_final = d.t_final;
-        int rc;
-        if ((rc = dev_alloc(R, &I.sig, (int64_t)max_el * NQ * dim * dim)) ||
-            (rc = dev_alloc(R, &I.f1_loc, (int64_t)max_el * NK * dim)) ||
-            (rc = dev_alloc(R, &I.ftv_loc, (int64_t)max_own * NT)) || (rc = dev_alloc(R, &I.fz1, max_ns1)) ||
-            (rc = dev_alloc(R, &I.fz2, max_ns2)))
+        I.n_windows = inst[i].n_windows;
+        I.t_final = inst[i].t_final;
+        int ie = 0;
+        for (auto& W : R->h_win[i]) ie = std::max(ie, W.n_el);
+        if ((rc = dev_alloc(R, &I.sig, (int64_t)ie * NQ * dim * dim)) ||
+            (rc = dev_alloc(R, &I.part, (int64_t)2 * G * PSTRIDE)) || (rc = dev_alloc(R, &I.flag, G)))
             return fail(rc);
+        hipLaunchKernelGGL(zero_int_kernel, dim3((G + 63) / 64), dim3(64), 0, s, I.flag, (int64_t)G);
         const WinDev* dw;
-        if ((rc = upload(R, R->h_win[i], &dw, s))) return fail(rc);
+        if ((rc = upload(R, R->h_win[i], &dw))) return fail(rc);
         I.win = dw;
     }
     const InstDev* di;
-    int rc = upload(R, R->h_inst, &di, s);
+    int rc = upload(R, R->h_inst, &di);
     if (rc) return fail(rc);
     R->d_inst = const_cast<InstDev*>(di);
     if (hipStreamSynchronize(s) != hipSuccess) {
@@ -789,12 +1143,9 @@ int rom_init_state(const lh_rom* R, const lh_instance_desc* inst, const double* 
     using namespace lh::rom;
     LH_REQUIRE(R && inst && x0 && v0 && e0 && state, "rom_init_state: null argument");
     const lh_problem* p = R->p;
-    std::vector<lh_rom_state> h(R->n_inst);
-    for (int i = 0; i < R->n_inst; ++i) {
-        std::memset(&h[i], 0, sizeof(lh_rom_state));
-        h[i].dt = dt0 > 0.0 ? dt0 : -1.0;  // <= 0: the first rom_step takes 0.85 tau(y~_0)
-    }
-    LH_HIP_CHECK(hipMemcpyAsync(state, h.data(), sizeof(lh_rom_state) * R->n_inst, hipMemcpyHostToDevice, s));
+    // dt <= 0 makes the first rom_step start from 0.85 tau(y~_0)
+    hipLaunchKernelGGL(reset_state_kernel, dim3((R->n_inst + 63) / 64), dim3(64), 0, s, state, R->n_inst,
+                       dt0 > 0.0 ? dt0 : -1.0);
     for (int i = 0; i < R->n_inst; ++i) {
         const lh_window_desc& w0 = inst[i].windows[0];
         const double* y0[3] = {x0 + (int64_t)i * p->NV, v0 + (int64_t)i * p->NV, e0 + (int64_t)i * p->NE};
@@ -809,6 +1160,43 @@ int rom_init_state(const lh_rom* R, const lh_instance_desc* inst, const double* 
     return launch_check("rom_init_state");
 }
 
+}  // extern "C"
+
+namespace lh {
+namespace rom {
+
+template <int DIM, class TT, bool RES>
+static int launch_rom(const lh_rom* R, const RomArgs& A, size_t dyn, hipStream_t s) {
+    auto kern = rom_step_kernel<DIM, TT, RES>;
+    if (dyn > 0) LH_HIP_CHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+    dim3 grid(R->n_inst * R->G), block(BLK);
+    if (R->G > 1) {
+        RomArgs a = A;
+        void* args[] = {&a};
+        LH_HIP_CHECK(hipLaunchCooperativeKernel((const void*)kern, grid, block, args, (unsigned)dyn, s));
+    } else {
+        hipLaunchKernelGGL(kern, grid, block, dyn, s, A);
+    }
+    return launch_check("rom_step_kernel");
+}
+
+template <int DIM>
+static int dispatch(const lh_rom* R, const RomArgs& A, bool f32, hipStream_t s) {
+    const size_t entries = 8 * (size_t)(A.nkin_max + A.nth_max + (int64_t)((A.G + 7) / 8) * PSTRIDE);
+    const int budget = lds_budget() - STATIC_LDS_RESERVE;
+    const int res = f32 ? R->res_max32 : R->res_max64;
+    const bool resident = (int64_t)entries + res <= budget;
+    const size_t dyn = entries + (resident ? (size_t)res : 0);
+    if (f32)
+        return resident ? launch_rom<DIM, float, true>(R, A, dyn, s) : launch_rom<DIM, float, false>(R, A, dyn, s);
+    return resident ? launch_rom<DIM, double, true>(R, A, dyn, s) : launch_rom<DIM, double, false>(R, A, dyn, s);
+}
+
+}  // namespace rom
+}  // namespace lh
+
+extern "C" {
+
 int rom_step(const lh_rom* R, lh_rom_state* state, int32_t max_steps, uint32_t flags, const double* dt_replay,
              int32_t n_replay, hipStream_t s) {
     using namespace lh;
@@ -819,30 +1207,18 @@ int rom_step(const lh_rom* R, lh_rom_state* state, int32_t max_steps, uint32_t f
     RomArgs A;
     A.T = p->tab;
     A.fc = p->fc;
-    A.nex = p->nel[0];
-    A.ney = p->nel[1];
-    A.nnx = p->nn[0];
-    A.nny = p->nn[1];
     A.inst = R->d_inst;
     A.state = state;
     A.n_inst = R->n_inst;
+    A.G = R->G;
     A.max_steps = max_steps;
     A.flags = flags;
     A.dt_replay = dt_replay;
     A.n_replay = n_replay;
+    A.nkin_max = R->nkin_max;
+    A.nth_max = R->nth_max;
     const bool f32 = (flags & LH_FP32_LIFT) != 0;
-    if (p->dim == 2) {
-        if (f32)
-            hipLaunchKernelGGL((rom_step_kernel<2, true>), dim3(R->n_inst), dim3(Cfg<2>::BLK), 0, s, A);
-        else
-            hipLaunchKernelGGL((rom_step_kernel<2, false>), dim3(R->n_inst), dim3(Cfg<2>::BLK), 0, s, A);
-    } else {
-        if (f32)
-            hipLaunchKernelGGL((rom_step_kernel<3, true>), dim3(R->n_inst), dim3(Cfg<3>::BLK), 0, s, A);
-        else
-            hipLaunchKernelGGL((rom_step_kernel<3, false>), dim3(R->n_inst), dim3(Cfg<3>::BLK), 0, s, A);
-    }
-    return launch_check("rom_step_kernel");
+    return p->dim == 2 ? dispatch<2>(R, A, f32, s) : dispatch<3>(R, A, f32, s);
 }
 
 int rom_lift(const lh_rom* R, const lh_rom_state* state, int32_t inst, const lh_instance_desc* d, double* x,
@@ -871,8 +1247,15 @@ int rom_sampled_elements(const lh_rom* R, int32_t inst, int32_t window, int32_t*
     using namespace lh;
     LH_REQUIRE(R && n_elems, "rom_sampled_elements: null argument");
     LH_REQUIRE(inst >= 0 && inst < R->n_inst, "rom_sampled_elements: instance out of range");
-    LH_REQUIRE(window >= 0 && window < (int)R->n_el[inst].size(), "rom_sampled_elements: window out of range");
-    *n_elems = R->n_el[inst][window];
+    LH_REQUIRE(window >= 0 && window < (int)R->h_win[inst].size(), "rom_sampled_elements: window out of range");
+    *n_elems = R->h_win[inst][window].n_el;
+    return LH_OK;
+}
+
+int rom_workgroups_per_instance(const lh_rom* R, int32_t* G) {
+    using namespace lh;
+    LH_REQUIRE(R && G, "rom_workgroups_per_instance: null argument");
+    *G = R->G;
     return LH_OK;
 }
 

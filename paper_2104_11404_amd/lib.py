@@ -89,6 +89,13 @@ _SIGNATURES = {
     "rom_step": (_I32, [_VP, _VP, _I32, _U32, _VP, _I32, _VP]),
     "rom_lift": (_I32, [_VP, _VP, _I32, C.POINTER(InstanceDesc), _VP, _VP, _VP, _VP]),
     "rom_sampled_elements": (_I32, [_VP, _I32, _I32, C.POINTER(_I32)]),
+    "rom_workgroups_per_instance": (_I32, [_VP, C.POINTER(_I32)]),
+    "lh_snapshot_deviation": (_I32, [_VP, _I64, _I32, _I64, _VP, _VP, _I64, _VP]),
+    "lh_mass_apply_v": (_I32, [_VP, _VP, _VP, _VP]),
+    "lh_mass_apply_e": (_I32, [_VP, _VP, _VP, _VP]),
+    "lh_windows_by_samples": (_I32, [_I32, C.POINTER(C.POINTER(_D)), C.POINTER(_I32), _I32, C.POINTER(_D), _I32,
+                                     C.POINTER(_I32)]),
+    "lh_window_columns": (_I32, [C.POINTER(_D), _I32, C.POINTER(_D), _I32, C.POINTER(_I32), C.POINTER(_I32)]),
     "lh_status_read": (_I32, [_VP, C.POINTER(_I32), _VP]),
     "lh_last_error": (C.c_char_p, []),
 }

@@ -1,0 +1,96 @@
+"""Offline phase on the GPU: FOM snapshots, time windows, POD, SNS bases, DEIM.
+
+Argument marshalling and call sequencing only: every numerical step is a
+liblagrom call (lh_fom_run, lh_windows_by_samples, lh_window_columns,
+lh_snapshot_deviation, rom_build_basis, lh_mass_apply_v/_e, rom_sample_deim).
+The result is the instance description that ``lib.Rom`` hands to rom_create.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import lib
+
+
+def windows_by_samples(t_lists: list, n_sample: int) -> list:
+    """Window end points by number of samples (eq. sample_window) over every parameter's times."""
+    so = lib.load()
+    arrs = [(C.c_double * len(t))(*t) for t in t_lists]
+    ptrs = (C.POINTER(C.c_double) * len(arrs))(*[C.cast(a, C.POINTER(C.c_double)) for a in arrs])
+    nsteps = (C.c_int32 * len(t_lists))(*[len(t) - 1 for t in t_lists])
+    cap = 4 * max(len(t) for t in t_lists) + 8
+    T = (C.c_double * cap)()
+    nw = C.c_int32()
+    lib._check(so.lh_windows_by_samples(len(t_lists), ptrs, nsteps, int(n_sample), T, cap, C.byref(nw)))
+    return list(T[: nw.value])
+
+
+def windows_physical(t_final: float, n_windows: int) -> list:
+    """User-chosen uniform window end points (Sec. 4.4.1)."""
+    return [t_final * (w + 1) / n_windows for w in range(n_windows)]
+
+
+def window_columns(t: list, T: list):
+    so = lib.load()
+    ta = (C.c_double * len(t))(*t)
+    Ta = (C.c_double * len(T))(*T)
+    first = (C.c_int32 * len(T))()
+    ncol = (C.c_int32 * len(T))()
+    lib._check(so.lh_window_columns(ta, len(t) - 1, Ta, len(T), first, ncol))
+    return list(first), list(ncol)
+
+
+def fom_trajectory(P: lib.Problem, t_final: float, fixed_dt: float = 0.0, max_steps: int = 200000):
+    """GPU FOM from the problem's initial state; returns initial state, final state and snapshots."""
+    x0, v0, e0 = P.initial_state()
+    x, v, e = x0.clone(), v0.clone(), e0.clone()
+    probe = P.fom_run(x, v, e, t_final, fixed_dt=fixed_dt, max_steps=max_steps, record=False)
+    x, v, e = x0.clone(), v0.clone(), e0.clone()
+    out = P.fom_run(x, v, e, t_final, fixed_dt=fixed_dt, max_steps=probe["n_steps"], record=True,
+                    max_snap=2 * probe["n_steps"])
+    out.update(y0=(x0, v0, e0), y_final=(x, v, e))
+    return out
+
+
+def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_frac=0.9999, n_fixed=(), n_max=64,
+                  lam=(2.0, 2.0), t_final=None, verbose=False):
+    """Per-window POD, SNS and DEIM on the GPU; returns a lib.Rom instance description."""
+    so = lib.load()
+    stream = lib.stream_handle()
+    sizes = (P.NV, P.NV, P.NE)
+    cols = [window_columns(tr["t"], T) for tr in trajs]
+    windows = []
+    for w, Tw in enumerate(T):
+        m_tot = sum(c[1][w] for c in cols)
+        phis, dims = [], []
+        for f in range(3):
+            N = sizes[f]
+            S = torch.empty((m_tot, N), dtype=torch.float64, device="cuda")
+            off = 0
+            for tr, (first, ncol) in zip(trajs, cols):
+                snaps = tr["snaps"][f]
+                os_ = tr["y0"][f]
+                lib._check(so.lh_snapshot_deviation(lib.ptr(snaps[first[w]:first[w] + ncol[w]]) if ncol[w] else
+                                                    lib.ptr(snaps), N, ncol[w], N, lib.ptr(os_),
+                                                    C.c_void_p(S.data_ptr() + 8 * off * N), N, stream))
+                off += ncol[w]
+            nf = n_fixed[f] if n_fixed else 0
+            if verbose:
+                print(f"[offline] window {w} field {f}: POD of {N} x {m_tot}", flush=True)
+            Phi, _, n = lib.rom_build_basis(S, energy_frac=energy_frac, n_fixed=nf,
+                                            n_max=min(n_max, lib.LH_NMAX, m_tot))
+            phis.append(Phi.contiguous())
+            dims.append(n)
+            del S
+        PF1 = torch.empty_like(phis[1])
+        PFtv = torch.empty_like(phis[2])
+        for k in range(dims[1]):
+            lib._check(so.lh_mass_apply_v(P.h, lib.ptr(phis[1][k]), lib.ptr(PF1[k]), stream))
+        for k in range(dims[2]):
+            lib._check(so.lh_mass_apply_e(P.h, lib.ptr(phis[2][k]), lib.ptr(PFtv[k]), stream))
+        z1, a1 = lib.rom_sample_deim(PF1, int(round(lam[0] * dims[1])))
+        z2, a2 = lib.rom_sample_deim(PFtv, int(round(lam[1] * dims[2])))
+        windows.append(dict(t_end=Tw, phi=phis, os=list(online_offsets), z1=z1, z2=z2, a1=a1, a2=a2))
+    return dict(t_final=t_final if t_final is not None else T[-1], windows=windows)

@@ -175,3 +175,43 @@ def test_rom_step_in_pieces_equals_one_call(gpu_lib, tg):
     P2, G2 = _gpu_rom(wl, [(rom, wl.t_final)], [y0], dt0=wl.fixed_dt)
     G2.step(flags=lib.LH_FIXED_DT)
     assert torch.equal(G.state, G2.state)
+
+
+@pytest.mark.parametrize("per_wg", ["1", "3"])
+def test_rom_multi_workgroup_instance_matches_oracle(gpu_lib, sedov_windows, tg, monkeypatch, per_wg):
+    """One instance split over several workgroups (per-instance barriers, LDS-resident tiles)."""
+    from paper_2104_11404_amd import lib
+    monkeypatch.setenv("LAGROM_ELEMS_PER_WG", per_wg)
+    # adaptive steps, three windows
+    wl, op, tr, y0, rom = sedov_windows
+    run = R.run_rom(op, rom, y0, wl.t_final)
+    P, G = _gpu_rom(wl, [(rom, wl.t_final)], [y0])
+    g = lib._I32()
+    lib._check(lib.load().rom_workgroups_per_instance(G.h, lib.C.byref(g)))
+    n_el = max(len(w.elems) for w in rom.windows)
+    print(f"[case] rom multi-workgroup sedov per_wg={per_wg} G={g.value} max sampled elements={n_el}", flush=True)
+    assert g.value == -(-n_el // int(per_wg)) and g.value > 1
+    G.step()
+    st = G.states()[0]
+    assert st.status == 0 and st.done == 1
+    assert st.n_steps == len(run.dt) and st.n_rejected == run.rejections and st.w == run.w
+    for a, b in zip(G.coords(0), run.yhat):
+        assert rel(a, b) < 1e-9
+    P2, G2 = _gpu_rom(wl, [(rom, wl.t_final)], [y0])
+    G2.step()
+    assert torch.equal(G.state, G2.state)
+    # fixed steps, 22 sampled elements, FP64 and FP32 lift
+    wl, op, tr, y0 = tg
+    rom = R.build_rom(op, [tr], [y0], [wl.t_final], n_fixed=wl.n_fixed, lam=wl.lam)
+    run = R.run_rom(op, rom, y0, wl.t_final, fixed_dt=wl.fixed_dt)
+    P3, G3 = _gpu_rom(wl, [(rom, wl.t_final)], [y0], dt0=wl.fixed_dt)
+    lib._check(lib.load().rom_workgroups_per_instance(G3.h, lib.C.byref(g)))
+    print(f"[case] rom multi-workgroup tg per_wg={per_wg} G={g.value}", flush=True)
+    assert g.value > 1
+    G3.step(flags=lib.LH_FIXED_DT)
+    for a, b in zip(G3.coords(0), run.yhat):
+        assert rel(a, b) < 1e-10
+    P4, G4 = _gpu_rom(wl, [(rom, wl.t_final)], [y0], dt0=wl.fixed_dt)
+    G4.step(flags=lib.LH_FIXED_DT | lib.LH_FP32_LIFT)
+    for a, b in zip(G4.lift(0), R.final_lift(rom, run)):
+        assert rel(a.cpu().numpy(), b) < 1e-5
