@@ -100,6 +100,37 @@ def cpu_baseline(wl, dims, evals_per_step, seconds: float = 12.0, n_pre: int = 2
                         f"of the full workload"))
 
 
+def fom_force_rate(lib, wl, reps: int = 20, seed: int = 7):
+    """Full-mesh fom_force (F.1, F^T.v and tau, artificial viscosity on) on a perturbed state.
+
+    Algorithmic bytes per call: read x, v, v_c (3 N_V) and e (N_E), write F.1 (N_V) and
+    F^T.v (N_E), FP64.
+    """
+    import torch
+
+    import workloads as Wl
+
+    P = lib.Problem.from_workload(wl)
+    x, v, e, vc = (torch.from_numpy(a).cuda() for a in Wl.random_state(wl, seed))
+    F1, Ftv, tau = P.fom_force(x, v, e, vc)
+    for _ in range(3):
+        P.fom_force(x, v, e, vc, F1=F1, Ftv=Ftv, tau=tau)
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        P.fom_force(x, v, e, vc, F1=F1, Ftv=Ftv, tau=tau)
+    b.record(stream)
+    torch.cuda.synchronize()
+    P.status()
+    s = a.elapsed_time(b) / 1e3 / reps
+    nbytes = 8 * (4 * P.NV + 2 * P.NE)
+    return {"mesh": list(wl.nel[: wl.dim]), "elements": wl.n_elem, "avg_us_per_call": s * 1e6,
+            "elements_per_s": wl.n_elem / s, "algorithmic_bytes": nbytes, "achieved_GBs": nbytes / s / 1e9,
+            "hbm_frac": nbytes / s / 1e9 / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +138,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp32", action="store_true", help="FP32 lift/projection (FP64 force and reduced state)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-force", action="store_true", help="skip the full-mesh fom_force measurement")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, help="also run a plain device copy of this many MiB")
     args = ap.parse_args()
@@ -227,6 +259,10 @@ def main():
     }
     if calib:
         out["copy_calibration"] = calib
+    if not args.no_force:
+        out["fom_force"] = [fom_force_rate(lib, w) for w in (wl, Wl.sedov2d(512), Wl.sedov3d(32))]
+        print(f"[bench] fom_force {[(r['mesh'], round(r['avg_us_per_call'], 1)) for r in out['fom_force']]}",
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         med = [int(sorted(d[f] for d in dims)[len(dims) // 2]) for f in range(3)]
         out["cpu_baseline"] = cpu_baseline(wl, med, st.n_force_evals / st.n_steps, args.cpu_seconds)

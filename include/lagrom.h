@@ -249,8 +249,12 @@ enum { LH_FP32_LIFT = 1, LH_REPLAY_DT = 2, LH_FIXED_DT = 4 };
 /* Build the online data of n_inst instances sharing one problem: element
  * closure of the sampled rows, element-local tiles of the sampled basis
  * rows and offsets, B_xv = Phi_x^T Phi_v, b_x = Phi_x^T v_os and the window
- * transition maps of eq. ic-tw.  Allocates device memory (not a hot call).
- * Synchronises. */
+ * transition maps of eq. ic-tw.  Also fixes G, the workgroups that advance
+ * each instance (1 <= G <= 64, at most 8 sampled elements per workgroup, no
+ * more than fit in LDS and no more than the compute units allow for n_inst
+ * co-resident instances; the environment variable LAGROM_ELEMS_PER_WG, read
+ * here, overrides the elements per workgroup for tuning).  Allocates device
+ * memory (not a hot call).  Synchronises. */
 int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst, lh_rom** out,
                hipStream_t stream);
 void rom_destroy(lh_rom* r);
@@ -267,8 +271,12 @@ int rom_init_state(const lh_rom* r, const lh_instance_desc* inst, const double* 
 /* Advance every instance with the RK2-average hyper-reduced scheme
  * (eq. RK2-avg-rom-hr) and the step control of Sec. 2.2.3, for at most
  * max_steps accepted steps or until its t_final.  One persistent launch:
- * each instance is advanced by one workgroup, switching windows on device
- * (eq. ic-tw).  flags: LH_REPLAY_DT uses dt_replay (dev, n_replay steps,
+ * each instance is advanced by G workgroups (rom_workgroups_per_instance)
+ * that split its sampled elements and exchange per-stage partial reduced
+ * forces through device memory, combined in a fixed order so that results
+ * are bitwise reproducible; windows switch on device (eq. ic-tw).  With
+ * G > 1 the launch is cooperative (every workgroup resident); a partner that
+ * does not arrive within a bounded wait sets LH_FLAG_TIMEOUT.  flags: LH_REPLAY_DT uses dt_replay (dev, n_replay steps,
  * shared by all instances), LH_FIXED_DT keeps state.dt fixed,
  * LH_FP32_LIFT lifts and projects in FP32 (FP64 accumulation of the
  * reduced state).  Asynchronous. */

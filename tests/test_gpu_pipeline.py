@@ -9,7 +9,7 @@ import workloads as W
 from oracle import fom as F
 from oracle import rom as R
 from oracle.problems import initial_state
-from oracle.windows import window_columns, windows_by_samples
+from oracle.windows import windows_by_samples
 from tests.oracle_adapter import oracle_problem
 
 pytestmark = pytest.mark.gpu
@@ -18,25 +18,6 @@ pytestmark = pytest.mark.gpu
 def rel(a, b):
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0))
-
-
-def test_window_logic_matches_oracle(gpu_lib):
-    from paper_2104_11404_amd import pipeline
-    ta = list(np.cumsum([0.0] + list(np.random.default_rng(0).uniform(0.5, 1.5, 37))))
-    tb = list(np.cumsum([0.0] + list(np.random.default_rng(1).uniform(0.5, 1.5, 41))))
-    tb = [x * ta[-1] / tb[-1] for x in tb]
-    for ns in (4, 6, 10, 22):
-        T = pipeline.windows_by_samples([ta, tb], ns)
-        assert T == windows_by_samples([ta, tb], ns)
-
-        class Tr:
-            t = ta
-        first, ncol = pipeline.window_columns(ta, T)
-        cols = window_columns(Tr, T)
-        for w, c in enumerate(cols):
-            assert ncol[w] == len(c)
-            idx = [2 * (i - 1) + 1 if k == "init" else i for k, i in c]
-            assert idx == list(range(first[w], first[w] + ncol[w]))
 
 
 def test_mass_apply_matches_oracle(gpu_lib):
