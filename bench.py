@@ -26,6 +26,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -131,6 +133,66 @@ def fom_force_rate(lib, wl, reps: int = 20, seed: int = 7):
             "hbm_frac": nbytes / s / 1e9 / HBM_PEAK_GBS}
 
 
+def batched_gresho(lib, pipeline, n_inst: int = 256, reps: int = 3, lam=None):
+    """256 parametrised 2D Gresho ROM instances (48 x 48, t = 0.1) in one persistent launch.
+
+    Each instance has its own bases from its own GPU FOM run (uneven POD dimensions 8-40 capped by
+    the snapshots per window, 1-8 uniform physical windows, lambda = 8).  Timed: init + one launch
+    advancing every instance to t = 0.1, FP64 and FP32 lift/projection; errors are per-field
+    relative errors of each instance's lifted final state against its FOM, maximum over instances.
+    """
+    import torch
+
+    import workloads as Wl
+
+    wl = Wl.gresho_batch(n_inst)
+    lam = wl.lam if lam is None else tuple(lam)
+    t0 = time.perf_counter()
+    insts, y0s, finals, fom_steps = pipeline.build_batch(wl, lam=lam)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    P = lib.Problem.from_workload(wl)
+    rom = lib.Rom(P, insts)
+    y0 = [torch.cat([y[f] for y in y0s]) for f in range(3)]
+    g = lib._I32()
+    lib._check(lib.load().rom_workgroups_per_instance(rom.h, lib.C.byref(g)))
+    out = {"workload": f"gresho2d_48x48_t0.1_batch{n_inst}_uneven_dims_windows_lambda{lam[0]:g}", "instances": n_inst,
+           "fom_steps_total": int(sum(fom_steps)), "setup_s": t_setup, "workgroups_per_instance": g.value,
+           "windows_total": int(sum(len(i["windows"]) for i in insts))}
+    stream = torch.cuda.current_stream()
+    for name, flags in (("f64", 0), ("f32_lift", lib.LH_FP32_LIFT)):
+        rom.init_state(*y0)
+        rom.step(flags=flags)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            rom.init_state(*y0)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            rom.step(flags=flags)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        sts = rom.states()
+        bad = [i for i, st in enumerate(sts) if st.status != 0 or st.done != 1]
+        steps = sum(st.n_steps for st in sts)
+        evals = sum(st.n_force_evals for st in sts)
+        ok = [i for i in range(n_inst) if i not in bad]
+        errs = np.zeros((len(ok), 3))
+        for r, i in enumerate(ok):
+            for f, (x, y) in enumerate(zip(rom.lift(i), finals[i])):
+                errs[r, f] = float(torch.linalg.norm(x - y) / torch.linalg.norm(y))
+        t = sorted(ms)[len(ms) // 2] / 1e3
+        out[name] = {"ms_per_launch": t * 1e3, "rom_steps_per_launch": int(steps), "rom_steps_per_s": steps / t,
+                     "sampled_force_evals_per_s": evals / t,
+                     "failed_instances": [dict(instance=i, status=sts[i].status, t=sts[i].t, **wl.params[i])
+                                          for i in bad],
+                     "max_rel_error_vs_fom_completed": dict(zip("xve", errs.max(axis=0).tolist())),
+                     "median_rel_error_vs_fom_completed": dict(zip("xve", np.median(errs, axis=0).tolist()))}
+        print(f"[bench] batched {name}: {t * 1e3:.2f} ms, {steps / t:.0f} ROM steps/s", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +201,7 @@ def main():
     ap.add_argument("--fp32", action="store_true", help="FP32 lift/projection (FP64 force and reduced state)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-force", action="store_true", help="skip the full-mesh fom_force measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-instance batched Gresho measurement")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, help="also run a plain device copy of this many MiB")
     args = ap.parse_args()
@@ -263,6 +326,8 @@ def main():
         out["fom_force"] = [fom_force_rate(lib, w) for w in (wl, Wl.sedov2d(512), Wl.sedov3d(32))]
         print(f"[bench] fom_force {[(r['mesh'], round(r['avg_us_per_call'], 1)) for r in out['fom_force']]}",
               file=sys.stderr, flush=True)
+    if not args.no_batch:
+        out["batched"] = batched_gresho(lib, pipeline)
     if not args.no_cpu_baseline:
         med = [int(sorted(d[f] for d in dims)[len(dims) // 2]) for f in range(3)]
         out["cpu_baseline"] = cpu_baseline(wl, med, st.n_force_evals / st.n_steps, args.cpu_seconds)

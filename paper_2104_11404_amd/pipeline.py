@@ -94,3 +94,31 @@ def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_f
         z2, a2 = lib.rom_sample_deim(PFtv, int(round(lam[1] * dims[2])))
         windows.append(dict(t_end=Tw, phi=phis, os=list(online_offsets), z1=z1, z2=z2, a1=a1, a2=a2))
     return dict(t_final=t_final if t_final is not None else T[-1], windows=windows)
+
+
+def build_batch(wl, lam=(2.0, 2.0), energy_frac=0.9999, verbose=False):
+    """Offline phase of a batch of parametrised instances, each from its own GPU FOM run.
+
+    wl.params holds one dict per instance: amp and p_bg (initial condition), n (fixed POD
+    dimension for x, v and e, capped by each window's snapshot count) and n_windows (uniform
+    physical windows, Sec. 4.4).  Returns (instances, y0 list, FOM final state list, FOM step
+    counts); the instance dicts feed lib.Rom, which shares one problem (mesh and material) between
+    all instances since the parameters enter only through the initial state.
+    """
+    insts, y0s, finals, steps = [], [], [], []
+    for i, prm in enumerate(wl.params):
+        Pi = lib.Problem.from_workload(wl, amp=prm["amp"], p_bg=prm["p_bg"])
+        traj = fom_trajectory(Pi, wl.t_final)
+        T = windows_physical(wl.t_final, prm["n_windows"])
+        n = int(prm["n"])
+        inst = build_offline(Pi, [traj], T, traj["y0"], energy_frac=energy_frac, n_fixed=(n, n, n), lam=lam,
+                             t_final=wl.t_final)
+        insts.append(inst)
+        y0s.append(traj["y0"])
+        finals.append(traj["y_final"])
+        steps.append(traj["n_steps"])
+        if verbose:
+            dims = [[int(p.shape[0]) for p in wd["phi"]] for wd in inst["windows"]]
+            print(f"[batch] instance {i}: {traj['n_steps']} FOM steps, windows {len(T)}, dims {dims}", flush=True)
+        del traj
+    return insts, y0s, finals, steps
