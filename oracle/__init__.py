@@ -24,6 +24,10 @@ Modules, in the order of the paper's method:
                   (Sec. 3.6, 3.3).
 * ``rom``      -- SNS hyper-reduced ROM with RK2-average and windows
                   (eq. RK2-avg-rom-hr, eq. rom-hr-sns, eq. ic-tw, eq. relerrors).
+* ``mlp``      -- the MLP surrogate of the reduced force coefficients (not
+                  in the paper): bfloat16-operand forward and backward, Adam,
+                  training targets from the DEIM chain, and the surrogate ROM
+                  run with DEIM audits and fallback.
 
 Everything is float64 NumPy/SciPy.
 """
