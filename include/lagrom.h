@@ -240,11 +240,19 @@ typedef struct {
     int32_t n_force_evals;/* sampled-element force evaluations (elements x stages) */
     int32_t done;
     double yhat[3][LH_NMAX]; /* x^, v^, e^ of the current window                   */
+    /* surrogate bookkeeping (rom_attach_surrogate) */
+    double tau_est;          /* step estimate of the last audit                       */
+    int32_t since;           /* accepted steps since entering the window              */
+    int32_t fallen;          /* the current window has fallen back to DEIM            */
+    int32_t n_audits;
+    int32_t n_surrogate_steps;
+    int32_t n_fallbacks;     /* windows that fell back                                */
+    int32_t pad_;
 } lh_rom_state;
 
 typedef struct lh_rom lh_rom;
 
-enum { LH_FP32_LIFT = 1, LH_REPLAY_DT = 2, LH_FIXED_DT = 4 };
+enum { LH_FP32_LIFT = 1, LH_REPLAY_DT = 2, LH_FIXED_DT = 4, LH_SURROGATE = 8 };
 
 /* Build the online data of n_inst instances sharing one problem: element
  * closure of the sampled rows, element-local tiles of the sampled basis
@@ -334,6 +342,78 @@ int lh_windows_by_samples(int32_t n_params, const double* const* t_lists, const 
  * states of every step up to the first one reaching T_w.  Host only. */
 int lh_window_columns(const double* t, int32_t n_steps, const double* T, int32_t n_windows, int32_t* first_col,
                       int32_t* n_cols);
+
+/* -------------------------------------------------------- MLP surrogate */
+
+/* A fully connected network that stands in for the sampled lift, force and
+ * projection of one window (an addition to the method; the paper has no
+ * learned component): inputs [x^, v^, e^, t], outputs the reduced force
+ * coefficients [F^1 (n_v), g (n_e), H (n_e x n_v, row-major)] with
+ * F^tv = g + H v^_c for a contraction velocity v^_c, which is exact for the
+ * DEIM chain of eq. rom-hr-sns because F^T v_c is linear in v_c.
+ *   z_0 = (x - mu_in) / s_in;  z_{l+1} = act(r(z_l) r(W_l) + b_l);  y = mu_out + s_out z_L,
+ * act = tanh on hidden layers, identity on the last; r() rounds to bfloat16
+ * (nearest even); products accumulate in FP32.  W_l is (sizes[l] x
+ * sizes[l+1]) row-major.  Loss: mean squared error of the normalised
+ * outputs; optimiser: Adam (beta 0.9, 0.999, eps 1e-8, bias-corrected) on
+ * FP32 master weights with bfloat16 copies refreshed after every step. */
+#define LH_MLP_MAX_LAYERS 8
+typedef struct {
+    int32_t n_layers;                      /* weight layers L, 1..LH_MLP_MAX_LAYERS        */
+    int32_t sizes[LH_MLP_MAX_LAYERS + 1];  /* d_in, hidden widths, d_out; each 1..8192     */
+} lh_mlp_desc;
+typedef struct lh_mlp lh_mlp;
+
+/* Allocates parameters, optimiser state and activations for batches of up
+ * to max_batch rows (device memory; not a hot call).  Parameters start at
+ * zero and the normalisation at mu = 0, s = 1. */
+int mlp_create(const lh_mlp_desc* d, int32_t max_batch, lh_mlp** out);
+void mlp_destroy(lh_mlp* m);
+
+/* Set parameters from FP64 device arrays: W[l] (sizes[l] x sizes[l+1],
+ * row-major), b[l] (sizes[l+1]), the input and output normalisation (any
+ * of the four may be NULL to keep the current one).  Resets Adam. */
+int mlp_set_params(lh_mlp* m, const double* const* W, const double* const* b, const double* mu_in,
+                   const double* s_in, const double* mu_out, const double* s_out, hipStream_t stream);
+/* Copy the FP32 master parameters into W[l], b[l] (device, unpadded). */
+int mlp_get_params(const lh_mlp* m, float* const* W, float* const* b, hipStream_t stream);
+
+/* Y (dev, B x d_out FP64, may be NULL) = network(X) for X (dev, B x d_in
+ * FP64), 1 <= B <= max_batch.  trace (host array of L + 1 device pointers,
+ * or NULL) receives z_0 .. z_L in FP32 (B x sizes[l] each), i.e. every
+ * layer's input before its bfloat16 rounding and the normalised output. */
+int mlp_forward(lh_mlp* m, const double* X, int32_t B, double* Y, float* const* trace, hipStream_t stream);
+
+/* Gradients of the loss on (X, T) (dev, B x d_in and B x d_out FP64) into
+ * gW[l] (sizes[l] x sizes[l+1]) and gb[l] (device FP32); *loss (dev, may be
+ * NULL) receives the loss before the step. */
+int mlp_gradients(lh_mlp* m, const double* X, const double* T, int32_t B, float* const* gW, float* const* gb,
+                  float* loss, hipStream_t stream);
+/* One Adam step with learning rate lr on the minibatch (X, T). */
+int mlp_train_step(lh_mlp* m, const double* X, const double* T, int32_t B, double lr, float* loss,
+                   hipStream_t stream);
+
+/* Training targets of window w of instance inst: for each of the B rows of
+ * yhat (dev, B x (n_x + n_v + n_e) FP64, coefficients in window w's bases)
+ * the DEIM chain's [F^1, g, H] at the lifted state (dev, B x (n_v + n_e +
+ * n_e n_v) FP64): F^1 = A1 (F.1)_Z1, g = A2 (F^T v_os)_Z2, column k of H =
+ * A2 (F^T Phi_v e_k)_Z2, on the sampled elements (eq. rom-hr-sns), with the
+ * same kernels and reduction order as rom_step; a row whose lifted state is
+ * tangled or not finite reads NaN.  Allocates scratch and
+ * synchronises (offline call). */
+int rom_surrogate_targets(const lh_rom* r, int32_t inst, int32_t w, const double* yhat, int32_t B, double* T,
+                          hipStream_t stream);
+
+/* Attach network m (sizes[0] = n_x + n_v + n_e + 1, sizes[L] = n_v + n_e +
+ * n_e n_v of that window) to window w of instance inst, used by rom_step
+ * when LH_SURROGATE is set (m = NULL detaches).  In such a window the first
+ * step and then every audit_every-th accepted step is an audit: it is taken
+ * with the DEIM chain, sets the step estimate tau used by the step control
+ * until the next audit, and compares the network's F^1 and F^tv at its first
+ * stage with the DEIM chain's; a relative discrepancy above tol makes the
+ * rest of the window use the DEIM chain (fallback).  m must outlive r's
+ * use.  Not a hot call. */
+int rom_attach_surrogate(lh_rom* r, int32_t inst, int32_t w, const lh_mlp* m, int32_t audit_every, double tol);
 
 /* ---------------------------------------------------------------- misc */
 

@@ -278,8 +278,11 @@ def audit(op: F.Operator, win: R.WindowROM, net: MLP, yhat, t, dt, r=bf16):
 
 
 def run_surrogate(op: F.Operator, rom: R.ROM, nets: dict, y0: tuple, t_final: float, audit_every: int,
-                  tol: float, r=bf16, max_steps=10**7) -> SurrogateRun:
-    """Online phase with the network in the windows of ``nets`` ({window: MLP}), DEIM elsewhere."""
+                  tol: float, r=bf16, max_steps=10**7, fixed_dt=None) -> SurrogateRun:
+    """Online phase with the network in the windows of ``nets`` ({window: MLP}), DEIM elsewhere.
+
+    With ``fixed_dt`` every step has that size and nothing is rejected (as ``rom.run_rom``).
+    """
     w = 0
     yhat = R.initial_coords(rom, y0)
     t = 0.0
@@ -288,13 +291,13 @@ def run_surrogate(op: F.Operator, rom: R.ROM, nets: dict, y0: tuple, t_final: fl
     st = F.stress(op, R.lift_rows(win, 0, yhat[0], win.rows_k, op.mesh.NV),
                   R.lift_rows(win, 1, yhat[1], win.rows_k, op.mesh.NV),
                   R.lift_rows(win, 2, yhat[2], win.rows_t, op.mesh.NE), elems=win.elems)
-    dt = F.BETA1 * float(np.min(st.tau))
+    dt = F.BETA1 * float(np.min(st.tau)) if fixed_dt is None else fixed_dt
     since = 0  # accepted steps since the last audit in this window
     fallen = False
     tau_est = np.inf
     n = 0
     while F.not_done(t, t_final) and n < max_steps:
-        h = F.final_step_clip(t, t_final, dt)
+        h = fixed_dt if fixed_dt is not None else F.final_step_clip(t, t_final, dt)
         net = nets.get(w)
         win = rom.windows[w]
         if net is None or fallen:
@@ -309,11 +312,12 @@ def run_surrogate(op: F.Operator, rom: R.ROM, nets: dict, y0: tuple, t_final: fl
         else:
             new = surrogate_step(win, net, *yhat, t, h, r)
             tau = tau_est
-        if h >= tau:
-            dt = F.BETA1 * h
-            run.rejections += 1
-            continue
-        dt = F.BETA2 * h if h <= F.GAMMA_DT * tau else h
+        if fixed_dt is None:
+            if h >= tau:
+                dt = F.BETA1 * h
+                run.rejections += 1
+                continue
+            dt = F.BETA2 * h if h <= F.GAMMA_DT * tau else h
         if net is not None and not fallen and since % audit_every != 0:
             run.surrogate_steps += 1
         yhat = new

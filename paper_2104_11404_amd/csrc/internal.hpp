@@ -51,6 +51,43 @@ constexpr double ORDER_K = 2.0;
 
 }  // namespace lh
 
+namespace lh {
+
+// Device view of a network (bfloat16 weights with rows padded to a multiple
+// of 4 entries, FP32 biases, FP64 normalisation), read by the ROM kernels.
+struct MlpDev {
+    int L;
+    int sizes[LH_MLP_MAX_LAYERS + 1];
+    int npad[LH_MLP_MAX_LAYERS + 1];
+    const uint16_t* W[LH_MLP_MAX_LAYERS];  // [sizes[l]][npad[l + 1]]
+    const float* b[LH_MLP_MAX_LAYERS];     // [npad[l + 1]]
+    const double* mu_in;
+    const double* s_in;
+    const double* mu_out;
+    const double* s_out;
+};
+
+// The view of a network created by mlp_create.
+MlpDev mlp_view(const lh_mlp* m);
+
+// Round to the nearest bfloat16 (ties to even); NaN stays a quiet NaN.
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x0040u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__host__ __device__ inline float bf16_to_f32(uint16_t h) {
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+}
+
+}  // namespace lh
+
 // Host-side problem object.
 struct lh_problem {
     lh_problem_desc desc;

@@ -1,0 +1,551 @@
+// MLP surrogate of the reduced force coefficients: bfloat16 training and
+// inference kernels with FP32 accumulation (an addition to the method of the
+// paper, which has no learned component).
+//
+// Layout: activations are row-major [batch][features] with rows padded to a
+// multiple of 4 entries; W_l is row-major [fan_in][fan_out padded].  The
+// products are one tiled MFMA kernel (v_mfma_f32_16x16x16_bf16): a 256-thread
+// workgroup computes a 64 x 64 tile of C = A B, each wave 16 rows, with
+// 64 x 16 slices of A and B staged in LDS per step over K.  A and B are
+// addressed through two strides each, so the backward products use the same
+// kernel on transposed views:
+//   forward   Z_{l+1} = act(r(Z_l) r(W_l) + b_l)
+//   backward  grad W_l = r(Z_l)^T r(D_{l+1}),  grad b_l = column sums of D_{l+1},
+//             D_l = (r(D_{l+1}) r(W_l)^T) * (1 - Z_l^2)
+// with D_L = 2 (Z_L - T~) / (B d_out).  Column sums run over rows in order,
+// so every result is deterministic.
+#include <algorithm>
+#include <vector>
+
+#include "internal.hpp"
+
+struct lh_mlp {
+    int L = 0;
+    int sizes[LH_MLP_MAX_LAYERS + 1] = {};
+    int npad[LH_MLP_MAX_LAYERS + 1] = {};
+    int max_batch = 0;
+    int step = 0;  // Adam steps taken
+    std::vector<void*> allocs;
+    float* W32[LH_MLP_MAX_LAYERS] = {};
+    uint16_t* Wb[LH_MLP_MAX_LAYERS] = {};
+    float* b32[LH_MLP_MAX_LAYERS] = {};
+    float* mW[LH_MLP_MAX_LAYERS] = {};
+    float* vW[LH_MLP_MAX_LAYERS] = {};
+    float* mb[LH_MLP_MAX_LAYERS] = {};
+    float* vb[LH_MLP_MAX_LAYERS] = {};
+    float* gW[LH_MLP_MAX_LAYERS] = {};
+    float* gb[LH_MLP_MAX_LAYERS] = {};
+    double *mu_in = nullptr, *s_in = nullptr, *mu_out = nullptr, *s_out = nullptr;
+    float* act32[LH_MLP_MAX_LAYERS + 1] = {};     // Z_l, [max_batch][npad[l]]
+    uint16_t* actb[LH_MLP_MAX_LAYERS + 1] = {};   // r(Z_l)
+    float* del32[LH_MLP_MAX_LAYERS + 1] = {};     // D_l
+    uint16_t* delb[LH_MLP_MAX_LAYERS + 1] = {};   // r(D_l)
+    float* loss_part = nullptr;
+    int n_loss_part = 0;
+};
+
+namespace lh {
+namespace mlp {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int BLK = 256;
+constexpr int TM = 64, TN = 64, TK = 16;
+
+enum { ACT_NONE = 0, ACT_TANH = 1, ACT_DTANH = 2 };
+
+struct GemmArgs {
+    int M, N, K;
+    const uint16_t* A;
+    int64_t sam, sak;  // A(m, k) = A[m * sam + k * sak]
+    const uint16_t* B;
+    int64_t sbk, sbn;  // B(k, n) = B[k * sbk + n * sbn]
+    const float* bias;  // [N] or null
+    int act;
+    const float* aux;  // ACT_DTANH: multiply by 1 - aux(m, n)^2
+    int64_t ldaux;
+    float* out32;
+    int64_t ldo;
+    uint16_t* outb;
+    int64_t ldob;
+};
+
+__global__ void __launch_bounds__(BLK) gemm_bf16_kernel(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[TM][TK];  // [m][k]
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][TK];  // [n][k]
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    f4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+    const int r = tid >> 2, kk = (tid & 3) * 4;
+    for (int k0 = 0; k0 < g.K; k0 += TK) {
+        const int m = m0 + r, n = n0 + r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = k0 + kk + i;
+            As[r][kk + i] = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : (uint16_t)0;
+            Bs[r][kk + i] = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : (uint16_t)0;
+        }
+        __syncthreads();
+        const s4 a = *reinterpret_cast<const s4*>(&As[wave * 16 + (lane & 15)][(lane >> 4) * 4]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const s4 b = *reinterpret_cast<const s4*>(&Bs[j * 16 + (lane & 15)][(lane >> 4) * 4]);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // lane holds C(4 (lane / 16) + i, lane % 16) of each 16 x 16 tile
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int n = n0 + j * 16 + (lane & 15);
+        if (n >= g.N) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = m0 + wave * 16 + (lane >> 4) * 4 + i;
+            if (m >= g.M) continue;
+            float v = acc[j][i];
+            if (g.bias) v += g.bias[n];
+            if (g.act == ACT_TANH) {
+                v = tanhf(v);
+            } else if (g.act == ACT_DTANH) {
+                const float a = g.aux[(int64_t)m * g.ldaux + n];
+                v *= 1.0f - a * a;
+            }
+            if (g.out32) g.out32[(int64_t)m * g.ldo + n] = v;
+            if (g.outb) g.outb[(int64_t)m * g.ldob + n] = f32_to_bf16(v);
+        }
+    }
+}
+
+// Z_0 = (X - mu) / s (FP64 arithmetic, then FP32 and its bfloat16 rounding); padding columns zero.
+__global__ void norm_in_kernel(const double* X, int B, int d, int ld, const double* mu, const double* s, float* z,
+                               uint16_t* zb) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)B * ld) return;
+    const int i = (int)(t / ld), j = (int)(t % ld);
+    const float v = j < d ? (float)((X[(int64_t)i * d + j] - mu[j]) / s[j]) : 0.0f;
+    z[t] = v;
+    zb[t] = f32_to_bf16(v);
+}
+
+// Y = mu_out + s_out Z_L (FP64).
+__global__ void denorm_kernel(const float* z, int B, int d, int ld, const double* mu, const double* s, double* Y) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)B * d) return;
+    const int i = (int)(t / d), j = (int)(t % d);
+    Y[t] = mu[j] + s[j] * (double)z[(int64_t)i * ld + j];
+}
+
+// D_L = 2 (Z_L - (T - mu) / s) / (B d) and per-block partial sums of the squared error.
+__global__ void __launch_bounds__(BLK) loss_grad_kernel(const float* z, const double* T, int B, int d, int ld,
+                                                        const double* mu, const double* s, float* dz, uint16_t* dzb,
+                                                        float* part) {
+    __shared__ float red[BLK];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float sq = 0.0f;
+    if (t < (int64_t)B * ld) {
+        const int i = (int)(t / ld), j = (int)(t % ld);
+        float g = 0.0f;
+        if (j < d) {
+            const float diff = z[t] - (float)((T[(int64_t)i * d + j] - mu[j]) / s[j]);
+            sq = diff * diff;
+            g = 2.0f * diff / ((float)B * (float)d);
+        }
+        dz[t] = g;
+        dzb[t] = f32_to_bf16(g);
+    }
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int w = BLK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(BLK) loss_reduce_kernel(const float* part, int n, float scale, float* out) {
+    __shared__ float red[BLK];
+    float a = 0.0f;
+    for (int i = threadIdx.x; i < n; i += BLK) a += part[i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = BLK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] * scale;
+}
+
+// gb[j] = sum over rows of D[i][j], rows in order.
+__global__ void colsum_kernel(const float* D, int B, int N, int ld, float* gb) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    float a = 0.0f;
+    for (int i = 0; i < B; ++i) a += D[(int64_t)i * ld + j];
+    gb[j] = a;
+}
+
+// Adam on n entries; refreshes the bfloat16 copy when wb is given.
+__global__ void adam_kernel(float* w, uint16_t* wb, float* m, float* v, const float* g, int64_t n, float lr,
+                            float c1, float c2) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const float gi = g[t];
+    const float mi = 0.9f * m[t] + 0.1f * gi;
+    const float vi = 0.999f * v[t] + 0.001f * gi * gi;
+    m[t] = mi;
+    v[t] = vi;
+    const float wi = w[t] - lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+    w[t] = wi;
+    if (wb) wb[t] = f32_to_bf16(wi);
+}
+
+// dst[r][c] (ld ldd) = src[r][c] (ld lds) as FP32 (+ bfloat16 copy); padding columns zero.
+__global__ void set_kernel(const double* src, int rows, int cols, int lds, float* dst, uint16_t* dstb, int ldd) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)rows * ldd) return;
+    const int r = (int)(t / ldd), c = (int)(t % ldd);
+    const float v = c < cols ? (float)src[(int64_t)r * lds + c] : 0.0f;
+    dst[t] = v;
+    if (dstb) dstb[t] = f32_to_bf16(v);
+}
+
+__global__ void unpad_kernel(const float* src, int rows, int cols, int lds, float* dst) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)rows * cols) return;
+    const int r = (int)(t / cols), c = (int)(t % cols);
+    dst[t] = src[(int64_t)r * lds + c];
+}
+
+__global__ void fill_f64_kernel(double* p, int64_t n, double v) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+__global__ void copy_f64_kernel(const double* s, double* d, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) d[t] = s[t];
+}
+
+__global__ void zero_f32_kernel(float* p, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0.0f;
+}
+
+__global__ void zero_u16_kernel(uint16_t* p, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0;
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + BLK - 1) / BLK); }
+
+int gemm(const GemmArgs& a, hipStream_t s) {
+    if (a.M <= 0 || a.N <= 0) return LH_OK;
+    dim3 grid((a.N + TN - 1) / TN, (a.M + TM - 1) / TM);
+    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(BLK), 0, s, a);
+    return launch_check("gemm_bf16_kernel");
+}
+
+template <class T>
+int alloc(lh_mlp* m, T** p, int64_t n) {
+    void* q = nullptr;
+    if (hipMalloc(&q, sizeof(T) * std::max<int64_t>(n, 1)) != hipSuccess) {
+        set_error("mlp_create: device allocation failed");
+        return LH_EDEVICE;
+    }
+    m->allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return LH_OK;
+}
+
+// Forward pass of B rows into act32 / actb (Z_0 .. Z_L).
+int forward(lh_mlp* m, const double* X, int B, hipStream_t s) {
+    const int ld0 = m->npad[0];
+    hipLaunchKernelGGL(norm_in_kernel, dim3(blocks((int64_t)B * ld0)), dim3(BLK), 0, s, X, B, m->sizes[0], ld0,
+                       m->mu_in, m->s_in, m->act32[0], m->actb[0]);
+    for (int l = 0; l < m->L; ++l) {
+        GemmArgs a{};
+        a.M = B;
+        a.N = m->sizes[l + 1];
+        a.K = m->sizes[l];
+        a.A = m->actb[l];
+        a.sam = m->npad[l];
+        a.sak = 1;
+        a.B = m->Wb[l];
+        a.sbk = m->npad[l + 1];
+        a.sbn = 1;
+        a.bias = m->b32[l];
+        a.act = l < m->L - 1 ? ACT_TANH : ACT_NONE;
+        a.out32 = m->act32[l + 1];
+        a.ldo = m->npad[l + 1];
+        a.outb = m->actb[l + 1];
+        a.ldob = m->npad[l + 1];
+        int rc = gemm(a, s);
+        if (rc) return rc;
+    }
+    return LH_OK;
+}
+
+// Loss gradient and backward pass into gW / gb (padded layouts); loss (dev) optional.
+int backward(lh_mlp* m, const double* T, int B, float* loss, hipStream_t s) {
+    const int L = m->L;
+    const int ldL = m->npad[L];
+    const int64_t nL = (int64_t)B * ldL;
+    const unsigned nb = blocks(nL);
+    if ((int)nb > m->n_loss_part) {
+        set_error("mlp: loss partial buffer too small");
+        return LH_EINVAL;
+    }
+    hipLaunchKernelGGL(loss_grad_kernel, dim3(nb), dim3(BLK), 0, s, m->act32[L], T, B, m->sizes[L], ldL, m->mu_out,
+                       m->s_out, m->del32[L], m->delb[L], m->loss_part);
+    if (loss)
+        hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(BLK), 0, s, m->loss_part, (int)nb,
+                           1.0f / ((float)B * (float)m->sizes[L]), loss);
+    for (int l = L - 1; l >= 0; --l) {
+        GemmArgs a{};  // grad W_l = r(Z_l)^T r(D_{l+1})
+        a.M = m->sizes[l];
+        a.N = m->sizes[l + 1];
+        a.K = B;
+        a.A = m->actb[l];
+        a.sam = 1;
+        a.sak = m->npad[l];
+        a.B = m->delb[l + 1];
+        a.sbk = m->npad[l + 1];
+        a.sbn = 1;
+        a.out32 = m->gW[l];
+        a.ldo = m->npad[l + 1];
+        int rc = gemm(a, s);
+        if (rc) return rc;
+        hipLaunchKernelGGL(colsum_kernel, dim3(blocks(m->sizes[l + 1])), dim3(BLK), 0, s, m->del32[l + 1], B,
+                           m->sizes[l + 1], m->npad[l + 1], m->gb[l]);
+        if (l > 0) {
+            GemmArgs d{};  // D_l = (r(D_{l+1}) r(W_l)^T) * (1 - Z_l^2)
+            d.M = B;
+            d.N = m->sizes[l];
+            d.K = m->sizes[l + 1];
+            d.A = m->delb[l + 1];
+            d.sam = m->npad[l + 1];
+            d.sak = 1;
+            d.B = m->Wb[l];
+            d.sbk = 1;
+            d.sbn = m->npad[l + 1];
+            d.act = ACT_DTANH;
+            d.aux = m->act32[l];
+            d.ldaux = m->npad[l];
+            d.out32 = m->del32[l];
+            d.ldo = m->npad[l];
+            d.outb = m->delb[l];
+            d.ldob = m->npad[l];
+            rc = gemm(d, s);
+            if (rc) return rc;
+        }
+    }
+    return launch_check("mlp backward");
+}
+
+}  // namespace mlp
+
+MlpDev mlp_view(const lh_mlp* m) {
+    MlpDev v{};
+    v.L = m->L;
+    for (int l = 0; l <= m->L; ++l) {
+        v.sizes[l] = m->sizes[l];
+        v.npad[l] = m->npad[l];
+    }
+    for (int l = 0; l < m->L; ++l) {
+        v.W[l] = m->Wb[l];
+        v.b[l] = m->b32[l];
+    }
+    v.mu_in = m->mu_in;
+    v.s_in = m->s_in;
+    v.mu_out = m->mu_out;
+    v.s_out = m->s_out;
+    return v;
+}
+
+}  // namespace lh
+
+extern "C" {
+
+int mlp_create(const lh_mlp_desc* d, int32_t max_batch, lh_mlp** out) {
+    using namespace lh;
+    using namespace lh::mlp;
+    LH_REQUIRE(d && out && max_batch >= 1, "mlp_create: bad arguments");
+    LH_REQUIRE(d->n_layers >= 1 && d->n_layers <= LH_MLP_MAX_LAYERS, "mlp_create: 1..8 layers");
+    for (int l = 0; l <= d->n_layers; ++l)
+        LH_REQUIRE(d->sizes[l] >= 1 && d->sizes[l] <= 8192, "mlp_create: layer sizes must be in 1..8192");
+    lh_mlp* m = new lh_mlp();
+    auto fail = [&](int rc) {
+        mlp_destroy(m);
+        return rc;
+    };
+    m->L = d->n_layers;
+    m->max_batch = max_batch;
+    for (int l = 0; l <= m->L; ++l) {
+        m->sizes[l] = d->sizes[l];
+        m->npad[l] = (d->sizes[l] + 3) / 4 * 4;
+    }
+    hipStream_t s = nullptr;
+    for (int l = 0; l < m->L; ++l) {
+        const int64_t nw = (int64_t)m->sizes[l] * m->npad[l + 1];
+        const int64_t nb = m->npad[l + 1];
+        int rc = alloc(m, &m->W32[l], nw);
+        if (!rc) rc = alloc(m, &m->Wb[l], nw);
+        if (!rc) rc = alloc(m, &m->mW[l], nw);
+        if (!rc) rc = alloc(m, &m->vW[l], nw);
+        if (!rc) rc = alloc(m, &m->gW[l], nw);
+        if (!rc) rc = alloc(m, &m->b32[l], nb);
+        if (!rc) rc = alloc(m, &m->mb[l], nb);
+        if (!rc) rc = alloc(m, &m->vb[l], nb);
+        if (!rc) rc = alloc(m, &m->gb[l], nb);
+        if (rc) return fail(rc);
+        for (float* p : {m->W32[l], m->mW[l], m->vW[l], m->gW[l]})
+            hipLaunchKernelGGL(zero_f32_kernel, dim3(blocks(nw)), dim3(BLK), 0, s, p, nw);
+        hipLaunchKernelGGL(zero_u16_kernel, dim3(blocks(nw)), dim3(BLK), 0, s, m->Wb[l], nw);
+        for (float* p : {m->b32[l], m->mb[l], m->vb[l], m->gb[l]})
+            hipLaunchKernelGGL(zero_f32_kernel, dim3(blocks(nb)), dim3(BLK), 0, s, p, nb);
+    }
+    for (int l = 0; l <= m->L; ++l) {
+        const int64_t n = (int64_t)max_batch * m->npad[l];
+        int rc = alloc(m, &m->act32[l], n);
+        if (!rc) rc = alloc(m, &m->actb[l], n);
+        if (!rc) rc = alloc(m, &m->del32[l], n);
+        if (!rc) rc = alloc(m, &m->delb[l], n);
+        if (rc) return fail(rc);
+    }
+    int rc = alloc(m, &m->mu_in, m->sizes[0]);
+    if (!rc) rc = alloc(m, &m->s_in, m->sizes[0]);
+    if (!rc) rc = alloc(m, &m->mu_out, m->sizes[m->L]);
+    if (!rc) rc = alloc(m, &m->s_out, m->sizes[m->L]);
+    m->n_loss_part = (int)blocks((int64_t)max_batch * m->npad[m->L]);
+    if (!rc) rc = alloc(m, &m->loss_part, m->n_loss_part);
+    if (rc) return fail(rc);
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(blocks(m->sizes[0])), dim3(BLK), 0, s, m->mu_in, (int64_t)m->sizes[0], 0.0);
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(blocks(m->sizes[0])), dim3(BLK), 0, s, m->s_in, (int64_t)m->sizes[0], 1.0);
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(blocks(m->sizes[m->L])), dim3(BLK), 0, s, m->mu_out,
+                       (int64_t)m->sizes[m->L], 0.0);
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(blocks(m->sizes[m->L])), dim3(BLK), 0, s, m->s_out,
+                       (int64_t)m->sizes[m->L], 1.0);
+    if (hipDeviceSynchronize() != hipSuccess) {
+        set_error("mlp_create: initialisation failed");
+        return fail(LH_EDEVICE);
+    }
+    *out = m;
+    return LH_OK;
+}
+
+void mlp_destroy(lh_mlp* m) {
+    if (!m) return;
+    for (void* p : m->allocs) (void)hipFree(p);
+    delete m;
+}
+
+int mlp_set_params(lh_mlp* m, const double* const* W, const double* const* b, const double* mu_in,
+                   const double* s_in, const double* mu_out, const double* s_out, hipStream_t s) {
+    using namespace lh;
+    using namespace lh::mlp;
+    LH_REQUIRE(m, "mlp_set_params: null network");
+    for (int l = 0; l < m->L; ++l) {
+        if (W && W[l]) {
+            const int64_t n = (int64_t)m->sizes[l] * m->npad[l + 1];
+            hipLaunchKernelGGL(set_kernel, dim3(blocks(n)), dim3(BLK), 0, s, W[l], m->sizes[l], m->sizes[l + 1],
+                               m->sizes[l + 1], m->W32[l], m->Wb[l], m->npad[l + 1]);
+        }
+        if (b && b[l])
+            hipLaunchKernelGGL(set_kernel, dim3(blocks(m->npad[l + 1])), dim3(BLK), 0, s, b[l], 1, m->sizes[l + 1],
+                               m->sizes[l + 1], m->b32[l], (uint16_t*)nullptr, m->npad[l + 1]);
+        const int64_t nw = (int64_t)m->sizes[l] * m->npad[l + 1];
+        for (float* p : {m->mW[l], m->vW[l]}) hipLaunchKernelGGL(zero_f32_kernel, dim3(blocks(nw)), dim3(BLK), 0, s, p, nw);
+        for (float* p : {m->mb[l], m->vb[l]})
+            hipLaunchKernelGGL(zero_f32_kernel, dim3(blocks(m->npad[l + 1])), dim3(BLK), 0, s, p,
+                               (int64_t)m->npad[l + 1]);
+    }
+    const int64_t di = m->sizes[0], dout = m->sizes[m->L];
+    if (mu_in) hipLaunchKernelGGL(copy_f64_kernel, dim3(blocks(di)), dim3(BLK), 0, s, mu_in, m->mu_in, di);
+    if (s_in) hipLaunchKernelGGL(copy_f64_kernel, dim3(blocks(di)), dim3(BLK), 0, s, s_in, m->s_in, di);
+    if (mu_out) hipLaunchKernelGGL(copy_f64_kernel, dim3(blocks(dout)), dim3(BLK), 0, s, mu_out, m->mu_out, dout);
+    if (s_out) hipLaunchKernelGGL(copy_f64_kernel, dim3(blocks(dout)), dim3(BLK), 0, s, s_out, m->s_out, dout);
+    m->step = 0;
+    return launch_check("mlp_set_params");
+}
+
+int mlp_get_params(const lh_mlp* m, float* const* W, float* const* b, hipStream_t s) {
+    using namespace lh;
+    using namespace lh::mlp;
+    LH_REQUIRE(m, "mlp_get_params: null network");
+    for (int l = 0; l < m->L; ++l) {
+        if (W && W[l]) {
+            const int64_t n = (int64_t)m->sizes[l] * m->sizes[l + 1];
+            hipLaunchKernelGGL(unpad_kernel, dim3(blocks(n)), dim3(BLK), 0, s, m->W32[l], m->sizes[l],
+                               m->sizes[l + 1], m->npad[l + 1], W[l]);
+        }
+        if (b && b[l])
+            hipLaunchKernelGGL(unpad_kernel, dim3(blocks(m->sizes[l + 1])), dim3(BLK), 0, s, m->b32[l], 1,
+                               m->sizes[l + 1], m->npad[l + 1], b[l]);
+    }
+    return launch_check("mlp_get_params");
+}
+
+int mlp_forward(lh_mlp* m, const double* X, int32_t B, double* Y, float* const* trace, hipStream_t s) {
+    using namespace lh;
+    using namespace lh::mlp;
+    LH_REQUIRE(m && X && B >= 1 && B <= m->max_batch, "mlp_forward: bad arguments (B must be 1..max_batch)");
+    int rc = forward(m, X, B, s);
+    if (rc) return rc;
+    if (Y)
+        hipLaunchKernelGGL(denorm_kernel, dim3(blocks((int64_t)B * m->sizes[m->L])), dim3(BLK), 0, s, m->act32[m->L],
+                           B, m->sizes[m->L], m->npad[m->L], m->mu_out, m->s_out, Y);
+    if (trace)
+        for (int l = 0; l <= m->L; ++l)
+            if (trace[l])
+                hipLaunchKernelGGL(unpad_kernel, dim3(blocks((int64_t)B * m->sizes[l])), dim3(BLK), 0, s, m->act32[l], B,
+                                   m->sizes[l], m->npad[l], trace[l]);
+    return launch_check("mlp_forward");
+}
+
+int mlp_gradients(lh_mlp* m, const double* X, const double* T, int32_t B, float* const* gW, float* const* gb,
+                  float* loss, hipStream_t s) {
+    using namespace lh;
+    using namespace lh::mlp;
+    LH_REQUIRE(m && X && T && B >= 1 && B <= m->max_batch, "mlp_gradients: bad arguments");
+    int rc = forward(m, X, B, s);
+    if (!rc) rc = backward(m, T, B, loss, s);
+    if (rc) return rc;
+    for (int l = 0; l < m->L; ++l) {
+        if (gW && gW[l]) {
+            const int64_t n = (int64_t)m->sizes[l] * m->sizes[l + 1];
+            hipLaunchKernelGGL(unpad_kernel, dim3(blocks(n)), dim3(BLK), 0, s, m->gW[l], m->sizes[l], m->sizes[l + 1],
+                               m->npad[l + 1], gW[l]);
+        }
+        if (gb && gb[l])
+            hipLaunchKernelGGL(unpad_kernel, dim3(blocks(m->sizes[l + 1])), dim3(BLK), 0, s, m->gb[l], 1,
+                               m->sizes[l + 1], m->npad[l + 1], gb[l]);
+    }
+    return launch_check("mlp_gradients");
+}
+
+int mlp_train_step(lh_mlp* m, const double* X, const double* T, int32_t B, double lr, float* loss, hipStream_t s) {
+    using namespace lh;
+    using namespace lh::mlp;
+    LH_REQUIRE(m && X && T && B >= 1 && B <= m->max_batch && lr > 0.0, "mlp_train_step: bad arguments");
+    int rc = forward(m, X, B, s);
+    if (!rc) rc = backward(m, T, B, loss, s);
+    if (rc) return rc;
+    m->step += 1;
+    const float c1 = (float)(1.0 - std::pow(0.9, m->step));
+    const float c2 = (float)(1.0 - std::pow(0.999, m->step));
+    for (int l = 0; l < m->L; ++l) {
+        // padding entries have zero gradient and stay zero
+        const int64_t nw = (int64_t)m->sizes[l] * m->npad[l + 1];
+        hipLaunchKernelGGL(adam_kernel, dim3(blocks(nw)), dim3(BLK), 0, s, m->W32[l], m->Wb[l], m->mW[l], m->vW[l],
+                           m->gW[l], nw, (float)lr, c1, c2);
+        hipLaunchKernelGGL(adam_kernel, dim3(blocks(m->npad[l + 1])), dim3(BLK), 0, s, m->b32[l], (uint16_t*)nullptr,
+                           m->mb[l], m->vb[l], m->gb[l], (int64_t)m->npad[l + 1], (float)lr, c1, c2);
+    }
+    return launch_check("mlp_train_step");
+}
+
+}  // extern "C"

@@ -76,6 +76,9 @@ struct WinDev {
     const double* T[3];  // from the previous window: n_f^w x n_f^{w-1}
     const double* c[3];
     const WgView* views;  // [G]
+    MlpDev net;           // surrogate of this window (net.L == 0: none)
+    int audit_every;
+    double tol;
 };
 
 struct InstDev {
@@ -99,6 +102,7 @@ struct RomArgs {
     const double* dt_replay;
     int n_replay;
     int nkin_max, nth_max;  // sizes of the entry-value arrays in LDS
+    int mlp_floats;         // LDS scratch of the surrogate (0: no surrogate this launch)
 };
 
 template <int DIM>
@@ -484,6 +488,122 @@ __device__ void x_update(const WinDev& W, const Local<TT>& L, const double* base
     }
 }
 
+// ------------------------------------------------------------- surrogate
+
+// LDS floats the surrogate needs: two activation buffers, the split-K partial
+// sums and the normalised output.
+inline int mlp_scratch_floats(const MlpDev& N) {
+    int wmax = N.npad[0];
+    for (int l = 1; l < N.L; ++l) wmax = std::max(wmax, N.npad[l]);
+    return (2 * wmax + 4 * BLK + N.npad[N.L] + 3) / 4 * 4;
+}
+
+// out[0..d_out) = normalised output of the network at [x^, v^, e^, t]
+// (bfloat16 operands, FP32 accumulation).  Every thread of the workgroup
+// takes part; the result is identical in every workgroup that evaluates it.
+__device__ void mlp_eval(const MlpDev& N, const double* yx, const double* yv, const double* ye, const int* n,
+                         double t, float* scr, float*& out) {
+    const int tid = threadIdx.x;
+    int wmax = N.npad[0];
+    for (int l = 1; l < N.L; ++l) wmax = max(wmax, N.npad[l]);
+    float* in = scr;
+    float* nxt = scr + wmax;
+    float* red = scr + 2 * wmax;
+    out = red + 4 * BLK;
+    const int nx = n[0], nv = n[1], ne = n[2];
+    for (int j = tid; j < N.sizes[0]; j += BLK) {
+        const double x = j < nx ? yx[j] : j < nx + nv ? yv[j - nx] : j < nx + nv + ne ? ye[j - nx - nv] : t;
+        in[j] = bf16_to_f32(f32_to_bf16((float)((x - N.mu_in[j]) / N.s_in[j])));
+    }
+    __syncthreads();
+    for (int l = 0; l < N.L; ++l) {
+        const int K = N.sizes[l], Nn = N.sizes[l + 1], ld = N.npad[l + 1];
+        const bool last = l == N.L - 1;
+        float* dst = last ? out : nxt;
+        const int nq = ld / 4;
+        const int KS = nq >= BLK ? 1 : min(BLK / nq, 4);
+        const int kc = (K + KS - 1) / KS;
+        const uint16_t* Wl = N.W[l];
+        for (int tt = tid; tt < nq * KS; tt += BLK) {
+            const int jq = tt % nq, ks = tt / nq;
+            const int k1 = min(K, (ks + 1) * kc);
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+            for (int k = ks * kc; k < k1; ++k) {
+                const float x = in[k];
+                const uint2 wv = *reinterpret_cast<const uint2*>(Wl + (int64_t)k * ld + 4 * jq);
+                a0 += x * bf16_to_f32((uint16_t)(wv.x & 0xFFFFu));
+                a1 += x * bf16_to_f32((uint16_t)(wv.x >> 16));
+                a2 += x * bf16_to_f32((uint16_t)(wv.y & 0xFFFFu));
+                a3 += x * bf16_to_f32((uint16_t)(wv.y >> 16));
+            }
+            if (KS == 1) {  // whole dot products: finish here (wide layers)
+                const float av[4] = {a0, a1, a2, a3};
+                for (int i = 0; i < 4; ++i) {
+                    const int j = 4 * jq + i;
+                    if (j >= Nn) break;
+                    const float v = av[i] + N.b[l][j];
+                    dst[j] = last ? v : bf16_to_f32(f32_to_bf16(tanhf(v)));
+                }
+            } else {  // KS * ld <= 4 BLK partial sums
+                float* r = red + ks * ld + 4 * jq;
+                r[0] = a0;
+                r[1] = a1;
+                r[2] = a2;
+                r[3] = a3;
+            }
+        }
+        __syncthreads();
+        if (KS > 1) {
+            for (int j = tid; j < Nn; j += BLK) {
+                float v = 0.f;
+                for (int ks = 0; ks < KS; ++ks) v += red[ks * ld + j];
+                v += N.b[l][j];
+                dst[j] = last ? v : bf16_to_f32(f32_to_bf16(tanhf(v)));
+            }
+            __syncthreads();
+        }
+        float* tmp = in;
+        in = nxt;
+        nxt = tmp;
+    }
+}
+
+// F^1 of the network (de-normalised) into f1h.
+__device__ void mlp_f1(const MlpDev& N, const float* out, int nv, double* f1h) {
+    for (int i = threadIdx.x; i < nv; i += BLK) f1h[i] = N.mu_out[i] + N.s_out[i] * (double)out[i];
+    __syncthreads();
+}
+
+// F^tv = g + H v^_c of the network into ftvh.
+__device__ void mlp_ftv(const MlpDev& N, const float* out, int nv, int ne, const double* vc, double* ftvh) {
+    for (int i = threadIdx.x; i < ne; i += BLK) {
+        const int jg = nv + i;
+        double acc = N.mu_out[jg] + N.s_out[jg] * (double)out[jg];
+        for (int k = 0; k < nv; ++k) {
+            const int jh = nv + ne + i * nv + k;
+            acc += (N.mu_out[jh] + N.s_out[jh] * (double)out[jh]) * vc[k];
+        }
+        ftvh[i] = acc;
+    }
+    __syncthreads();
+}
+
+// Relative discrepancy |a - b| / |b| of two LDS vectors (thread 0 sums in order).
+__device__ double rel_disc(const double* a, const double* b, int n, double* red) {
+    if (threadIdx.x == 0) {
+        double d = 0.0, r = 0.0;
+        for (int i = 0; i < n; ++i) {
+            d += (a[i] - b[i]) * (a[i] - b[i]);
+            r += b[i] * b[i];
+        }
+        red[0] = r > 0.0 ? sqrt(d / r) : sqrt(d);
+    }
+    __syncthreads();
+    const double v = red[0];
+    __syncthreads();
+    return v;
+}
+
 template <int DIM, class TT, bool RES>
 __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
     extern __shared__ double dyn_raw[];
@@ -499,7 +619,8 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
     double* fe = dyn_raw;
     double* te = fe + A.nkin_max;
     double* stage = te + A.nth_max;  // ceil(G / 8) x PSTRIDE partial results of combine
-    char* dyn = reinterpret_cast<char*>(stage + (int64_t)((A.G + 7) / 8) * PSTRIDE);
+    float* mscr = reinterpret_cast<float*>(stage + (int64_t)((A.G + 7) / 8) * PSTRIDE);  // surrogate scratch
+    char* dyn = reinterpret_cast<char*>(mscr + A.mlp_floats);
     if (tid == 0) {
         st = A.state[ii];
         s_status = 0;
@@ -515,6 +636,10 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
     int w = st.w;
     double t = st.t, dt = st.dt;
     int n_steps = st.n_steps, n_rej = st.n_rejected, evals = st.n_force_evals;
+    double tau_est = st.tau_est;
+    int since = st.since, fallen = st.fallen, n_audits = st.n_audits, n_surr = st.n_surrogate_steps,
+        n_fallbacks = st.n_fallbacks;
+    const bool surrogate = (A.flags & LH_SURROGATE) != 0 && A.mlp_floats > 0;
     int phase = 0;
     Local<TT> L;
     load_local<DIM, TT>(I.win[w], I.win[w].views[g], I, RES, dyn, L);
@@ -553,6 +678,34 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             done = true;
             break;
         }
+        const bool has_net = surrogate && W.net.L > 0 && !fallen;
+        const bool audit_now = has_net && since % W.audit_every == 0;
+        double tau;
+        if (has_net && !audit_now) {
+            // ---- surrogate step: the network's F^1 and F^tv = g + H v^_c in both stages
+            float* out;
+            mlp_eval(W.net, S.y[0], S.y[1], S.y[2], W.n, t, mscr, out);
+            mlp_f1(W.net, out, W.n[1], S.f1h);
+            for (int i = tid; i < W.n[1]; i += BLK) S.yh[1][i] = S.y[1][i] - 0.5 * h * S.f1h[i];
+            __syncthreads();
+            mlp_ftv(W.net, out, W.n[1], W.n[2], S.yh[1], S.ftvh);
+            for (int i = tid; i < W.n[2]; i += BLK) S.yh[2][i] = S.y[2][i] + 0.5 * h * S.ftvh[i];
+            x_update(W, L, S.y[0], 0.5 * h, S.yh[1], S.yh[0]);
+            __syncthreads();
+            mlp_eval(W.net, S.yh[0], S.yh[1], S.yh[2], W.n, t + 0.5 * h, mscr, out);
+            mlp_f1(W.net, out, W.n[1], S.f1h);
+            for (int i = tid; i < W.n[1]; i += BLK) {
+                const double vn = S.y[1][i] - h * S.f1h[i];
+                S.yn[1][i] = vn;
+                S.vc[i] = 0.5 * (S.y[1][i] + vn);
+            }
+            __syncthreads();
+            mlp_ftv(W.net, out, W.n[1], W.n[2], S.vc, S.ftvh);
+            for (int i = tid; i < W.n[2]; i += BLK) S.yn[2][i] = S.y[2][i] + h * S.ftvh[i];
+            x_update(W, L, S.y[0], h, S.vc, S.yn[0]);
+            __syncthreads();
+            tau = tau_est;
+        } else {
         // ---- stage 1 at y_n
         pass_a<DIM, TT>(A, W, V, L, B, S, fe, S.y[0], S.y[1], S.y[2], (phase & 1) ? part1 : part0, &s_status);
         sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status);
@@ -564,6 +717,20 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status);
         combine((phase & 1) ? all1 : all0, A.G, W.n[2], S.ftvh, &s_status, S, stage);
         ++phase;
+        if (audit_now) {
+            // the network against the DEIM chain at the first stage: F^1 at y_n, F^tv at v^_{1/2}
+            float* out;
+            mlp_eval(W.net, S.y[0], S.y[1], S.y[2], W.n, t, mscr, out);
+            mlp_f1(W.net, out, W.n[1], S.tmp);
+            const double d1 = rel_disc(S.tmp, S.f1h, W.n[1], S.red);
+            mlp_ftv(W.net, out, W.n[1], W.n[2], S.yh[1], S.tmp);
+            const double d2 = rel_disc(S.tmp, S.ftvh, W.n[2], S.red);
+            ++n_audits;
+            if (!(fmax(d1, d2) <= W.tol) || isnan(d1) || isnan(d2)) {
+                fallen = 1;
+                ++n_fallbacks;
+            }
+        }
         for (int i = tid; i < W.n[2]; i += BLK) S.yh[2][i] = S.y[2][i] + 0.5 * h * S.ftvh[i];
         x_update(W, L, S.y[0], 0.5 * h, S.yh[1], S.yh[0]);
         __syncthreads();
@@ -586,7 +753,9 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         x_update(W, L, S.y[0], h, S.vc, S.yn[0]);
         __syncthreads();
         evals += 2 * W.n_el;
-        const double tau = fmin(tau1, tau2);
+        tau = fmin(tau1, tau2);
+        if (audit_now) tau_est = tau;
+        }
         if (s_status & (LH_FLAG_TANGLED | LH_FLAG_NONFINITE | LH_FLAG_TIMEOUT)) {
             done = true;
             break;
@@ -603,6 +772,8 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         t = t + h;
         ++n_steps;
         ++accepted;
+        if (has_net && !audit_now) ++n_surr;
+        ++since;
         // window change (eq. ic-tw): y^w = T_w y^{w-1} + c_w
         bool moved = false;
         while (w + 1 < I.n_windows && t >= I.win[w].t_end) {
@@ -621,7 +792,12 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             ++w;
             moved = true;
         }
-        if (moved) load_local<DIM, TT>(I.win[w], I.win[w].views[g], I, RES, dyn, L);
+        if (moved) {
+            load_local<DIM, TT>(I.win[w], I.win[w].views[g], I, RES, dyn, L);
+            since = 0;
+            fallen = 0;
+            tau_est = INFINITY;
+        }
         if (replay)
             done = n_steps >= A.n_replay;
         else
@@ -639,11 +815,105 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         st.n_rejected = n_rej;
         st.n_force_evals = evals;
         st.done = done ? 1 : 0;
+        st.tau_est = tau_est;
+        st.since = since;
+        st.fallen = fallen;
+        st.n_audits = n_audits;
+        st.n_surrogate_steps = n_surr;
+        st.n_fallbacks = n_fallbacks;
     }
     for (int f = 0; f < 3; ++f)
         for (int k = tid; k < LH_NMAX; k += BLK) st.yhat[f][k] = S.y[f][k];
     __syncthreads();
     if (tid == 0) A.state[ii] = st;
+}
+
+// ------------------------------------------------------- surrogate targets
+
+// The window's data of view V read from global memory, with the kept stress in sig.
+template <int DIM>
+__device__ Local<double> global_local(const WinDev& W, const WgView& V, double* sig) {
+    constexpr int NKD = Cfg<DIM>::NKD, NT = Cfg<DIM>::NT, NQ = Cfg<DIM>::NQ, DD = Cfg<DIM>::DD;
+    const int rows[3] = {NKD, NKD, NT};
+    Local<double> L;
+    for (int f = 0; f < 3; ++f) {
+        L.tile[f] = W.tile[f] + (int64_t)V.s0 * W.n[f] * rows[f];
+        L.os[f] = W.os_loc[f] + (int64_t)V.s0 * rows[f];
+    }
+    L.a1 = W.A1;
+    L.a2 = W.A2;
+    L.res = false;
+    L.Bxv = W.Bxv;
+    L.bx = W.bx;
+    L.sig = sig + (int64_t)V.s0 * NQ * DD;
+    return L;
+}
+
+// One workgroup per sample: [F^1, g, H] of the DEIM chain at y^ (window w), with
+// every view of the window evaluated in turn and the shares combined in the same
+// order as rom_step.  zeros: n_el * NKD zeros (velocity offset left out for H).
+template <int DIM>
+__global__ void __launch_bounds__(BLK) targets_kernel(RomArgs A, const InstDev* Ip, int w, const double* yhat, int B,
+                                                      int s0, double* T, double* scr_share, double* scr_sig,
+                                                      const double* zeros) {
+    constexpr int NKD = Cfg<DIM>::NKD, NQ = Cfg<DIM>::NQ, DD = Cfg<DIM>::DD;
+    extern __shared__ double dyn_raw[];
+    __shared__ NodeBuf<DIM> Bn;
+    __shared__ Shared S;
+    __shared__ int s_status;
+    const int smp = s0 + blockIdx.x;
+    if (smp >= B) return;
+    const int tid = threadIdx.x;
+    const InstDev& I = *Ip;
+    const WinDev& W = I.win[w];
+    const int G = A.G;
+    const int nx = W.n[0], nv = W.n[1], ne = W.n[2];
+    const int din = nx + nv + ne, dout = nv + ne + ne * nv;
+    double* fe = dyn_raw;
+    double* te = fe + A.nkin_max;
+    double* stage = te + A.nth_max;
+    double* share = scr_share + (int64_t)blockIdx.x * G * PSTRIDE;
+    double* sig = scr_sig + (int64_t)blockIdx.x * W.n_el * NQ * DD;
+    for (int f = 0, off = 0; f < 3; off += W.n[f], ++f)
+        for (int k = tid; k < LH_NMAX; k += BLK) S.y[f][k] = k < W.n[f] ? yhat[(int64_t)smp * din + off + k] : 0.0;
+    if (tid == 0) s_status = 0;
+    __syncthreads();
+    double* out = T + (int64_t)smp * dout;
+    for (int g = 0; g < G; ++g) {
+        const Local<double> L = global_local<DIM>(W, W.views[g], sig);
+        pass_a<DIM, double>(A, W, W.views[g], L, Bn, S, fe, S.y[0], S.y[1], S.y[2], share + (int64_t)g * PSTRIDE,
+                            &s_status);
+        __syncthreads();
+    }
+    __threadfence();
+    __syncthreads();
+    combine(share, G, nv, S.f1h, &s_status, S, stage);
+    for (int i = tid; i < nv; i += BLK) out[i] = S.f1h[i];
+    // columns: k = -1 gives g (offset velocity), k >= 0 gives H e_k (no offset)
+    for (int k = -1; k < nv; ++k) {
+        for (int i = tid; i < LH_NMAX; i += BLK) S.vc[i] = (i == k) ? 1.0 : 0.0;
+        __syncthreads();
+        for (int g = 0; g < G; ++g) {
+            Local<double> L = global_local<DIM>(W, W.views[g], sig);
+            if (k >= 0) L.os[1] = zeros;  // rows of every slot read zero
+            pass_b<DIM, double>(A, W, W.views[g], L, Bn, te, S.vc, share + (int64_t)g * PSTRIDE, &s_status);
+            __syncthreads();
+        }
+        __threadfence();
+        __syncthreads();
+        combine(share, G, ne, S.ftvh, &s_status, S, stage);
+        for (int i = tid; i < ne; i += BLK) {
+            if (k < 0)
+                out[nv + i] = S.ftvh[i];
+            else
+                out[nv + ne + (int64_t)i * nv + k] = S.ftvh[i];
+        }
+        __syncthreads();
+    }
+    // a tangled or non-finite lifted state has no targets: the row reads NaN
+    if (s_status & (LH_FLAG_TANGLED | LH_FLAG_NONFINITE))
+        for (int i = tid; i < dout; i += BLK) out[i] = NAN;
+    (void)NKD;
 }
 
 // ------------------------------------------------------------ set-up kernels
@@ -730,6 +1000,8 @@ __global__ void reset_state_kernel(lh_rom_state* st, int n, double dt) {
     z.w = z.status = z.n_steps = z.n_rejected = z.n_force_evals = z.done = 0;
     for (int f = 0; f < 3; ++f)
         for (int k = 0; k < LH_NMAX; ++k) z.yhat[f][k] = 0.0;
+    z.tau_est = INFINITY;
+    z.since = z.fallen = z.n_audits = z.n_surrogate_steps = z.n_fallbacks = z.pad_ = 0;
     st[i] = z;
 }
 
@@ -763,6 +1035,7 @@ struct lh_rom {
     int G;
     int nkin_max, nth_max;
     int res_max64, res_max32;
+    int mlp_floats = 0;  // LDS scratch of the largest attached surrogate
     std::vector<void*> allocs;
     lh::rom::InstDev* d_inst;
     std::vector<lh::rom::InstDev> h_inst;
@@ -1182,7 +1455,8 @@ static int launch_rom(const lh_rom* R, const RomArgs& A, size_t dyn, hipStream_t
 
 template <int DIM>
 static int dispatch(const lh_rom* R, const RomArgs& A, bool f32, hipStream_t s) {
-    const size_t entries = 8 * (size_t)(A.nkin_max + A.nth_max + (int64_t)((A.G + 7) / 8) * PSTRIDE);
+    const size_t entries = 8 * (size_t)(A.nkin_max + A.nth_max + (int64_t)((A.G + 7) / 8) * PSTRIDE) +
+                           4 * (size_t)A.mlp_floats;
     const int budget = lds_budget() - STATIC_LDS_RESERVE;
     const int res = f32 ? R->res_max32 : R->res_max64;
     const bool resident = (int64_t)entries + res <= budget;
@@ -1217,6 +1491,7 @@ int rom_step(const lh_rom* R, lh_rom_state* state, int32_t max_steps, uint32_t f
     A.n_replay = n_replay;
     A.nkin_max = R->nkin_max;
     A.nth_max = R->nth_max;
+    A.mlp_floats = (flags & LH_SURROGATE) ? R->mlp_floats : 0;
     const bool f32 = (flags & LH_FP32_LIFT) != 0;
     return p->dim == 2 ? dispatch<2>(R, A, f32, s) : dispatch<3>(R, A, f32, s);
 }
@@ -1250,6 +1525,103 @@ int rom_sampled_elements(const lh_rom* R, int32_t inst, int32_t window, int32_t*
     LH_REQUIRE(window >= 0 && window < (int)R->h_win[inst].size(), "rom_sampled_elements: window out of range");
     *n_elems = R->h_win[inst][window].n_el;
     return LH_OK;
+}
+
+int rom_attach_surrogate(lh_rom* R, int32_t inst, int32_t w, const lh_mlp* m, int32_t audit_every, double tol) {
+    using namespace lh;
+    using namespace lh::rom;
+    LH_REQUIRE(R && inst >= 0 && inst < R->n_inst, "rom_attach_surrogate: bad instance");
+    LH_REQUIRE(w >= 0 && w < (int)R->h_win[inst].size(), "rom_attach_surrogate: bad window");
+    WinDev& D = R->h_win[inst][w];
+    if (m) {
+        const MlpDev v = mlp_view(m);
+        LH_REQUIRE(audit_every >= 1, "rom_attach_surrogate: audit_every must be >= 1");
+        LH_REQUIRE(v.sizes[0] == D.n[0] + D.n[1] + D.n[2] + 1, "rom_attach_surrogate: input size must be n_x+n_v+n_e+1");
+        LH_REQUIRE(v.sizes[v.L] == D.n[1] + D.n[2] + D.n[2] * D.n[1],
+                   "rom_attach_surrogate: output size must be n_v+n_e+n_e*n_v");
+        const int need = mlp_scratch_floats(v);
+        LH_REQUIRE(4 * need <= 64 * 1024, "rom_attach_surrogate: network too wide for the LDS scratch");
+        D.net = v;
+        D.audit_every = audit_every;
+        D.tol = tol;
+        R->mlp_floats = std::max(R->mlp_floats, need);
+    } else {
+        D.net = MlpDev{};
+        D.audit_every = 1;
+        D.tol = 0.0;
+    }
+    LH_HIP_CHECK(hipMemcpy(const_cast<WinDev*>(R->h_inst[inst].win) + w, &D, sizeof(WinDev), hipMemcpyHostToDevice));
+    return LH_OK;
+}
+
+int rom_surrogate_targets(const lh_rom* R, int32_t inst, int32_t w, const double* yhat, int32_t B, double* T,
+                          hipStream_t s) {
+    using namespace lh;
+    using namespace lh::rom;
+    LH_REQUIRE(R && yhat && T && B >= 0, "rom_surrogate_targets: bad arguments");
+    LH_REQUIRE(inst >= 0 && inst < R->n_inst, "rom_surrogate_targets: bad instance");
+    LH_REQUIRE(w >= 0 && w < (int)R->h_win[inst].size(), "rom_surrogate_targets: bad window");
+    if (B == 0) return LH_OK;
+    const lh_problem* p = R->p;
+    const WinDev& D = R->h_win[inst][w];
+    const int dim = p->dim;
+    const int NQ = dim == 2 ? 16 : 64, DD = dim * dim, NKD = dim * (dim == 2 ? 9 : 27);
+    const int CH = std::min<int>(B, 512);
+    double *share = nullptr, *sig = nullptr, *zeros = nullptr;
+    const size_t n_sig = (size_t)CH * std::max(D.n_el, 1) * NQ * DD;
+    const size_t n_zero = (size_t)std::max(D.n_el, 1) * NKD;
+    auto cleanup = [&]() {
+        if (share) (void)hipFree(share);
+        if (sig) (void)hipFree(sig);
+        if (zeros) (void)hipFree(zeros);
+    };
+    if (hipMalloc(&share, sizeof(double) * (size_t)CH * R->G * PSTRIDE) != hipSuccess ||
+        hipMalloc(&sig, sizeof(double) * n_sig) != hipSuccess || hipMalloc(&zeros, sizeof(double) * n_zero) != hipSuccess) {
+        cleanup();
+        set_error("rom_surrogate_targets: device allocation failed");
+        return LH_EDEVICE;
+    }
+    RomArgs A{};
+    A.T = p->tab;
+    A.fc = p->fc;
+    A.inst = R->d_inst;
+    A.state = nullptr;
+    A.n_inst = R->n_inst;
+    A.G = R->G;
+    A.nkin_max = R->nkin_max;
+    A.nth_max = R->nth_max;
+    int rc = LH_OK;
+    {
+        // zero the offset stand-in
+        std::vector<double> hz(n_zero, 0.0);
+        if (hipMemcpyAsync(zeros, hz.data(), sizeof(double) * n_zero, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            rc = LH_EDEVICE;
+    }
+    const size_t dyn = 8 * (size_t)(A.nkin_max + A.nth_max + (int64_t)((A.G + 7) / 8) * PSTRIDE);
+    for (int s0 = 0; s0 < B && rc == LH_OK; s0 += CH) {
+        const int nb_ = std::min(CH, B - s0);
+        if (dim == 2) {
+            if (dyn > 0 && hipFuncSetAttribute((const void*)targets_kernel<2>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess)
+                rc = LH_EDEVICE;
+            hipLaunchKernelGGL(targets_kernel<2>, dim3(nb_), dim3(BLK), dyn, s, A, R->d_inst + inst, w, yhat, B, s0, T,
+                               share, sig, (const double*)zeros);
+        } else {
+            if (dyn > 0 && hipFuncSetAttribute((const void*)targets_kernel<3>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess)
+                rc = LH_EDEVICE;
+            hipLaunchKernelGGL(targets_kernel<3>, dim3(nb_), dim3(BLK), dyn, s, A, R->d_inst + inst, w, yhat, B, s0, T,
+                               share, sig, (const double*)zeros);
+        }
+        if (!rc) rc = launch_check("targets_kernel");
+    }
+    if (!rc && hipStreamSynchronize(s) != hipSuccess) {
+        set_error("rom_surrogate_targets: synchronisation failed");
+        rc = LH_EDEVICE;
+    }
+    cleanup();
+    return rc;
 }
 
 int rom_workgroups_per_instance(const lh_rom* R, int32_t* G) {

@@ -18,7 +18,8 @@ LH_OK = 0
 LH_ERRORS = {-1: "LH_EINVAL", -2: "LH_EWORKSPACE", -3: "LH_EDEVICE", -4: "LH_ETANGLED", -5: "LH_ENONFINITE",
              -6: "LH_EDTCOLLAPSE", -7: "LH_ERANK"}
 LH_F1, LH_FTV, LH_TAU, LH_KEEP_STRESS, LH_USE_STRESS, LH_NO_BC = 1, 2, 4, 8, 16, 32
-LH_FP32_LIFT, LH_REPLAY_DT, LH_FIXED_DT = 1, 2, 4
+LH_FP32_LIFT, LH_REPLAY_DT, LH_FIXED_DT, LH_SURROGATE = 1, 2, 4, 8
+LH_MLP_MAX_LAYERS = 8
 LH_NMAX = 64
 KIND = {"taylor_green": 1, "sedov": 2, "gresho": 3}
 
@@ -56,10 +57,16 @@ class InstanceDesc(C.Structure):
     _fields_ = [("n_windows", C.c_int32), ("windows", C.POINTER(WindowDesc)), ("t_final", C.c_double)]
 
 
+class MlpDesc(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("sizes", C.c_int32 * (LH_MLP_MAX_LAYERS + 1))]
+
+
 class RomState(C.Structure):
     _fields_ = [("t", C.c_double), ("dt", C.c_double), ("w", C.c_int32), ("status", C.c_int32),
                 ("n_steps", C.c_int32), ("n_rejected", C.c_int32), ("n_force_evals", C.c_int32),
-                ("done", C.c_int32), ("yhat", (C.c_double * LH_NMAX) * 3)]
+                ("done", C.c_int32), ("yhat", (C.c_double * LH_NMAX) * 3), ("tau_est", C.c_double),
+                ("since", C.c_int32), ("fallen", C.c_int32), ("n_audits", C.c_int32),
+                ("n_surrogate_steps", C.c_int32), ("n_fallbacks", C.c_int32), ("pad_", C.c_int32)]
 
 
 ROM_STATE_BYTES = C.sizeof(RomState)
@@ -90,6 +97,15 @@ _SIGNATURES = {
     "rom_lift": (_I32, [_VP, _VP, _I32, C.POINTER(InstanceDesc), _VP, _VP, _VP, _VP]),
     "rom_sampled_elements": (_I32, [_VP, _I32, _I32, C.POINTER(_I32)]),
     "rom_workgroups_per_instance": (_I32, [_VP, C.POINTER(_I32)]),
+    "mlp_create": (_I32, [C.POINTER(MlpDesc), _I32, C.POINTER(_VP)]),
+    "mlp_destroy": (None, [_VP]),
+    "mlp_set_params": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "mlp_get_params": (_I32, [_VP, _VP, _VP, _VP]),
+    "mlp_forward": (_I32, [_VP, _VP, _I32, _VP, _VP, _VP]),
+    "mlp_gradients": (_I32, [_VP, _VP, _VP, _I32, _VP, _VP, _VP, _VP]),
+    "mlp_train_step": (_I32, [_VP, _VP, _VP, _I32, _D, _VP, _VP]),
+    "rom_surrogate_targets": (_I32, [_VP, _I32, _I32, _VP, _I32, _VP, _VP]),
+    "rom_attach_surrogate": (_I32, [_VP, _I32, _I32, _VP, _I32, _D]),
     "lh_snapshot_deviation": (_I32, [_VP, _I64, _I32, _I64, _VP, _VP, _I64, _VP]),
     "lh_mass_apply_v": (_I32, [_VP, _VP, _VP, _VP]),
     "lh_mass_apply_e": (_I32, [_VP, _VP, _VP, _VP]),
@@ -361,7 +377,85 @@ class Rom:
                                stream_handle()))
         return x, v, e
 
+    def attach_surrogate(self, i, w, mlp, audit_every=10, tol=0.05):
+        self._keep.append(mlp)
+        _check(load().rom_attach_surrogate(self.h, int(i), int(w), None if mlp is None else mlp.h, int(audit_every),
+                                           float(tol)))
+
     def sampled_elements(self, i, w):
         n = _I32()
         _check(load().rom_sampled_elements(self.h, int(i), int(w), C.byref(n)))
         return n.value
+
+
+def _ptr_array(ts):
+    """Host array of device pointers (None -> NULL); returns (array, keep-alive list)."""
+    arr = (C.c_void_p * len(ts))(*[None if t is None else t.data_ptr() for t in ts])
+    return arr
+
+
+class Mlp:
+    """Surrogate network (mlp_create ... mlp_train_step): bfloat16 operands, FP32 accumulation."""
+
+    def __init__(self, sizes, max_batch):
+        lib = load()
+        d = MlpDesc()
+        d.n_layers = len(sizes) - 1
+        for i, n in enumerate(sizes):
+            d.sizes[i] = int(n)
+        h = C.c_void_p()
+        _check(lib.mlp_create(C.byref(d), int(max_batch), C.byref(h)))
+        self.h = h
+        self.sizes = [int(n) for n in sizes]
+        self.L = len(sizes) - 1
+        self.max_batch = int(max_batch)
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _LIB is not None:
+            _LIB.mlp_destroy(self.h)
+            self.h = None
+
+    def set_params(self, W=None, b=None, mu_in=None, s_in=None, mu_out=None, s_out=None):
+        """W, b: lists of FP64 device tensors (W[l] of shape (sizes[l], sizes[l+1]))."""
+        Wa = _ptr_array([w.contiguous() for w in W]) if W is not None else None
+        ba = _ptr_array([x.contiguous() for x in b]) if b is not None else None
+        _check(load().mlp_set_params(self.h, Wa, ba, ptr(mu_in), ptr(s_in), ptr(mu_out), ptr(s_out),
+                                     stream_handle()))
+
+    def get_params(self):
+        W = [torch.empty((self.sizes[l], self.sizes[l + 1]), dtype=torch.float32, device="cuda")
+             for l in range(self.L)]
+        b = [torch.empty(self.sizes[l + 1], dtype=torch.float32, device="cuda") for l in range(self.L)]
+        _check(load().mlp_get_params(self.h, _ptr_array(W), _ptr_array(b), stream_handle()))
+        return W, b
+
+    def forward(self, X, trace=False):
+        B = int(X.shape[0])
+        Y = torch.empty((B, self.sizes[-1]), dtype=torch.float64, device="cuda")
+        tr = [torch.empty((B, n), dtype=torch.float32, device="cuda") for n in self.sizes] if trace else None
+        _check(load().mlp_forward(self.h, ptr(X), B, ptr(Y), _ptr_array(tr) if trace else None, stream_handle()))
+        return (Y, tr) if trace else Y
+
+    def gradients(self, X, T):
+        B = int(X.shape[0])
+        gW = [torch.empty((self.sizes[l], self.sizes[l + 1]), dtype=torch.float32, device="cuda")
+              for l in range(self.L)]
+        gb = [torch.empty(self.sizes[l + 1], dtype=torch.float32, device="cuda") for l in range(self.L)]
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(load().mlp_gradients(self.h, ptr(X), ptr(T), B, _ptr_array(gW), _ptr_array(gb), ptr(loss),
+                                    stream_handle()))
+        return gW, gb, loss
+
+    def train_step(self, X, T, lr, loss=None):
+        _check(load().mlp_train_step(self.h, ptr(X), ptr(T), int(X.shape[0]), float(lr), ptr(loss),
+                                     stream_handle()))
+
+
+def rom_surrogate_targets(rom, inst, w, yhat):
+    """DEIM-chain targets [F^1, g, H] (B x (n_v + n_e + n_e n_v)) at reduced states yhat (B x (n_x + n_v + n_e))."""
+    wd = rom.instances[inst]["windows"][w]
+    nv, ne = (int(wd["phi"][f].shape[0]) for f in (1, 2))
+    B = int(yhat.shape[0])
+    T = torch.empty((B, nv + ne + ne * nv), dtype=torch.float64, device="cuda")
+    _check(load().rom_surrogate_targets(rom.h, int(inst), int(w), ptr(yhat), B, ptr(T), stream_handle()))
+    return T
