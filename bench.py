@@ -193,6 +193,97 @@ def batched_gresho(lib, pipeline, n_inst: int = 256, reps: int = 3, lam=None):
     return out
 
 
+def surrogate_tg2d(lib, pipeline, n_inst: int = 64, train_steps: int = 4000, reps: int = 3, audit_every: int = 10,
+                   tol: float = 0.05, n_fixed=None, lam=None, variants=None):
+    """Batched plain DEIM ROM against the surrogate ROM, parametric 2D Taylor-Green.
+
+    32 x 32 mesh, fixed dt = 1e-3 to t = 0.2, amplitude A ~ U[0.8, 1.2] per instance; bases (one
+    window, dims 20/20/20, lambda = 2) from GPU FOM runs at A = 0.8, 1.0, 1.2, relative to the A = 1
+    initial state.  The network (inputs [x^, v^, e^, t], 3 tanh layers of 256, bfloat16 operands)
+    is trained on the GPU on the snapshots of GPU FOM runs at 17 amplitudes in [0.8, 1.2], projected
+    onto those bases; in the surrogate runs every
+    audit_every-th step is a DEIM audit.  Errors: each instance's lifted final state against its own
+    GPU FOM run.
+    """
+    import torch
+
+    import workloads as Wl
+
+    wl = Wl.tg2d_param(n_inst=n_inst)
+    t0 = time.perf_counter()
+    trajs = []
+    for A in Wl.TG_TRAIN_AMPS:
+        Pa = lib.Problem.from_workload(wl, amp=A)
+        trajs.append(pipeline.fom_trajectory(Pa, wl.t_final, fixed_dt=wl.fixed_dt))
+    nominal = trajs[1]["y0"]
+    P = lib.Problem.from_workload(wl, amp=1.0)
+    n_fixed = wl.n_fixed if n_fixed is None else n_fixed
+    lam = wl.lam if lam is None else lam
+    inst = pipeline.build_offline(P, trajs, [wl.t_final], nominal, n_fixed=n_fixed, lam=lam,
+                                  t_final=wl.t_final, snapshot_offsets=nominal)
+    t_offline = time.perf_counter() - t0
+    y0s, finals = [], []
+    for prm in wl.params:
+        Pi = lib.Problem.from_workload(wl, amp=prm["amp"])
+        x, v, e = Pi.initial_state()
+        y0s.append((x.clone(), v.clone(), e.clone()))
+        Pi.fom_run(x, v, e, wl.t_final, fixed_dt=wl.fixed_dt, record=False)
+        finals.append((x, v, e))
+    y0 = [torch.cat([y[f] for y in y0s]) for f in range(3)]
+    rom = lib.Rom(P, [inst] * n_inst)
+    t1 = time.perf_counter()
+    # network training data: the projected snapshots of FOM runs at 17 amplitudes spread over the range
+    ntr = [pipeline.fom_trajectory(lib.Problem.from_workload(wl, amp=float(A)), wl.t_final, fixed_dt=wl.fixed_dt)
+           for A in np.linspace(0.8, 1.2, 17)]
+    X = pipeline.surrogate_inputs(rom, 0, 0, ntr)
+    del ntr
+    net, T, hist = pipeline.train_surrogate(rom, 0, 0, X, steps=train_steps, lr=2e-3, lr_final=1e-4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    print(f"[bench] surrogate: {int(X.shape[0])} samples, loss {hist[0]:.3e} -> {hist[-1]:.3e} in {t_train:.1f} s",
+          file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    g = lib._I32()
+    lib._check(lib.load().rom_workgroups_per_instance(rom.h, lib.C.byref(g)))
+    out = {"workload": f"tg2d_32x32_param_A0.8-1.2_batch{n_inst}_fixed_dt1e-3_t{wl.t_final:g}_dims20_lambda2",
+           "instances": n_inst, "workgroups_per_instance": g.value, "offline_s": t_offline,
+           "training": {"samples": int(X.shape[0]), "steps": train_steps, "seconds": t_train,
+                        "loss_first": hist[0], "loss_last": hist[-1],
+                        "network": [int(X.shape[1]), 256, 256, 256, int(T.shape[1])]}}
+    runs = [("deim", lib.LH_FIXED_DT, audit_every, tol), ("surrogate", lib.LH_FIXED_DT | lib.LH_SURROGATE, audit_every, tol)]
+    for k_, tol_ in variants or ():
+        runs.append((f"surrogate_K{k_}_tol{tol_:g}", lib.LH_FIXED_DT | lib.LH_SURROGATE, k_, tol_))
+    for name, flags, k_audit, tol_run in runs:
+        for i in range(n_inst):
+            rom.attach_surrogate(i, 0, net if name != "deim" else None, audit_every=k_audit, tol=tol_run)
+        ms = []
+        for r in range(reps + 1):
+            rom.init_state(*y0, wl.fixed_dt)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            rom.step(flags=flags)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if r:
+                ms.append(a.elapsed_time(b))
+        sts = rom.states()
+        steps = sum(st.n_steps for st in sts)
+        errs = np.array([[float(torch.linalg.norm(x - y) / torch.linalg.norm(y)) for x, y in zip(rom.lift(i), finals[i])]
+                         for i in range(n_inst)])
+        t = sorted(ms)[len(ms) // 2] / 1e3
+        out[name] = {"ms_per_launch": t * 1e3, "rom_steps_per_s": steps / t,
+                     "sampled_force_evals_per_s": sum(st.n_force_evals for st in sts) / t,
+                     "failed_instances": [i for i, st in enumerate(sts) if st.status != 0 or st.done != 1],
+                     "max_rel_error_vs_fom": dict(zip("xve", errs.max(axis=0).tolist())),
+                     "median_rel_error_vs_fom": dict(zip("xve", np.median(errs, axis=0).tolist())),
+                     "audits": sum(st.n_audits for st in sts), "surrogate_steps": sum(st.n_surrogate_steps for st in sts),
+                     "fallback_windows": sum(st.n_fallbacks for st in sts)}
+        print(f"[bench] {name}: {t * 1e3:.2f} ms, {steps / t:.0f} ROM steps/s, max err "
+              f"{errs.max(axis=0)}", file=sys.stderr, flush=True)
+    out["speedup_surrogate_vs_deim"] = out["surrogate"]["rom_steps_per_s"] / out["deim"]["rom_steps_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +293,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-force", action="store_true", help="skip the full-mesh fom_force measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-instance batched Gresho measurement")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate against DEIM measurement")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, help="also run a plain device copy of this many MiB")
     args = ap.parse_args()
@@ -328,6 +420,8 @@ def main():
               file=sys.stderr, flush=True)
     if not args.no_batch:
         out["batched"] = batched_gresho(lib, pipeline)
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_tg2d(lib, pipeline, train_steps=3000, variants=[(25, 1e30)])
     if not args.no_cpu_baseline:
         med = [int(sorted(d[f] for d in dims)[len(dims) // 2]) for f in range(3)]
         out["cpu_baseline"] = cpu_baseline(wl, med, st.n_force_evals / st.n_steps, args.cpu_seconds)

@@ -319,6 +319,14 @@ int rom_workgroups_per_instance(const lh_rom* r, int32_t* G);
 int lh_snapshot_deviation(const double* snaps, int64_t N, int32_t m, int64_t ld, const double* os, double* out,
                           int64_t ldo, hipStream_t stream);
 
+/* Reduced coordinates of snapshots (Sec. 3.1, y^ = Phi^T (y - os)):
+ * out[j * ldo + k] = sum_r Phi[k * ldp + r] (S[j * lds + r] - os[r]) for
+ * j < m, k < n.  Phi (dev, n rows of length N, ldp), S (dev, m snapshot rows
+ * of length N, lds), os (dev, N), out (dev, m rows, ldo >= n; may be a column
+ * block of a wider matrix).  n <= LH_NMAX. */
+int lh_project_snapshots(const double* Phi, int32_t n, int64_t N, int64_t ldp, const double* S, int32_t m,
+                         int64_t lds, const double* os, double* out, int64_t ldo, hipStream_t stream);
+
 /* SNS nonlinear bases (Sec. 3.5): out = M_V in with the wall rows and
  * columns eliminated and identity on the wall rows (the form whose inverse
  * lh_mass_solve_v applies), and out = M_E in.  One column (N_V resp. N_E,
@@ -348,8 +356,9 @@ int lh_window_columns(const double* t, int32_t n_steps, const double* T, int32_t
 /* A fully connected network that stands in for the sampled lift, force and
  * projection of one window (an addition to the method; the paper has no
  * learned component): inputs [x^, v^, e^, t], outputs the reduced force
- * coefficients [F^1 (n_v), g (n_e), H (n_e x n_v, row-major)] with
- * F^tv = g + H v^_c for a contraction velocity v^_c, which is exact for the
+ * coefficients [F^1 (n_v), f (n_e), H (n_e x n_v, row-major)] at that state,
+ * f the energy right-hand side at the state's own velocity v^, so that for a
+ * contraction velocity v^_c F^tv = f + H (v^_c - v^), which is exact for the
  * DEIM chain of eq. rom-hr-sns because F^T v_c is linear in v_c.
  *   z_0 = (x - mu_in) / s_in;  z_{l+1} = act(r(z_l) r(W_l) + b_l);  y = mu_out + s_out z_L,
  * act = tanh on hidden layers, identity on the last; r() rounds to bfloat16
@@ -392,27 +401,35 @@ int mlp_gradients(lh_mlp* m, const double* X, const double* T, int32_t B, float*
 /* One Adam step with learning rate lr on the minibatch (X, T). */
 int mlp_train_step(lh_mlp* m, const double* X, const double* T, int32_t B, double lr, float* loss,
                    hipStream_t stream);
+/* Set the normalisation to the column means and population standard
+ * deviations of X and T (dev, B rows each; a zero deviation becomes 1). */
+int mlp_fit_normalisation(lh_mlp* m, const double* X, const double* T, int32_t B, hipStream_t stream);
 
 /* Training targets of window w of instance inst: for each of the B rows of
- * yhat (dev, B x (n_x + n_v + n_e) FP64, coefficients in window w's bases)
- * the DEIM chain's [F^1, g, H] at the lifted state (dev, B x (n_v + n_e +
- * n_e n_v) FP64): F^1 = A1 (F.1)_Z1, g = A2 (F^T v_os)_Z2, column k of H =
- * A2 (F^T Phi_v e_k)_Z2, on the sampled elements (eq. rom-hr-sns), with the
+ * yhat (dev, B rows with leading dimension ldy >= n_x + n_v + n_e, FP64;
+ * coefficients x^, v^, e^ in window w's bases, further columns ignored)
+ * the DEIM chain's [F^1, f, H] at the lifted state (dev, B x (n_v + n_e +
+ * n_e n_v) FP64): F^1 = A1 (F.1)_Z1, f = A2 (F^T v~)_Z2 with v~ = v_os +
+ * Phi_v v^, column k of H = A2 (F^T Phi_v e_k)_Z2, on the sampled elements
+ * (eq. rom-hr-sns), with the
  * same kernels and reduction order as rom_step; a row whose lifted state is
  * tangled or not finite reads NaN.  Allocates scratch and
  * synchronises (offline call). */
-int rom_surrogate_targets(const lh_rom* r, int32_t inst, int32_t w, const double* yhat, int32_t B, double* T,
-                          hipStream_t stream);
+int rom_surrogate_targets(const lh_rom* r, int32_t inst, int32_t w, const double* yhat, int32_t ldy, int32_t B,
+                          double* T, hipStream_t stream);
 
 /* Attach network m (sizes[0] = n_x + n_v + n_e + 1, sizes[L] = n_v + n_e +
  * n_e n_v of that window) to window w of instance inst, used by rom_step
  * when LH_SURROGATE is set (m = NULL detaches).  In such a window the first
  * step and then every audit_every-th accepted step is an audit: it is taken
  * with the DEIM chain, sets the step estimate tau used by the step control
- * until the next audit, and compares the network's F^1 and F^tv at its first
- * stage with the DEIM chain's; a relative discrepancy above tol makes the
- * rest of the window use the DEIM chain (fallback).  m must outlive r's
- * use.  Not a hot call. */
+ * until the next audit, and compares the network with the DEIM chain at
+ * its first stage: d1 = |F^1_net - F^1| / (|F^1| + |s_F1|) at y^_n and
+ * d2 = |F^tv_net - F^tv| / (|F^tv| + |s_f|) at the midpoint velocity,
+ * s_F1 and s_f the network's output scales (s_out) of F^1 and f (F^tv itself
+ * vanishes where the flow is divergence free); max(d1, d2) above tol makes
+ * the rest of the window use the DEIM chain (fallback).
+ * m must outlive r's use.  Not a hot call. */
 int rom_attach_surrogate(lh_rom* r, int32_t inst, int32_t w, const lh_mlp* m, int32_t audit_every, double tol);
 
 /* ---------------------------------------------------------------- misc */

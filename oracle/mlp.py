@@ -12,10 +12,14 @@ of Sec. 3.6 and the windowed SNS system (eq. rom-hr-sns):
   y = mu_out + s_out * y~.  r() rounds an operand to bfloat16 (round to
   nearest even); every product is accumulated exactly here (FP64), in FP32 on
   the GPU.  W_l is stored (fan_in x fan_out), row-major.
-* Output: [F^1 (n_v), g (n_e), H (n_e x n_v, row-major)], so that the energy
-  right-hand side for a contraction velocity v^_c is F^tv = g + H v^_c.  This
-  is exact for the DEIM chain because F^T v_c is linear in v_c
-  (eq. forceOneforceTv) and v~_c = v_os + Phi_v v^_c.
+* Output: [F^1 (n_v), f (n_e), H (n_e x n_v, row-major)] at the state y^ =
+  (x^, v^, e^), with f the energy right-hand side at the state's own velocity,
+  so that for a contraction velocity v^_c the energy right-hand side is
+  F^tv(v^_c) = f + H (v^_c - v^).  This is exact for the DEIM chain because
+  F^T v_c is linear in v_c (eq. forceOneforceTv) and v~_c = v_os + Phi_v v^_c;
+  H only multiplies the O(dt) difference v^_c - v^, whereas f is the physical
+  quantity itself (a split into F^T v_os and H v^ would be a small difference
+  of large terms wherever the flow is nearly divergence free).
 * Loss: mean over the batch and the outputs of (y~ - t~)^2 with the targets
   normalised by the same mu_out, s_out.
 * Backward: delta_L = 2 (y~ - t~) / (B d_out); grad W_l = r(a_{l-1})^T r(delta_l);
@@ -29,7 +33,7 @@ with a network and then every K-th accepted step is an audit step, taken with
 the DEIM chain exactly as the plain ROM (``rom.rom_step``); it also supplies
 the time-step estimate tau used by the step control until the next audit, and
 compares the network's F^1 and F^tv (at the audit's first stage) with the
-DEIM chain's.  A relative discrepancy above ``tol`` switches the window to
+DEIM chain's (``audit``).  A discrepancy above ``tol`` switches the window to
 the DEIM chain for the rest of the window (fallback).
 """
 from __future__ import annotations
@@ -179,10 +183,10 @@ def split_output(win: R.WindowROM, y: np.ndarray):
 
 
 def deim_targets(op: F.Operator, win: R.WindowROM, yhat) -> np.ndarray:
-    """[F^1, g, H] of the DEIM chain at the lifted state of yhat (eq. rom-hr-sns).
+    """[F^1, f, H] of the DEIM chain at the lifted state of yhat (eq. rom-hr-sns).
 
     F^1 = A1 (F.1)_Z1 at y~ = y_os + Phi y^ on the sampled elements;
-    g = A2 (F^T v_os)_Z2 and column k of H is A2 (F^T Phi_v e_k)_Z2.
+    f = A2 (F^T v~)_Z2 with v~ = v_os + Phi_v v^ and column k of H is A2 (F^T Phi_v e_k)_Z2.
     """
     NV, NE = op.mesh.NV, op.mesh.NE
     els = win.elems
@@ -190,15 +194,13 @@ def deim_targets(op: F.Operator, win: R.WindowROM, yhat) -> np.ndarray:
                   R.lift_rows(win, 2, yhat[2], win.rows_t, NE), elems=els)
     f1 = win.A1 @ F.force_one(op, st, elems=els)[win.Z1]
     nv = win.dims[1]
-    u0 = np.zeros(NV)
-    u0[win.rows_k] = win.os[1][win.rows_k]
-    g = win.A2 @ F.force_tv(op, st, u0, elems=els)[win.Z2]
+    f = win.A2 @ F.force_tv(op, st, R.lift_rows(win, 1, yhat[1], win.rows_k, NV), elems=els)[win.Z2]
     H = np.zeros((win.dims[2], nv))
     for k in range(nv):
         u = np.zeros(NV)
         u[win.rows_k] = win.Phi[1][win.rows_k, k]
         H[:, k] = win.A2 @ F.force_tv(op, st, u, elems=els)[win.Z2]
-    return np.concatenate([f1, g, H.ravel()])
+    return np.concatenate([f1, f, H.ravel()])
 
 
 def training_set(op: F.Operator, rom: R.ROM, w: int, trajs: list, windows_of_snap: list):
@@ -244,14 +246,14 @@ class SurrogateRun:
 
 def surrogate_step(win: R.WindowROM, net: MLP, xh, vh, eh, t, dt, r=bf16):
     """One RK2-average step with the network's reduced forces (eq. RK2-avg-rom-hr)."""
-    f1, g, H = split_output(win, predict(net, net_input((xh, vh, eh), t)[None, :], r)[0])
+    f1, f, H = split_output(win, predict(net, net_input((xh, vh, eh), t)[None, :], r)[0])
     v_half = vh - 0.5 * dt * f1
-    e_half = eh + 0.5 * dt * (g + H @ v_half)
+    e_half = eh + 0.5 * dt * (f + H @ (v_half - vh))
     x_half = xh + 0.5 * dt * (win.bx + win.Bxv @ v_half)
-    f1, g, H = split_output(win, predict(net, net_input((x_half, v_half, e_half), t + 0.5 * dt)[None, :], r)[0])
+    f1, f, H = split_output(win, predict(net, net_input((x_half, v_half, e_half), t + 0.5 * dt)[None, :], r)[0])
     v_new = vh - dt * f1
     v_bar = 0.5 * (vh + v_new)
-    e_new = eh + dt * (g + H @ v_bar)
+    e_new = eh + dt * (f + H @ (v_bar - v_half))
     x_new = xh + dt * (win.bx + win.Bxv @ v_bar)
     return x_new, v_new, e_new
 
@@ -259,22 +261,30 @@ def surrogate_step(win: R.WindowROM, net: MLP, xh, vh, eh, t, dt, r=bf16):
 def audit(op: F.Operator, win: R.WindowROM, net: MLP, yhat, t, dt, r=bf16):
     """DEIM step plus the network's discrepancy at the first stage.
 
-    Returns (new state, tau, discrepancy) with discrepancy = max of the relative errors of the
-    network's F^1 and of its F^tv at the DEIM chain's midpoint velocity v^_{1/2}.
+    Returns (new state, tau, discrepancy) with discrepancy = max(d1, d2):
+    d1 = |F^1_net - F^1| / (|F^1| + |s_F1|) at y^_n and
+    d2 = |F^tv_net - F^tv| / (|F^tv| + |s_f|) at the DEIM chain's midpoint velocity v^_{1/2},
+    where s_F1 and s_f are the network's output scales (training standard deviations) of F^1 and
+    f: they keep a locally small force (F^tv vanishes where the flow is divergence free) from
+    turning an error that is small on the scale the network was trained on into a large relative one.
     """
     new, half, tau = R.rom_step(op, win, *yhat, dt)
     tgt = deim_targets(op, win, yhat)
-    f1_d, g_d, H_d = split_output(win, tgt)
-    f1_m, g_m, H_m = split_output(win, predict(net, net_input(yhat, t)[None, :], r)[0])
+    f1_d, f_d, H_d = split_output(win, tgt)
+    f1_m, f_m, H_m = split_output(win, predict(net, net_input(yhat, t)[None, :], r)[0])
     v_half = half[1]
-    ftv_d = g_d + H_d @ v_half
-    ftv_m = g_m + H_m @ v_half
+    ftv_d = f_d + H_d @ (v_half - yhat[1])
+    ftv_m = f_m + H_m @ (v_half - yhat[1])
+    nv, ne = win.dims[1], win.dims[2]
+    s_f1 = np.linalg.norm(net.s_out[:nv]) if net is not None else 0.0
+    s_f = np.linalg.norm(net.s_out[nv:nv + ne]) if net is not None else 0.0
 
-    def rel(a, b):
-        nb = np.linalg.norm(b)
-        return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
+    def rel(a, b, scale):
+        return np.linalg.norm(a - b) / scale if scale > 0 else np.linalg.norm(a - b)
 
-    return new, tau, max(rel(f1_m, f1_d), rel(ftv_m, ftv_d))
+    d1 = rel(f1_m, f1_d, np.linalg.norm(f1_d) + s_f1)
+    d2 = rel(ftv_m, ftv_d, np.linalg.norm(ftv_d) + s_f)
+    return new, tau, max(d1, d2)
 
 
 def run_surrogate(op: F.Operator, rom: R.ROM, nets: dict, y0: tuple, t_final: float, audit_every: int,

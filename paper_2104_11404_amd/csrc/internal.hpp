@@ -54,7 +54,7 @@ constexpr double ORDER_K = 2.0;
 namespace lh {
 
 // Device view of a network (bfloat16 weights with rows padded to a multiple
-// of 4 entries, FP32 biases, FP64 normalisation), read by the ROM kernels.
+// of 8 entries, FP32 biases, FP64 normalisation), read by the ROM kernels.
 struct MlpDev {
     int L;
     int sizes[LH_MLP_MAX_LAYERS + 1];

@@ -3,7 +3,7 @@
 // paper, which has no learned component).
 //
 // Layout: activations are row-major [batch][features] with rows padded to a
-// multiple of 4 entries; W_l is row-major [fan_in][fan_out padded].  The
+// multiple of 8 entries; W_l is row-major [fan_in][fan_out padded].  The
 // products are one tiled MFMA kernel (v_mfma_f32_16x16x16_bf16): a 256-thread
 // workgroup computes a 64 x 64 tile of C = A B, each wave 16 rows, with
 // 64 x 16 slices of A and B staged in LDS per step over K.  A and B are
@@ -240,6 +240,23 @@ __global__ void zero_u16_kernel(uint16_t* p, int64_t n) {
     if (t < n) p[t] = 0;
 }
 
+// Column mean and population standard deviation (rows in order; zero deviation -> 1).
+__global__ void colstats_kernel(const double* X, int B, int d, double* mu, double* sd) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= d) return;
+    double a = 0.0;
+    for (int i = 0; i < B; ++i) a += X[(int64_t)i * d + j];
+    const double mean = a / B;
+    double v = 0.0;
+    for (int i = 0; i < B; ++i) {
+        const double dx = X[(int64_t)i * d + j] - mean;
+        v += dx * dx;
+    }
+    const double s = sqrt(v / B);
+    mu[j] = mean;
+    sd[j] = s > 0.0 ? s : 1.0;
+}
+
 inline unsigned blocks(int64_t n) { return (unsigned)((n + BLK - 1) / BLK); }
 
 int gemm(const GemmArgs& a, hipStream_t s) {
@@ -386,7 +403,7 @@ int mlp_create(const lh_mlp_desc* d, int32_t max_batch, lh_mlp** out) {
     m->max_batch = max_batch;
     for (int l = 0; l <= m->L; ++l) {
         m->sizes[l] = d->sizes[l];
-        m->npad[l] = (d->sizes[l] + 3) / 4 * 4;
+        m->npad[l] = (d->sizes[l] + 7) / 8 * 8;
     }
     hipStream_t s = nullptr;
     for (int l = 0; l < m->L; ++l) {
@@ -525,6 +542,17 @@ int mlp_gradients(lh_mlp* m, const double* X, const double* T, int32_t B, float*
                                m->sizes[l + 1], m->npad[l + 1], gb[l]);
     }
     return launch_check("mlp_gradients");
+}
+
+int mlp_fit_normalisation(lh_mlp* m, const double* X, const double* T, int32_t B, hipStream_t s) {
+    using namespace lh;
+    using namespace lh::mlp;
+    LH_REQUIRE(m && X && T && B >= 1, "mlp_fit_normalisation: bad arguments");
+    hipLaunchKernelGGL(colstats_kernel, dim3(blocks(m->sizes[0])), dim3(BLK), 0, s, X, B, m->sizes[0], m->mu_in,
+                       m->s_in);
+    hipLaunchKernelGGL(colstats_kernel, dim3(blocks(m->sizes[m->L])), dim3(BLK), 0, s, T, B, m->sizes[m->L],
+                       m->mu_out, m->s_out);
+    return launch_check("mlp_fit_normalisation");
 }
 
 int mlp_train_step(lh_mlp* m, const double* X, const double* T, int32_t B, double lr, float* loss, hipStream_t s) {

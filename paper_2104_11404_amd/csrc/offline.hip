@@ -56,6 +56,52 @@ __global__ void diag_mul_kernel(const double* in, double* out, const double* __r
 }  // namespace off
 }  // namespace lh
 
+namespace lh {
+namespace off {
+
+// out[j * ldo + k] = sum_r Phi[k * ldp + r] (S[j * lds + r] - os[r]) for 8 snapshots j per
+// block and every coefficient k; rows in chunks of 64 staged in LDS, chunk sums added in order.
+__global__ void __launch_bounds__(256) project_kernel(const double* Phi, int64_t ldp, int n, const double* S,
+                                                     int64_t lds, int m, const double* os, int64_t N, double* out,
+                                                     int64_t ldo) {
+    __shared__ double sp[64][65];
+    __shared__ double ss[8][64];
+    const int j0 = blockIdx.x * 8;
+    const int tid = threadIdx.x;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t r0 = 0; r0 < N; r0 += 64) {
+        for (int t = tid; t < n * 64; t += 256) {
+            const int k = t / 64, r = t % 64;
+            sp[k][r] = r0 + r < N ? Phi[(int64_t)k * ldp + r0 + r] : 0.0;
+        }
+        for (int t = tid; t < 8 * 64; t += 256) {
+            const int j = t / 64, r = t % 64;
+            ss[j][r] = (j0 + j < m && r0 + r < N) ? S[(int64_t)(j0 + j) * lds + r0 + r] - os[r0 + r] : 0.0;
+        }
+        __syncthreads();
+        for (int q = 0; q < 2; ++q) {
+            const int pq = tid + q * 256;
+            if (pq < 8 * n) {
+                const int j = pq / n, k = pq % n;
+                double a = 0.0;
+                for (int r = 0; r < 64; ++r) a += sp[k][r] * ss[j][r];
+                acc[q] += a;
+            }
+        }
+        __syncthreads();
+    }
+    for (int q = 0; q < 2; ++q) {
+        const int pq = tid + q * 256;
+        if (pq < 8 * n) {
+            const int j = pq / n, k = pq % n;
+            if (j0 + j < m) out[(int64_t)(j0 + j) * ldo + k] = acc[q];
+        }
+    }
+}
+
+}  // namespace off
+}  // namespace lh
+
 extern "C" {
 
 int lh_snapshot_deviation(const double* snaps, int64_t N, int32_t m, int64_t ld, const double* os, double* out,
@@ -66,6 +112,18 @@ int lh_snapshot_deviation(const double* snaps, int64_t N, int32_t m, int64_t ld,
     hipLaunchKernelGGL(off::deviation_kernel, dim3((unsigned)((N + 255) / 256), m), dim3(256), 0, s, snaps, N, m, ld,
                        os, out, ldo);
     return launch_check("deviation_kernel");
+}
+
+int lh_project_snapshots(const double* Phi, int32_t n, int64_t N, int64_t ldp, const double* S, int32_t m,
+                         int64_t lds, const double* os, double* out, int64_t ldo, hipStream_t s) {
+    using namespace lh;
+    LH_REQUIRE(Phi && S && os && out && n >= 1 && n <= LH_NMAX && N > 0 && m >= 0 && ldp >= N && lds >= N &&
+                   ldo >= n,
+               "lh_project_snapshots: bad arguments");
+    if (m == 0) return LH_OK;
+    hipLaunchKernelGGL(off::project_kernel, dim3((unsigned)((m + 7) / 8)), dim3(256), 0, s, Phi, ldp, n, S, lds, m, os,
+                       N, out, ldo);
+    return launch_check("project_kernel");
 }
 
 int lh_windows_by_samples(int32_t n_params, const double* const* t_lists, const int32_t* n_steps, int32_t n_sample,

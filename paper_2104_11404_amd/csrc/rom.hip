@@ -495,7 +495,7 @@ __device__ void x_update(const WinDev& W, const Local<TT>& L, const double* base
 inline int mlp_scratch_floats(const MlpDev& N) {
     int wmax = N.npad[0];
     for (int l = 1; l < N.L; ++l) wmax = std::max(wmax, N.npad[l]);
-    return (2 * wmax + 4 * BLK + N.npad[N.L] + 3) / 4 * 4;
+    return (2 * wmax + 8 * BLK + N.npad[N.L] + 3) / 4 * 4;
 }
 
 // out[0..d_out) = normalised output of the network at [x^, v^, e^, t]
@@ -509,7 +509,7 @@ __device__ void mlp_eval(const MlpDev& N, const double* yx, const double* yv, co
     float* in = scr;
     float* nxt = scr + wmax;
     float* red = scr + 2 * wmax;
-    out = red + 4 * BLK;
+    out = red + 8 * BLK;
     const int nx = n[0], nv = n[1], ne = n[2];
     for (int j = tid; j < N.sizes[0]; j += BLK) {
         const double x = j < nx ? yx[j] : j < nx + nv ? yv[j - nx] : j < nx + nv + ne ? ye[j - nx - nv] : t;
@@ -520,36 +520,53 @@ __device__ void mlp_eval(const MlpDev& N, const double* yx, const double* yv, co
         const int K = N.sizes[l], Nn = N.sizes[l + 1], ld = N.npad[l + 1];
         const bool last = l == N.L - 1;
         float* dst = last ? out : nxt;
-        const int nq = ld / 4;
-        const int KS = nq >= BLK ? 1 : min(BLK / nq, 4);
+        const int nq = ld / 8;  // groups of 8 outputs
+        const int KS = nq >= BLK ? 1 : min(BLK / nq, 8);
         const int kc = (K + KS - 1) / KS;
         const uint16_t* Wl = N.W[l];
         for (int tt = tid; tt < nq * KS; tt += BLK) {
             const int jq = tt % nq, ks = tt / nq;
             const int k1 = min(K, (ks + 1) * kc);
-            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-            for (int k = ks * kc; k < k1; ++k) {
+            float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            const uint16_t* wp = Wl + 8 * jq;
+            int k = ks * kc;
+            // eight independent 16-byte weight loads in flight per thread
+            for (; k + 8 <= k1; k += 8) {
+                uint4 wv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) wv[u] = *reinterpret_cast<const uint4*>(wp + (int64_t)(k + u) * ld);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const float x = in[k + u];
+                    const uint32_t w4[4] = {wv[u].x, wv[u].y, wv[u].z, wv[u].w};
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        a[2 * h] += x * bf16_to_f32((uint16_t)(w4[h] & 0xFFFFu));
+                        a[2 * h + 1] += x * bf16_to_f32((uint16_t)(w4[h] >> 16));
+                    }
+                }
+            }
+            for (; k < k1; ++k) {
                 const float x = in[k];
-                const uint2 wv = *reinterpret_cast<const uint2*>(Wl + (int64_t)k * ld + 4 * jq);
-                a0 += x * bf16_to_f32((uint16_t)(wv.x & 0xFFFFu));
-                a1 += x * bf16_to_f32((uint16_t)(wv.x >> 16));
-                a2 += x * bf16_to_f32((uint16_t)(wv.y & 0xFFFFu));
-                a3 += x * bf16_to_f32((uint16_t)(wv.y >> 16));
+                const uint4 wv = *reinterpret_cast<const uint4*>(wp + (int64_t)k * ld);
+                const uint32_t w4[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    a[2 * h] += x * bf16_to_f32((uint16_t)(w4[h] & 0xFFFFu));
+                    a[2 * h + 1] += x * bf16_to_f32((uint16_t)(w4[h] >> 16));
+                }
             }
             if (KS == 1) {  // whole dot products: finish here (wide layers)
-                const float av[4] = {a0, a1, a2, a3};
-                for (int i = 0; i < 4; ++i) {
-                    const int j = 4 * jq + i;
+                for (int i = 0; i < 8; ++i) {
+                    const int j = 8 * jq + i;
                     if (j >= Nn) break;
-                    const float v = av[i] + N.b[l][j];
+                    const float v = a[i] + N.b[l][j];
                     dst[j] = last ? v : bf16_to_f32(f32_to_bf16(tanhf(v)));
                 }
-            } else {  // KS * ld <= 4 BLK partial sums
-                float* r = red + ks * ld + 4 * jq;
-                r[0] = a0;
-                r[1] = a1;
-                r[2] = a2;
-                r[3] = a3;
+            } else {  // KS * ld <= 8 BLK partial sums
+                float* r = red + ks * ld + 8 * jq;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) r[i] = a[i];
             }
         }
         __syncthreads();
@@ -574,29 +591,46 @@ __device__ void mlp_f1(const MlpDev& N, const float* out, int nv, double* f1h) {
     __syncthreads();
 }
 
-// F^tv = g + H v^_c of the network into ftvh.
-__device__ void mlp_ftv(const MlpDev& N, const float* out, int nv, int ne, const double* vc, double* ftvh) {
-    for (int i = threadIdx.x; i < ne; i += BLK) {
+// F^tv = f + H (v^_c - v^_ref) of the network into ftvh (f, H taken at the state whose velocity
+// is v^_ref): thread (i, c) sums chunk c of row i of the product, then the chunks are added in
+// order (red: BLK doubles).
+__device__ void mlp_ftv(const MlpDev& N, const float* out, int nv, int ne, const double* vc, const double* vref,
+                        double* ftvh, double* red) {
+    const int tid = threadIdx.x;
+    const int nc = max(1, BLK / ne);
+    const int cl = (nv + nc - 1) / nc;
+    if (tid < nc * ne) {
+        const int i = tid % ne, c = tid / ne;
+        const int k1 = min(nv, (c + 1) * cl);
+        double acc = 0.0;
+        for (int k = c * cl; k < k1; ++k) {
+            const int jh = nv + ne + i * nv + k;
+            acc += (N.mu_out[jh] + N.s_out[jh] * (double)out[jh]) * (vc[k] - vref[k]);
+        }
+        red[c * ne + i] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < ne; i += BLK) {
         const int jg = nv + i;
         double acc = N.mu_out[jg] + N.s_out[jg] * (double)out[jg];
-        for (int k = 0; k < nv; ++k) {
-            const int jh = nv + ne + i * nv + k;
-            acc += (N.mu_out[jh] + N.s_out[jh] * (double)out[jh]) * vc[k];
-        }
+        for (int c = 0; c < nc; ++c) acc += red[c * ne + i];
         ftvh[i] = acc;
     }
     __syncthreads();
 }
 
-// Relative discrepancy |a - b| / |b| of two LDS vectors (thread 0 sums in order).
-__device__ double rel_disc(const double* a, const double* b, int n, double* red) {
+// |a - b| / (|b| + |s|) of two LDS vectors, s the network's output scales of that quantity
+// (thread 0 sums in order).
+__device__ double rel_disc(const double* a, const double* b, const double* sc, int n, double* red) {
     if (threadIdx.x == 0) {
-        double d = 0.0, r = 0.0;
+        double d = 0.0, r = 0.0, q = 0.0;
         for (int i = 0; i < n; ++i) {
             d += (a[i] - b[i]) * (a[i] - b[i]);
             r += b[i] * b[i];
+            q += sc[i] * sc[i];
         }
-        red[0] = r > 0.0 ? sqrt(d / r) : sqrt(d);
+        const double den = sqrt(r) + sqrt(q);
+        red[0] = den > 0.0 ? sqrt(d) / den : sqrt(d);
     }
     __syncthreads();
     const double v = red[0];
@@ -688,7 +722,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             mlp_f1(W.net, out, W.n[1], S.f1h);
             for (int i = tid; i < W.n[1]; i += BLK) S.yh[1][i] = S.y[1][i] - 0.5 * h * S.f1h[i];
             __syncthreads();
-            mlp_ftv(W.net, out, W.n[1], W.n[2], S.yh[1], S.ftvh);
+            mlp_ftv(W.net, out, W.n[1], W.n[2], S.yh[1], S.y[1], S.ftvh, S.red);
             for (int i = tid; i < W.n[2]; i += BLK) S.yh[2][i] = S.y[2][i] + 0.5 * h * S.ftvh[i];
             x_update(W, L, S.y[0], 0.5 * h, S.yh[1], S.yh[0]);
             __syncthreads();
@@ -700,7 +734,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
                 S.vc[i] = 0.5 * (S.y[1][i] + vn);
             }
             __syncthreads();
-            mlp_ftv(W.net, out, W.n[1], W.n[2], S.vc, S.ftvh);
+            mlp_ftv(W.net, out, W.n[1], W.n[2], S.vc, S.yh[1], S.ftvh, S.red);
             for (int i = tid; i < W.n[2]; i += BLK) S.yn[2][i] = S.y[2][i] + h * S.ftvh[i];
             x_update(W, L, S.y[0], h, S.vc, S.yn[0]);
             __syncthreads();
@@ -722,9 +756,9 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             float* out;
             mlp_eval(W.net, S.y[0], S.y[1], S.y[2], W.n, t, mscr, out);
             mlp_f1(W.net, out, W.n[1], S.tmp);
-            const double d1 = rel_disc(S.tmp, S.f1h, W.n[1], S.red);
-            mlp_ftv(W.net, out, W.n[1], W.n[2], S.yh[1], S.tmp);
-            const double d2 = rel_disc(S.tmp, S.ftvh, W.n[2], S.red);
+            const double d1 = rel_disc(S.tmp, S.f1h, W.net.s_out, W.n[1], S.red);
+            mlp_ftv(W.net, out, W.n[1], W.n[2], S.yh[1], S.y[1], S.tmp, S.red);
+            const double d2 = rel_disc(S.tmp, S.ftvh, W.net.s_out + W.n[1], W.n[2], S.red);
             ++n_audits;
             if (!(fmax(d1, d2) <= W.tol) || isnan(d1) || isnan(d2)) {
                 fallen = 1;
@@ -849,13 +883,13 @@ __device__ Local<double> global_local(const WinDev& W, const WgView& V, double* 
     return L;
 }
 
-// One workgroup per sample: [F^1, g, H] of the DEIM chain at y^ (window w), with
+// One workgroup per sample: [F^1, f, H] of the DEIM chain at y^ (window w), with
 // every view of the window evaluated in turn and the shares combined in the same
 // order as rom_step.  zeros: n_el * NKD zeros (velocity offset left out for H).
 template <int DIM>
-__global__ void __launch_bounds__(BLK) targets_kernel(RomArgs A, const InstDev* Ip, int w, const double* yhat, int B,
-                                                      int s0, double* T, double* scr_share, double* scr_sig,
-                                                      const double* zeros) {
+__global__ void __launch_bounds__(BLK) targets_kernel(RomArgs A, const InstDev* Ip, int w, const double* yhat,
+                                                      int ldy, int B, int s0, double* T, double* scr_share,
+                                                      double* scr_sig, const double* zeros) {
     constexpr int NKD = Cfg<DIM>::NKD, NQ = Cfg<DIM>::NQ, DD = Cfg<DIM>::DD;
     extern __shared__ double dyn_raw[];
     __shared__ NodeBuf<DIM> Bn;
@@ -875,7 +909,7 @@ __global__ void __launch_bounds__(BLK) targets_kernel(RomArgs A, const InstDev* 
     double* share = scr_share + (int64_t)blockIdx.x * G * PSTRIDE;
     double* sig = scr_sig + (int64_t)blockIdx.x * W.n_el * NQ * DD;
     for (int f = 0, off = 0; f < 3; off += W.n[f], ++f)
-        for (int k = tid; k < LH_NMAX; k += BLK) S.y[f][k] = k < W.n[f] ? yhat[(int64_t)smp * din + off + k] : 0.0;
+        for (int k = tid; k < LH_NMAX; k += BLK) S.y[f][k] = k < W.n[f] ? yhat[(int64_t)smp * ldy + off + k] : 0.0;
     if (tid == 0) s_status = 0;
     __syncthreads();
     double* out = T + (int64_t)smp * dout;
@@ -889,9 +923,9 @@ __global__ void __launch_bounds__(BLK) targets_kernel(RomArgs A, const InstDev* 
     __syncthreads();
     combine(share, G, nv, S.f1h, &s_status, S, stage);
     for (int i = tid; i < nv; i += BLK) out[i] = S.f1h[i];
-    // columns: k = -1 gives g (offset velocity), k >= 0 gives H e_k (no offset)
+    // k = -1 gives f (the state's own velocity), k >= 0 column k of H (e_k, no offset)
     for (int k = -1; k < nv; ++k) {
-        for (int i = tid; i < LH_NMAX; i += BLK) S.vc[i] = (i == k) ? 1.0 : 0.0;
+        for (int i = tid; i < LH_NMAX; i += BLK) S.vc[i] = k < 0 ? S.y[1][i] : (i == k) ? 1.0 : 0.0;
         __syncthreads();
         for (int g = 0; g < G; ++g) {
             Local<double> L = global_local<DIM>(W, W.views[g], sig);
@@ -1554,8 +1588,8 @@ int rom_attach_surrogate(lh_rom* R, int32_t inst, int32_t w, const lh_mlp* m, in
     return LH_OK;
 }
 
-int rom_surrogate_targets(const lh_rom* R, int32_t inst, int32_t w, const double* yhat, int32_t B, double* T,
-                          hipStream_t s) {
+int rom_surrogate_targets(const lh_rom* R, int32_t inst, int32_t w, const double* yhat, int32_t ldy, int32_t B,
+                          double* T, hipStream_t s) {
     using namespace lh;
     using namespace lh::rom;
     LH_REQUIRE(R && yhat && T && B >= 0, "rom_surrogate_targets: bad arguments");
@@ -1564,6 +1598,7 @@ int rom_surrogate_targets(const lh_rom* R, int32_t inst, int32_t w, const double
     if (B == 0) return LH_OK;
     const lh_problem* p = R->p;
     const WinDev& D = R->h_win[inst][w];
+    LH_REQUIRE(ldy >= D.n[0] + D.n[1] + D.n[2], "rom_surrogate_targets: ldy < n_x + n_v + n_e");
     const int dim = p->dim;
     const int NQ = dim == 2 ? 16 : 64, DD = dim * dim, NKD = dim * (dim == 2 ? 9 : 27);
     const int CH = std::min<int>(B, 512);
@@ -1605,13 +1640,13 @@ int rom_surrogate_targets(const lh_rom* R, int32_t inst, int32_t w, const double
             if (dyn > 0 && hipFuncSetAttribute((const void*)targets_kernel<2>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess)
                 rc = LH_EDEVICE;
-            hipLaunchKernelGGL(targets_kernel<2>, dim3(nb_), dim3(BLK), dyn, s, A, R->d_inst + inst, w, yhat, B, s0, T,
+            hipLaunchKernelGGL(targets_kernel<2>, dim3(nb_), dim3(BLK), dyn, s, A, R->d_inst + inst, w, yhat, ldy, B, s0, T,
                                share, sig, (const double*)zeros);
         } else {
             if (dyn > 0 && hipFuncSetAttribute((const void*)targets_kernel<3>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess)
                 rc = LH_EDEVICE;
-            hipLaunchKernelGGL(targets_kernel<3>, dim3(nb_), dim3(BLK), dyn, s, A, R->d_inst + inst, w, yhat, B, s0, T,
+            hipLaunchKernelGGL(targets_kernel<3>, dim3(nb_), dim3(BLK), dyn, s, A, R->d_inst + inst, w, yhat, ldy, B, s0, T,
                                share, sig, (const double*)zeros);
         }
         if (!rc) rc = launch_check("targets_kernel");

@@ -104,7 +104,9 @@ _SIGNATURES = {
     "mlp_forward": (_I32, [_VP, _VP, _I32, _VP, _VP, _VP]),
     "mlp_gradients": (_I32, [_VP, _VP, _VP, _I32, _VP, _VP, _VP, _VP]),
     "mlp_train_step": (_I32, [_VP, _VP, _VP, _I32, _D, _VP, _VP]),
-    "rom_surrogate_targets": (_I32, [_VP, _I32, _I32, _VP, _I32, _VP, _VP]),
+    "rom_surrogate_targets": (_I32, [_VP, _I32, _I32, _VP, _I32, _I32, _VP, _VP]),
+    "mlp_fit_normalisation": (_I32, [_VP, _VP, _VP, _I32, _VP]),
+    "lh_project_snapshots": (_I32, [_VP, _I32, _I64, _I64, _VP, _I32, _I64, _VP, _VP, _I64, _VP]),
     "rom_attach_surrogate": (_I32, [_VP, _I32, _I32, _VP, _I32, _D]),
     "lh_snapshot_deviation": (_I32, [_VP, _I64, _I32, _I64, _VP, _VP, _I64, _VP]),
     "lh_mass_apply_v": (_I32, [_VP, _VP, _VP, _VP]),
@@ -446,16 +448,33 @@ class Mlp:
                                     stream_handle()))
         return gW, gb, loss
 
+    def fit_normalisation(self, X, T):
+        _check(load().mlp_fit_normalisation(self.h, ptr(X), ptr(T), int(X.shape[0]), stream_handle()))
+
     def train_step(self, X, T, lr, loss=None):
         _check(load().mlp_train_step(self.h, ptr(X), ptr(T), int(X.shape[0]), float(lr), ptr(loss),
                                      stream_handle()))
 
 
 def rom_surrogate_targets(rom, inst, w, yhat):
-    """DEIM-chain targets [F^1, g, H] (B x (n_v + n_e + n_e n_v)) at reduced states yhat (B x (n_x + n_v + n_e))."""
+    """DEIM-chain targets [F^1, f, H] (B x (n_v + n_e + n_e n_v)) at reduced states yhat (B rows starting with
+    x^, v^, e^; further columns are ignored)."""
     wd = rom.instances[inst]["windows"][w]
     nv, ne = (int(wd["phi"][f].shape[0]) for f in (1, 2))
     B = int(yhat.shape[0])
     T = torch.empty((B, nv + ne + ne * nv), dtype=torch.float64, device="cuda")
-    _check(load().rom_surrogate_targets(rom.h, int(inst), int(w), ptr(yhat), B, ptr(T), stream_handle()))
+    _check(load().rom_surrogate_targets(rom.h, int(inst), int(w), ptr(yhat), int(yhat.shape[1]), B, ptr(T),
+                                        stream_handle()))
     return T
+
+
+def project_snapshots(Phi, S, os, out=None, col=0):
+    """out[:, col:col+n] = (S - os) Phi^T for Phi (n, N) and snapshot rows S (m, N)."""
+    n, N = (int(x) for x in Phi.shape)
+    m = int(S.shape[0])
+    if out is None:
+        out = torch.empty((m, n), dtype=torch.float64, device="cuda")
+    ldo = int(out.shape[1])
+    _check(load().lh_project_snapshots(ptr(Phi), n, N, N, ptr(S), m, int(S.shape[1]), ptr(os),
+                                       C.c_void_p(out.data_ptr() + 8 * col), ldo, stream_handle()))
+    return out

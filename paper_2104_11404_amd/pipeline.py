@@ -55,8 +55,12 @@ def fom_trajectory(P: lib.Problem, t_final: float, fixed_dt: float = 0.0, max_st
 
 
 def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_frac=0.9999, n_fixed=(), n_max=64,
-                  lam=(2.0, 2.0), t_final=None, verbose=False):
-    """Per-window POD, SNS and DEIM on the GPU; returns a lib.Rom instance description."""
+                  lam=(2.0, 2.0), t_final=None, verbose=False, snapshot_offsets=None):
+    """Per-window POD, SNS and DEIM on the GPU; returns a lib.Rom instance description.
+
+    Snapshots are taken relative to each trajectory's own initial state, or to snapshot_offsets
+    (one (x, v, e) for every trajectory) when given.
+    """
     so = lib.load()
     stream = lib.stream_handle()
     sizes = (P.NV, P.NV, P.NE)
@@ -71,7 +75,7 @@ def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_f
             off = 0
             for tr, (first, ncol) in zip(trajs, cols):
                 snaps = tr["snaps"][f]
-                os_ = tr["y0"][f]
+                os_ = tr["y0"][f] if snapshot_offsets is None else snapshot_offsets[f]
                 lib._check(so.lh_snapshot_deviation(lib.ptr(snaps[first[w]:first[w] + ncol[w]]) if ncol[w] else
                                                     lib.ptr(snaps), N, ncol[w], N, lib.ptr(os_),
                                                     C.c_void_p(S.data_ptr() + 8 * off * N), N, stream))
@@ -122,3 +126,66 @@ def build_batch(wl, lam=(2.0, 2.0), energy_frac=0.9999, verbose=False):
             print(f"[batch] instance {i}: {traj['n_steps']} FOM steps, windows {len(T)}, dims {dims}", flush=True)
         del traj
     return insts, y0s, finals, steps
+
+
+def snapshot_times(traj) -> list:
+    """Times of the recorded states: stage n+1/2 at t_n + dt_n / 2, step n+1 at t_{n+1}."""
+    out = []
+    for n, h in enumerate(traj["dt"]):
+        out += [traj["t"][n] + 0.5 * h, traj["t"][n + 1]]
+    return out
+
+
+def surrogate_inputs(rom, inst, w, trajs, t_start=-1.0):
+    """[x^, v^, e^, t] of every snapshot of trajs with t_start < t <= window end, in window w's bases."""
+    wd = rom.instances[inst]["windows"][w]
+    n = [int(p.shape[0]) for p in wd["phi"]]
+    din = sum(n) + 1
+    rows, times = [], []
+    for k, tr in enumerate(trajs):
+        for j, t in enumerate(snapshot_times(tr)):
+            if t_start < t <= wd["t_end"] * (1 + 1e-12):
+                rows.append((k, j))
+                times.append(t)
+    X = torch.empty((len(rows), din), dtype=torch.float64, device="cuda")
+    r0 = 0
+    for k, tr in enumerate(trajs):
+        js = [j for kk, j in rows if kk == k]
+        if not js:
+            continue
+        j0, j1 = js[0], js[-1] + 1  # contiguous by construction (times increase)
+        for f in range(3):
+            lib.project_snapshots(wd["phi"][f], tr["snaps"][f][j0:j1], wd["os"][f], out=X[r0:r0 + (j1 - j0)],
+                                  col=sum(n[:f]))
+        r0 += j1 - j0
+    X[:, din - 1] = torch.tensor(times, dtype=torch.float64, device="cuda")
+    return X
+
+
+def train_surrogate(rom, inst, w, X, hidden=(256, 256, 256), steps=3000, lr=1e-3, seed=0, lr_final=None):
+    """Train the window's network on the GPU, full batch, on inputs X and the DEIM chain's targets.
+
+    Weights start from a uniform Glorot draw of numpy's PCG64(seed), biases at zero; Adam with the
+    learning rate decayed geometrically from lr to lr_final over the steps.  Returns (Mlp, targets,
+    [loss every 100 steps]).
+    """
+    import numpy as np
+
+    T = lib.rom_surrogate_targets(rom, inst, w, X)
+    din, dout = int(X.shape[1]), int(T.shape[1])
+    sizes = [din, *hidden, dout]
+    g = np.random.Generator(np.random.PCG64(seed))
+    Ws = [torch.from_numpy(g.uniform(-np.sqrt(6.0 / (a + b)), np.sqrt(6.0 / (a + b)), (a, b))).cuda()
+          for a, b in zip(sizes[:-1], sizes[1:])]
+    bs = [torch.zeros(b, dtype=torch.float64, device="cuda") for b in sizes[1:]]
+    m = lib.Mlp(sizes, int(X.shape[0]))
+    m.set_params(Ws, bs)
+    m.fit_normalisation(X, T)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    hist = []
+    decay = 1.0 if lr_final is None else (lr_final / lr) ** (1.0 / max(1, steps - 1))
+    for k in range(steps):
+        m.train_step(X, T, lr * decay ** k, loss)
+        if k % 100 == 0 or k == steps - 1:
+            hist.append(float(loss))
+    return m, T, hist

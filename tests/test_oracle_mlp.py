@@ -108,7 +108,7 @@ def test_targets_are_the_deim_chain_and_linear_in_the_contraction_velocity(tg_ro
     win = rom.windows[0]
     g = np.random.default_rng(5)
     yh = tuple(0.1 * g.normal(0, 1, n) for n in win.dims)
-    f1, gg, H = M.split_output(win, M.deim_targets(op, win, yh))
+    f1, ff, H = M.split_output(win, M.deim_targets(op, win, yh))
     # F^1 as the ROM step uses it: v_{1/2} = v^ - dt/2 F^1
     dt = 1e-4
     _, half, _ = R.rom_step(op, win, *yh, dt)
@@ -117,10 +117,9 @@ def test_targets_are_the_deim_chain_and_linear_in_the_contraction_velocity(tg_ro
     NV, NE = op.mesh.NV, op.mesh.NE
     st = F.stress(op, R.lift_rows(win, 0, yh[0], win.rows_k, NV), R.lift_rows(win, 1, yh[1], win.rows_k, NV),
                   R.lift_rows(win, 2, yh[2], win.rows_t, NE), elems=win.elems)
-    for _ in range(3):
-        vc = g.normal(0, 1, win.dims[1])
+    for vc in [yh[1]] + [g.normal(0, 1, win.dims[1]) for _ in range(3)]:
         direct = win.A2 @ F.force_tv(op, st, R.lift_rows(win, 1, vc, win.rows_k, NV), elems=win.elems)[win.Z2]
-        np.testing.assert_allclose(gg + H @ vc, direct, rtol=1e-10, atol=1e-12 * np.linalg.norm(direct))
+        np.testing.assert_allclose(ff + H @ (vc - yh[1]), direct, rtol=1e-10, atol=1e-12 * np.linalg.norm(direct))
 
 
 def test_surrogate_step_with_exact_targets_is_the_deim_step(tg_rom, monkeypatch):
@@ -163,3 +162,21 @@ def test_training_set_inputs_are_projected_snapshots(tg_rom):
     j = 7
     x, v, e = tr.snaps[j]
     np.testing.assert_allclose(X[j, :win.dims[0]], win.Phi[0].T @ (x - win.os[0]), rtol=1e-12, atol=1e-15)
+
+
+def test_audit_of_exact_targets_has_no_discrepancy(tg_rom, monkeypatch):
+    op, tr, y0, rom = tg_rom
+    win = rom.windows[0]
+    yh = tuple(0.05 * np.random.default_rng(8).normal(0, 1, n) for n in win.dims)
+
+    def exact(net, X, r=None):
+        row = X[0]
+        nx, nv, ne = win.dims
+        return M.deim_targets(op, win, (row[:nx], row[nx:nx + nv], row[nx + nv:nx + nv + ne]))[None, :]
+
+    monkeypatch.setattr(M, "predict", exact)
+    new, tau, disc = M.audit(op, win, None, yh, 0.0, 2e-4)
+    ref, _, tau_ref = R.rom_step(op, win, *yh, 2e-4)
+    assert disc < 1e-12 and tau == tau_ref
+    for a, b in zip(new, ref):
+        np.testing.assert_array_equal(a, b)

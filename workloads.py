@@ -101,6 +101,20 @@ def sedov3d(n: int = 32, t_final: float = 0.8) -> Workload:
                     n_windows=20, energy=0.25)
 
 
+def tg2d_param(n: int = 32, t_final: float = 0.2, n_inst: int = 64, seed: int = SEED) -> Workload:
+    """Parametric 2D Taylor-Green: amplitude A ~ U[0.8, 1.2] per instance, training at 0.8, 1.0, 1.2.
+
+    Fixed dt = 1e-3, one window, dims 20/20/20, lambda = 2; bases shared by every instance with the
+    nominal (A = 1) initial state as offset, so the reduced initial state carries the amplitude.
+    """
+    amps = rng(seed).uniform(0.8, 1.2, n_inst)
+    return Workload("tg2d_param", TAYLOR_GREEN, 2, (n, n), (0.0, 0.0), (1.0, 1.0), 5.0 / 3.0, True, 0.5, t_final,
+                    fixed_dt=1e-3, n_windows=1, n_fixed=(20, 20, 20), params=tuple(dict(amp=float(a)) for a in amps))
+
+
+TG_TRAIN_AMPS = (0.8, 1.0, 1.2)  # training amplitudes of the parametric Taylor-Green problems
+
+
 def rng(seed: int = SEED) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
