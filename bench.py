@@ -53,6 +53,24 @@ def rom_step_bytes(inst, st_counts, dim=2):
     return out
 
 
+def measured_traffic():
+    """HBM bytes per rom_step_kernel launch from the committed counter runs, or None when the
+    kernel's sources have changed since those counters were taken."""
+    import hashlib
+    import re
+
+    prof = os.path.join(ROOT, "profiles", "rom_step_kernel_sedov2d_64x64_traffic.md")
+    if not os.path.exists(prof):
+        return None
+    m = re.search(r"traffic_bytes_per_launch=(\d+) source_sha1=([0-9a-f]+)", open(prof).read())
+    if not m:
+        return None
+    h = hashlib.sha1()
+    for f in ("rom.hip", "internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2104_11404_amd", "csrc", f), "rb").read())
+    return float(m.group(1)) if h.hexdigest() == m.group(2) else None
+
+
 def cpu_baseline(wl, dims, evals_per_step, seconds: float = 12.0, n_pre: int = 24):
     """The oracle's ROM step, timed on the host on a bounded sample of the same problem.
 
@@ -406,7 +424,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "bytes_per_launch": bytes_per_launch,
             "avg_kernel_ms": avg_kernel_s * 1e3,
         },

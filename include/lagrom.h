@@ -282,7 +282,7 @@ int rom_init_state(const lh_rom* r, const lh_instance_desc* inst, const double* 
  * each instance is advanced by G workgroups (rom_workgroups_per_instance)
  * that split its sampled elements and exchange per-stage partial reduced
  * forces through device memory, combined in a fixed order so that results
- * are bitwise reproducible; windows switch on device (eq. ic-tw).  With
+ * are bitwise reproducible; windows switch on device (eq. ic-tw) once t >= T_w (1 - 1e-12).  With
  * G > 1 the launch is cooperative (every workgroup resident); a partner that
  * does not arrive within a bounded wait sets LH_FLAG_TIMEOUT.  flags: LH_REPLAY_DT uses dt_replay (dev, n_replay steps,
  * shared by all instances), LH_FIXED_DT keeps state.dt fixed,

@@ -336,7 +336,7 @@ def run_surrogate(op: F.Operator, rom: R.ROM, nets: dict, y0: tuple, t_final: fl
         since += 1
         run.t.append(t)
         run.dt.append(h)
-        while w + 1 < len(rom.windows) and t >= rom.windows[w].T_end:
+        while w + 1 < len(rom.windows) and R.reached(t, rom.windows[w].T_end):
             w += 1
             yhat = R.switch_window(rom, w, yhat)
             since = 0

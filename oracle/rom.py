@@ -15,8 +15,9 @@ second.  The FOM state is lifted only at the dofs of the sampled elements
 from the same controller as the FOM, evaluated on the lifted state at the
 sampled elements' quadrature points.
 
-On entering window w the reduced coordinates are re-expressed in the new
-basis by lifting with the old one and projecting (eq. ic-tw):
+On entering window w (once t >= T_w up to a relative 1e-12, see ``reached``)
+the reduced coordinates are re-expressed in the new basis by lifting with the
+old one and projecting (eq. ic-tw):
 y^w = Phi_w^T (y_os^{w-1} + Phi_{w-1} y^{w-1} - y_os^w).
 
 The relative error at the final time is the Euclidean one of eq. relerrors.
@@ -178,6 +179,20 @@ def switch_window(rom: ROM, w: int, yhat: tuple) -> tuple:
     return tuple(win.trans[f][0] @ yhat[f] + win.trans[f][1] for f in range(3))
 
 
+SWITCH_RTOL = 1e-12
+
+
+def reached(t: float, T_end: float) -> bool:
+    """Whether the online time t has reached the window end T_end.
+
+    Windows chosen by number of snapshots end at FOM step times, which a ROM
+    that reproduces the FOM's step sizes meets up to rounding; t within
+    SWITCH_RTOL relative below T_end counts as reaching it, so that the switch
+    does not depend on the last bits of the accumulated time.
+    """
+    return t >= T_end * (1.0 - SWITCH_RTOL)
+
+
 def run_rom(op: F.Operator, rom: ROM, y0: tuple, t_final: float, dt_replay=None, fixed_dt=None,
             max_steps=10**7) -> ROMRun:
     """Online phase from t = 0 to t_final (same step control as the FOM)."""
@@ -209,7 +224,7 @@ def run_rom(op: F.Operator, rom: ROM, y0: tuple, t_final: float, dt_replay=None,
         run.t.append(t)
         run.dt.append(h)
         run.window_of_step.append(w)
-        while w + 1 < len(rom.windows) and t >= rom.windows[w].T_end:
+        while w + 1 < len(rom.windows) and reached(t, rom.windows[w].T_end):
             w += 1
             yhat = switch_window(rom, w, yhat)
     run.w = w

@@ -810,7 +810,9 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         ++since;
         // window change (eq. ic-tw): y^w = T_w y^{w-1} + c_w
         bool moved = false;
-        while (w + 1 < I.n_windows && t >= I.win[w].t_end) {
+        // a window ends at T_w; a time within 1e-12 relative below T_w has reached it (window
+        // ends chosen by snapshot count are FOM step times, met by the ROM up to rounding)
+        while (w + 1 < I.n_windows && t >= I.win[w].t_end * (1.0 - 1e-12)) {
             const WinDev& Wn = I.win[w + 1];
             const WinDev& Wo = I.win[w];
             for (int f = 0; f < 3; ++f) {

@@ -1,0 +1,79 @@
+"""3D hexahedral ROM on the GPU against the oracle (MI355X): the same persistent rom_step
+kernel instantiated for Q2-Q1 hexahedra (27 kinematic nodes, 8 energy dofs, 64 quadrature points)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fom as F
+from oracle import mlp as M
+from oracle import rom as R
+from oracle.problems import initial_state
+from oracle.windows import windows_by_samples
+from tests.oracle_adapter import oracle_problem
+from tests.test_gpu_rom import _gpu_rom, _t, gpu_instance, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tg3():
+    wl = W.replace(W.tg3d(4), t_final=0.004, n_fixed=(5, 5, 5))
+    op = F.build_operator(oracle_problem(wl))
+    tr = F.run_fom(op, wl.t_final, fixed_dt=2e-4)
+    y0 = initial_state(op.prob)
+    rom = R.build_rom(op, [tr], [y0], [wl.t_final], n_fixed=wl.n_fixed, lam=(2, 2))
+    return wl, op, tr, y0, rom
+
+
+def test_rom3d_fixed_dt_matches_oracle(gpu_lib, tg3):
+    from paper_2104_11404_amd import lib
+    wl, op, tr, y0, rom = tg3
+    print(f"[case] rom 3d tg 4^3 fixed dt, {len(rom.windows[0].elems)} sampled elements", flush=True)
+    run = R.run_rom(op, rom, y0, wl.t_final, fixed_dt=2e-4)
+    P, G = _gpu_rom(wl, [(rom, wl.t_final)], [y0], dt0=2e-4)
+    G.step(flags=lib.LH_FIXED_DT)
+    st = G.states()[0]
+    assert st.status == 0 and st.n_steps == len(run.dt)
+    for a, b in zip(G.coords(0), run.yhat):
+        assert rel(a, b) < 1e-10
+    P2, G2 = _gpu_rom(wl, [(rom, wl.t_final)], [y0], dt0=2e-4)
+    G2.step(flags=lib.LH_FIXED_DT | lib.LH_FP32_LIFT)
+    for a, b in zip(G2.lift(0), R.final_lift(rom, run)):
+        assert rel(a.cpu().numpy(), b) < 1e-5
+
+
+@pytest.mark.parametrize("per_wg", [None, "2"])
+def test_rom3d_sedov_windows_adaptive(gpu_lib, monkeypatch, per_wg):
+    from paper_2104_11404_amd import lib
+    if per_wg:
+        monkeypatch.setenv("LAGROM_ELEMS_PER_WG", per_wg)
+    wl = W.replace(W.sedov3d(4), t_final=0.05)
+    op = F.build_operator(oracle_problem(wl))
+    tr = F.run_fom(op, wl.t_final)
+    y0 = initial_state(op.prob)
+    T = windows_by_samples([tr.t], 2 * int(np.ceil(len(tr.dt) / 2)))
+    rom = R.build_rom(op, [tr], [y0], T, energy_frac=0.9999, n_max=12, lam=(2, 2))
+    run = R.run_rom(op, rom, y0, wl.t_final)
+    P, G = _gpu_rom(wl, [(rom, wl.t_final)], [y0])
+    g = lib._I32()
+    lib._check(lib.load().rom_workgroups_per_instance(G.h, lib.C.byref(g)))
+    print(f"[case] rom 3d sedov 4^3 windows={len(rom.windows)} G={g.value} steps={len(run.dt)}", flush=True)
+    G.step()
+    st = G.states()[0]
+    assert st.status == 0 and st.done == 1
+    assert st.n_steps == len(run.dt) and st.n_rejected == run.rejections and st.w == run.w
+    for a, b in zip(G.coords(0), run.yhat):
+        assert rel(a, b) < 1e-9
+
+
+def test_surrogate_targets_3d_match_oracle(gpu_lib, tg3):
+    from paper_2104_11404_amd import lib
+    wl, op, tr, y0, rom = tg3
+    print("[case] surrogate targets 3d", flush=True)
+    X, T = M.training_set(op, rom, 0, [tr], [[0] * len(tr.snaps)])
+    P = lib.Problem.from_workload(wl)
+    G = lib.Rom(P, [gpu_instance(rom, wl.t_final)])
+    idx = np.arange(0, len(X), 5)
+    Tg = lib.rom_surrogate_targets(G, 0, 0, _t(X[idx])).cpu().numpy()
+    for r, i in enumerate(idx):
+        assert np.linalg.norm(Tg[r] - T[i]) <= 1e-10 * np.linalg.norm(T[i]), i
