@@ -258,7 +258,7 @@ enum { LH_FP32_LIFT = 1, LH_REPLAY_DT = 2, LH_FIXED_DT = 4, LH_SURROGATE = 8 };
  * closure of the sampled rows, element-local tiles of the sampled basis
  * rows and offsets, B_xv = Phi_x^T Phi_v, b_x = Phi_x^T v_os and the window
  * transition maps of eq. ic-tw.  Also fixes G, the workgroups that advance
- * each instance (1 <= G <= 64, at most 8 sampled elements per workgroup, no
+ * each instance (1 <= G <= 64, at most 10 sampled elements per workgroup, no
  * more than fit in LDS and no more than the compute units allow for n_inst
  * co-resident instances; the environment variable LAGROM_ELEMS_PER_WG, read
  * here, overrides the elements per workgroup for tuning).  Allocates device

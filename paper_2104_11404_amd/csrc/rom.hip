@@ -137,7 +137,8 @@ struct Shared {
     double ftvh[LH_NMAX];
     double tmp[LH_NMAX];
     double red[BLK];
-    double comb[2];  // combined step estimate and status bits
+    double wred[BLK / 64];  // per-wave results of block_min
+    double comb[2];         // combined step estimate and status bits
 };
 
 template <int DIM>
@@ -148,15 +149,13 @@ struct NodeBuf {
     double s[Cfg<DIM>::EC][Cfg<DIM>::NQ];
 };
 
-__device__ double block_min(double v, double* red) {
-    const int tid = threadIdx.x;
-    red[tid] = v;
+// Minimum over the workgroup: within each wave by shuffles, then over the waves (wred: BLK / 64).
+__device__ double block_min(double v, double* wred) {
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+    if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int w = BLK / 2; w > 0; w >>= 1) {
-        if (tid < w) red[tid] = fmin(red[tid], red[tid + w]);
-        __syncthreads();
-    }
-    const double r = red[0];
+    double r = wred[0];
+    for (int w = 1; w < BLK / 64; ++w) r = fmin(r, wred[w]);
     __syncthreads();
     return r;
 }
@@ -213,6 +212,33 @@ __device__ __forceinline__ double lift_row(const TT* tp, const double* os, int n
     }
     for (; k < n; ++k) a0 += tp[k * rows] * (TT)y[k];
     return *os + (double)((a0 + a1) + (a2 + a3));
+}
+
+// share[i] = sum_e a(e, i) val[e] for i < n over the workgroup's ne entries (a: resident rows
+// [e][n], or the global DEIM operator indexed by the entry's column, ent[3 e + 2]): thread (i, c)
+// sums chunk c of the entries, the chunks are added in order (red: BLK doubles).
+template <class TT>
+__device__ void project_share(const TT* a, bool res, const int* ent, int ne, int n, const double* val, double* red,
+                              double* share) {
+    const int tid = threadIdx.x;
+    const int nc = max(1, min(BLK / max(n, 1), 8));
+    const int cl = (ne + nc - 1) / nc;
+    if (tid < n * nc) {
+        const int i = tid % n, c = tid / n;
+        TT acc = 0;
+        for (int e = c * cl; e < min(ne, (c + 1) * cl); ++e) {
+            const TT w = res ? a[(int64_t)e * n + i] : a[(int64_t)ent[3 * e + 2] * n + i];
+            acc += w * (TT)val[e];
+        }
+        red[c * n + i] = (double)acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += BLK) {
+        double acc = 0.0;
+        for (int c = 0; c < nc; ++c) acc += red[c * n + i];
+        share[i] = acc;
+    }
+    __syncthreads();
 }
 
 // Pass A for one workgroup: kept stress, entries of F.1 at the sampled rows,
@@ -275,16 +301,8 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
         fe[e] = acc;
     }
     __syncthreads();
-    const int nv = W.n[1];
-    for (int i = tid; i < nv; i += BLK) {
-        TT acc = 0;
-        for (int e = 0; e < V.nkin; ++e) {
-            const TT a = L.res ? L.a1[(int64_t)e * nv + i] : L.a1[(int64_t)V.kin[3 * e + 2] * nv + i];
-            acc += a * (TT)fe[e];
-        }
-        share[i] = (double)acc;
-    }
-    const double tmin = block_min(tau, S.red);
+    project_share<TT>(L.a1, L.res, V.kin, V.nkin, W.n[1], fe, S.red, share);
+    const double tmin = block_min(tau, S.wred);
     if (tid == 0) {
         share[LH_NMAX] = tmin;
         share[LH_NMAX + 1] = (double)*status;
@@ -294,7 +312,7 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
 // Pass B for one workgroup: F^T.v_c at its sampled energy dofs and its share of F^tv.
 template <int DIM, class TT>
 __device__ void pass_b(const RomArgs& A, const WinDev& W, const WgView& V, const Local<TT>& L, NodeBuf<DIM>& B,
-                       double* te, const double* yvc, double* share, const int* status) {
+                       double* te, const double* yvc, double* share, const int* status, double* red) {
     constexpr int EC = Cfg<DIM>::EC, NKD = Cfg<DIM>::NKD, NK = Cfg<DIM>::NK, NQ = Cfg<DIM>::NQ, DD = Cfg<DIM>::DD;
     const int tid = threadIdx.x;
     for (int c0 = 0; c0 < V.nown; c0 += EC) {
@@ -341,15 +359,7 @@ __device__ void pass_b(const RomArgs& A, const WinDev& W, const WgView& V, const
         }
         __syncthreads();
     }
-    const int ne_ = W.n[2];
-    for (int i = tid; i < ne_; i += BLK) {
-        TT acc = 0;
-        for (int e = 0; e < V.nth; ++e) {
-            const TT a = L.res ? L.a2[(int64_t)e * ne_ + i] : L.a2[(int64_t)V.th[3 * e + 2] * ne_ + i];
-            acc += a * (TT)te[e];
-        }
-        share[i] = (double)acc;
-    }
+    project_share<TT>(L.a2, L.res, V.th, V.nth, W.n[2], te, red, share);
     if (tid == 0) {
         share[LH_NMAX] = INFINITY;
         share[LH_NMAX + 1] = (double)*status;
@@ -480,10 +490,21 @@ __device__ void load_local(const WinDev& W, const WgView& V, const InstDev& I, b
 // out = base + s * (b_x + B_xv vv)
 template <class TT>
 __device__ void x_update(const WinDev& W, const Local<TT>& L, const double* base, double s, const double* vv,
-                         double* out) {
-    for (int i = threadIdx.x; i < W.n[0]; i += BLK) {
+                         double* out, double* red) {
+    // thread (i, c) sums chunk c of row i of B_xv vv; chunks added in order (red: BLK doubles)
+    const int nx = W.n[0], nv = W.n[1], tid = threadIdx.x;
+    const int nc = max(1, min(BLK / max(nx, 1), 8));
+    const int cl = (nv + nc - 1) / nc;
+    if (tid < nx * nc) {
+        const int i = tid % nx, c = tid / nx;
+        double acc = 0.0;
+        for (int j = c * cl; j < min(nv, (c + 1) * cl); ++j) acc += L.Bxv[(int64_t)j * nx + i] * vv[j];
+        red[c * nx + i] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < nx; i += BLK) {
         double acc = L.bx[i];
-        for (int j = 0; j < W.n[1]; ++j) acc += L.Bxv[(int64_t)j * W.n[0] + i] * vv[j];
+        for (int c = 0; c < nc; ++c) acc += red[c * nx + i];
         out[i] = base[i] + s * acc;
     }
 }
@@ -724,7 +745,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             __syncthreads();
             mlp_ftv(W.net, out, W.n[1], W.n[2], S.yh[1], S.y[1], S.ftvh, S.red);
             for (int i = tid; i < W.n[2]; i += BLK) S.yh[2][i] = S.y[2][i] + 0.5 * h * S.ftvh[i];
-            x_update(W, L, S.y[0], 0.5 * h, S.yh[1], S.yh[0]);
+            x_update(W, L, S.y[0], 0.5 * h, S.yh[1], S.yh[0], S.red);
             __syncthreads();
             mlp_eval(W.net, S.yh[0], S.yh[1], S.yh[2], W.n, t + 0.5 * h, mscr, out);
             mlp_f1(W.net, out, W.n[1], S.f1h);
@@ -736,7 +757,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             __syncthreads();
             mlp_ftv(W.net, out, W.n[1], W.n[2], S.vc, S.yh[1], S.ftvh, S.red);
             for (int i = tid; i < W.n[2]; i += BLK) S.yn[2][i] = S.y[2][i] + h * S.ftvh[i];
-            x_update(W, L, S.y[0], h, S.vc, S.yn[0]);
+            x_update(W, L, S.y[0], h, S.vc, S.yn[0], S.red);
             __syncthreads();
             tau = tau_est;
         } else {
@@ -747,7 +768,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         ++phase;
         for (int i = tid; i < W.n[1]; i += BLK) S.yh[1][i] = S.y[1][i] - 0.5 * h * S.f1h[i];
         __syncthreads();
-        pass_b<DIM, TT>(A, W, V, L, B, te, S.yh[1], (phase & 1) ? part1 : part0, &s_status);
+        pass_b<DIM, TT>(A, W, V, L, B, te, S.yh[1], (phase & 1) ? part1 : part0, &s_status, S.red);
         sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status);
         combine((phase & 1) ? all1 : all0, A.G, W.n[2], S.ftvh, &s_status, S, stage);
         ++phase;
@@ -766,7 +787,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             }
         }
         for (int i = tid; i < W.n[2]; i += BLK) S.yh[2][i] = S.y[2][i] + 0.5 * h * S.ftvh[i];
-        x_update(W, L, S.y[0], 0.5 * h, S.yh[1], S.yh[0]);
+        x_update(W, L, S.y[0], 0.5 * h, S.yh[1], S.yh[0], S.red);
         __syncthreads();
         // ---- stage 2 at y_{n+1/2}
         pass_a<DIM, TT>(A, W, V, L, B, S, fe, S.yh[0], S.yh[1], S.yh[2], (phase & 1) ? part1 : part0, &s_status);
@@ -779,12 +800,12 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             S.vc[i] = 0.5 * (S.y[1][i] + vn);
         }
         __syncthreads();
-        pass_b<DIM, TT>(A, W, V, L, B, te, S.vc, (phase & 1) ? part1 : part0, &s_status);
+        pass_b<DIM, TT>(A, W, V, L, B, te, S.vc, (phase & 1) ? part1 : part0, &s_status, S.red);
         sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status);
         combine((phase & 1) ? all1 : all0, A.G, W.n[2], S.ftvh, &s_status, S, stage);
         ++phase;
         for (int i = tid; i < W.n[2]; i += BLK) S.yn[2][i] = S.y[2][i] + h * S.ftvh[i];
-        x_update(W, L, S.y[0], h, S.vc, S.yn[0]);
+        x_update(W, L, S.y[0], h, S.vc, S.yn[0], S.red);
         __syncthreads();
         evals += 2 * W.n_el;
         tau = fmin(tau1, tau2);
@@ -932,7 +953,7 @@ __global__ void __launch_bounds__(BLK) targets_kernel(RomArgs A, const InstDev* 
         for (int g = 0; g < G; ++g) {
             Local<double> L = global_local<DIM>(W, W.views[g], sig);
             if (k >= 0) L.os[1] = zeros;  // rows of every slot read zero
-            pass_b<DIM, double>(A, W, W.views[g], L, Bn, te, S.vc, share + (int64_t)g * PSTRIDE, &s_status);
+            pass_b<DIM, double>(A, W, W.views[g], L, Bn, te, S.vc, share + (int64_t)g * PSTRIDE, &s_status, S.red);
             __syncthreads();
         }
         __threadfence();
@@ -1352,7 +1373,7 @@ static int cu_count() {
 
 constexpr int STATIC_LDS_RESERVE = 24 * 1024;  // node buffers, reduced vectors, state (bytes, upper bound)
 constexpr int MAX_G = 64;                      // workgroups per instance (bounds the share staging in LDS)
-constexpr int ELEMS_PER_WG = 8;                // default cap on sampled elements per workgroup
+constexpr int ELEMS_PER_WG = 10;               // default cap on sampled elements per workgroup
 
 }  // namespace rom
 }  // namespace lh
@@ -1399,14 +1420,19 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
     const int max_g = std::max(1, std::min(MAX_G, cu_count() / n_inst));
     int G = 1;
     if (max_g > 1) {
-        int64_t worst_per_elem = 0;
+        // per element: its tiles, offsets, kept stress and (about 4 sampled rows) DEIM columns;
+        // per workgroup: B_xv and b_x
+        int64_t worst_per_elem = 0, worst_fixed = 0;
         for (int i = 0; i < n_inst; ++i)
-            for (auto& H : R->h_struct[i])
-                worst_per_elem = std::max<int64_t>(worst_per_elem, resident_bytes(dim, H, 1, 0, 0, 8) +
-                                                              8LL * (H.n[1] * 4 + H.n[2]));
+            for (auto& H : R->h_struct[i]) {
+                const int64_t fixed = resident_bytes(dim, H, 0, 0, 0, 8);
+                worst_fixed = std::max<int64_t>(worst_fixed, fixed);
+                worst_per_elem = std::max<int64_t>(worst_per_elem, resident_bytes(dim, H, 1, 0, 0, 8) - fixed +
+                                                                      8LL * (H.n[1] * 4 + H.n[2]));
+            }
         // at most ELEMS_PER_WG elements per workgroup: fewer workgroups make each pass longer, more
         // make the share exchange longer
-        int per_wg = std::max<int64_t>(1, std::min<int64_t>(ELEMS_PER_WG, (int64_t)(0.8 * budget) /
+        int per_wg = std::max<int64_t>(1, std::min<int64_t>(ELEMS_PER_WG, ((int64_t)(0.8 * budget) - worst_fixed) /
                                                                             std::max<int64_t>(1, worst_per_elem)));
         if (const char* env = std::getenv("LAGROM_ELEMS_PER_WG")) per_wg = std::max(1, std::atoi(env));
         G = std::min(max_g, std::max(1, (max_el + per_wg - 1) / per_wg));
