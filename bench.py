@@ -120,11 +120,20 @@ def cpu_baseline(wl, dims, evals_per_step, seconds: float = 12.0, n_pre: int = 2
                         f"of the full workload"))
 
 
+# FP64 flops per element of a full-mesh fom_force (dense per quadrature point: Jacobian, velocity
+# gradient, stress and viscosity, both contractions), 2D Q2-Q1 with 16 points and 3D with 64
+ALG_FLOPS_PER_ELEM = {2: 5.0e3, 3: 1.26e5}
+# FP64 flops per element the kernel executes, from SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 x 64 lanes
+EXEC_FLOPS_PER_ELEM = {2: 1.19e4, 3: 3.81e5}
+FP64_PEAK_TFLOPS = 78.6
+
+
 def fom_force_rate(lib, wl, reps: int = 20, seed: int = 7):
     """Full-mesh fom_force (F.1, F^T.v and tau, artificial viscosity on) on a perturbed state.
 
     Algorithmic bytes per call: read x, v, v_c (3 N_V) and e (N_E), write F.1 (N_V) and
-    F^T.v (N_E), FP64.
+    F^T.v (N_E), FP64.  Algorithmic flops: ALG_FLOPS_PER_ELEM per element; the kernel is bound by
+    FP64 arithmetic (2D at the FP64 ridge, 3D far above it), so both fractions are reported.
     """
     import torch
 
@@ -146,9 +155,13 @@ def fom_force_rate(lib, wl, reps: int = 20, seed: int = 7):
     P.status()
     s = a.elapsed_time(b) / 1e3 / reps
     nbytes = 8 * (4 * P.NV + 2 * P.NE)
+    flops = ALG_FLOPS_PER_ELEM[wl.dim] * wl.n_elem
     return {"mesh": list(wl.nel[: wl.dim]), "elements": wl.n_elem, "avg_us_per_call": s * 1e6,
             "elements_per_s": wl.n_elem / s, "algorithmic_bytes": nbytes, "achieved_GBs": nbytes / s / 1e9,
-            "hbm_frac": nbytes / s / 1e9 / HBM_PEAK_GBS}
+            "hbm_frac": nbytes / s / 1e9 / HBM_PEAK_GBS, "bound": "alu (FP64)",
+            "algorithmic_flops": flops, "achieved_TFLOPs": flops / s / 1e12,
+            "fp64_frac": flops / s / 1e12 / FP64_PEAK_TFLOPS,
+            "executed_fp64_TFLOPs": EXEC_FLOPS_PER_ELEM[wl.dim] * wl.n_elem / s / 1e12}
 
 
 def batched_gresho(lib, pipeline, n_inst: int = 256, reps: int = 3, lam=None):
