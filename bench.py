@@ -452,7 +452,7 @@ def main():
     if not args.no_batch:
         out["batched"] = batched_gresho(lib, pipeline)
     if not args.no_surrogate:
-        out["surrogate"] = surrogate_tg2d(lib, pipeline, train_steps=3000, variants=[(25, 1e30)])
+        out["surrogate"] = surrogate_tg2d(lib, pipeline, train_steps=10000, variants=[(25, 1e30)])
     if not args.no_cpu_baseline:
         med = [int(sorted(d[f] for d in dims)[len(dims) // 2]) for f in range(3)]
         out["cpu_baseline"] = cpu_baseline(wl, med, st.n_force_evals / st.n_steps, args.cpu_seconds)

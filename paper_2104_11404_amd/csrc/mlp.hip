@@ -12,8 +12,10 @@
 //   forward   Z_{l+1} = act(r(Z_l) r(W_l) + b_l)
 //   backward  grad W_l = r(Z_l)^T r(D_{l+1}),  grad b_l = column sums of D_{l+1},
 //             D_l = (r(D_{l+1}) r(W_l)^T) * (1 - Z_l^2)
-// with D_L = 2 (Z_L - T~) / (B d_out).  Column sums run over rows in order,
-// so every result is deterministic.
+// with D_L = 2 (Z_L - T~) / (B d_out).  Products with few output tiles and a
+// long K (the weight gradients, K = batch) are split over K into partial
+// tiles; partial tiles and the column sums' row chunks are added in a fixed
+// order, so every result is deterministic.
 #include <algorithm>
 #include <vector>
 
@@ -42,6 +44,8 @@ struct lh_mlp {
     uint16_t* delb[LH_MLP_MAX_LAYERS + 1] = {};   // r(D_l)
     float* loss_part = nullptr;
     int n_loss_part = 0;
+    float* ksplit_ws = nullptr;  // partial tiles of split-K products
+    int64_t ksplit_floats = 0;
 };
 
 namespace lh {
@@ -69,6 +73,8 @@ struct GemmArgs {
     int64_t ldo;
     uint16_t* outb;
     int64_t ldob;
+    int kchunk;     // split-K: block z covers k in [z kchunk, (z + 1) kchunk) ...
+    float* part;    // ... and writes its raw tile to part[z][M][N] (no epilogue)
 };
 
 __global__ void __launch_bounds__(BLK) gemm_bf16_kernel(GemmArgs g) {
@@ -80,13 +86,15 @@ __global__ void __launch_bounds__(BLK) gemm_bf16_kernel(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
     const int r = tid >> 2, kk = (tid & 3) * 4;
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
+    const int kbeg = g.part ? blockIdx.z * g.kchunk : 0;
+    const int kend = g.part ? min(g.K, kbeg + g.kchunk) : g.K;
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
         const int m = m0 + r, n = n0 + r;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int k = k0 + kk + i;
-            As[r][kk + i] = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : (uint16_t)0;
-            Bs[r][kk + i] = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : (uint16_t)0;
+            As[r][kk + i] = (m < g.M && k < kend) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : (uint16_t)0;
+            Bs[r][kk + i] = (n < g.N && k < kend) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : (uint16_t)0;
         }
         __syncthreads();
         const s4 a = *reinterpret_cast<const s4*>(&As[wave * 16 + (lane & 15)][(lane >> 4) * 4]);
@@ -107,6 +115,10 @@ __global__ void __launch_bounds__(BLK) gemm_bf16_kernel(GemmArgs g) {
             const int m = m0 + wave * 16 + (lane >> 4) * 4 + i;
             if (m >= g.M) continue;
             float v = acc[j][i];
+            if (g.part) {
+                g.part[((int64_t)blockIdx.z * g.M + m) * g.N + n] = v;
+                continue;
+            }
             if (g.bias) v += g.bias[n];
             if (g.act == ACT_TANH) {
                 v = tanhf(v);
@@ -118,6 +130,24 @@ __global__ void __launch_bounds__(BLK) gemm_bf16_kernel(GemmArgs g) {
             if (g.outb) g.outb[(int64_t)m * g.ldob + n] = f32_to_bf16(v);
         }
     }
+}
+
+// Sum of the split-K partial tiles in order of z, then the epilogue of gemm_bf16_kernel.
+__global__ void ksplit_reduce_kernel(GemmArgs g, int splits) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)g.M * g.N) return;
+    const int m = (int)(t / g.N), n = (int)(t % g.N);
+    float v = 0.0f;
+    for (int z = 0; z < splits; ++z) v += g.part[(int64_t)z * g.M * g.N + t];
+    if (g.bias) v += g.bias[n];
+    if (g.act == ACT_TANH) {
+        v = tanhf(v);
+    } else if (g.act == ACT_DTANH) {
+        const float a = g.aux[(int64_t)m * g.ldaux + n];
+        v *= 1.0f - a * a;
+    }
+    if (g.out32) g.out32[(int64_t)m * g.ldo + n] = v;
+    if (g.outb) g.outb[(int64_t)m * g.ldob + n] = f32_to_bf16(v);
 }
 
 // Z_0 = (X - mu) / s (FP64 arithmetic, then FP32 and its bfloat16 rounding); padding columns zero.
@@ -179,7 +209,30 @@ __global__ void __launch_bounds__(BLK) loss_reduce_kernel(const float* part, int
     if (threadIdx.x == 0) *out = red[0] * scale;
 }
 
-// gb[j] = sum over rows of D[i][j], rows in order.
+// Partial column sums: block (x, y) sums rows [256 y, 256 y + 256) of columns [64 x, 64 x + 64);
+// thread (j, ry) takes every fourth row from ry, the four are added in order.
+__global__ void __launch_bounds__(BLK) colsum_part_kernel(const float* D, int B, int N, int ld, float* part) {
+    __shared__ float red[4][64];
+    const int jx = threadIdx.x & 63, ry = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + jx;
+    const int r0 = blockIdx.y * 256;
+    float a = 0.0f;
+    if (j < N)
+        for (int r = r0 + ry; r < min(B, r0 + 256); r += 4) a += D[(int64_t)r * ld + j];
+    red[ry][jx] = a;
+    __syncthreads();
+    if (ry == 0 && j < N) part[(int64_t)blockIdx.y * N + j] = ((red[0][jx] + red[1][jx]) + red[2][jx]) + red[3][jx];
+}
+
+__global__ void colsum_final_kernel(const float* part, int chunks, int N, float* gb) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    float a = 0.0f;
+    for (int c = 0; c < chunks; ++c) a += part[(int64_t)c * N + j];
+    gb[j] = a;
+}
+
+// gb[j] = sum over rows of D[i][j], rows in order (used when no workspace is available).
 __global__ void colsum_kernel(const float* D, int B, int N, int ld, float* gb) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
@@ -259,10 +312,32 @@ __global__ void colstats_kernel(const double* X, int B, int d, double* mu, doubl
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + BLK - 1) / BLK); }
 
-int gemm(const GemmArgs& a, hipStream_t s) {
-    if (a.M <= 0 || a.N <= 0) return LH_OK;
-    dim3 grid((a.N + TN - 1) / TN, (a.M + TM - 1) / TM);
-    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(BLK), 0, s, a);
+constexpr int64_t KSPLIT_MAX_FLOATS = 8 << 20;  // 32 MB of partial tiles
+
+// C = A B with the epilogue; products with few output tiles and a long K (the weight gradients,
+// K = batch) are split over K into partial tiles that a second kernel adds in a fixed order.
+int gemm(const GemmArgs& a0, float* ws, int64_t ws_floats, hipStream_t s) {
+    if (a0.M <= 0 || a0.N <= 0) return LH_OK;
+    GemmArgs a = a0;
+    a.part = nullptr;
+    a.kchunk = a.K;
+    const int tiles = ((a.N + TN - 1) / TN) * ((a.M + TM - 1) / TM);
+    int splits = 1;
+    if (ws && tiles < 256 && a.K > 8 * TK) {
+        splits = (int)std::min<int64_t>((a.K + 8 * TK - 1) / (8 * TK), 512 / tiles + 1);
+        splits = (int)std::min<int64_t>(splits, ws_floats / ((int64_t)a.M * a.N));
+    }
+    if (splits > 1) {
+        a.kchunk = ((a.K + splits - 1) / splits + TK - 1) / TK * TK;
+        splits = (a.K + a.kchunk - 1) / a.kchunk;
+        a.part = ws;
+        dim3 grid((a.N + TN - 1) / TN, (a.M + TM - 1) / TM, splits);
+        hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(BLK), 0, s, a);
+        hipLaunchKernelGGL(ksplit_reduce_kernel, dim3(blocks((int64_t)a.M * a.N)), dim3(BLK), 0, s, a, splits);
+    } else {
+        dim3 grid((a.N + TN - 1) / TN, (a.M + TM - 1) / TM);
+        hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(BLK), 0, s, a);
+    }
     return launch_check("gemm_bf16_kernel");
 }
 
@@ -300,7 +375,7 @@ int forward(lh_mlp* m, const double* X, int B, hipStream_t s) {
         a.ldo = m->npad[l + 1];
         a.outb = m->actb[l + 1];
         a.ldob = m->npad[l + 1];
-        int rc = gemm(a, s);
+        int rc = gemm(a, m->ksplit_ws, m->ksplit_floats, s);
         if (rc) return rc;
     }
     return LH_OK;
@@ -334,10 +409,20 @@ int backward(lh_mlp* m, const double* T, int B, float* loss, hipStream_t s) {
         a.sbn = 1;
         a.out32 = m->gW[l];
         a.ldo = m->npad[l + 1];
-        int rc = gemm(a, s);
+        int rc = gemm(a, m->ksplit_ws, m->ksplit_floats, s);
         if (rc) return rc;
-        hipLaunchKernelGGL(colsum_kernel, dim3(blocks(m->sizes[l + 1])), dim3(BLK), 0, s, m->del32[l + 1], B,
-                           m->sizes[l + 1], m->npad[l + 1], m->gb[l]);
+        {
+            const int N = m->sizes[l + 1], chunks = (B + 255) / 256;
+            if (m->ksplit_ws && (int64_t)chunks * N <= m->ksplit_floats) {
+                hipLaunchKernelGGL(colsum_part_kernel, dim3((N + 63) / 64, chunks), dim3(BLK), 0, s, m->del32[l + 1], B,
+                                   N, m->npad[l + 1], m->ksplit_ws);
+                hipLaunchKernelGGL(colsum_final_kernel, dim3(blocks(N)), dim3(BLK), 0, s, m->ksplit_ws, chunks, N,
+                                   m->gb[l]);
+            } else {
+                hipLaunchKernelGGL(colsum_kernel, dim3(blocks(N)), dim3(BLK), 0, s, m->del32[l + 1], B, N,
+                                   m->npad[l + 1], m->gb[l]);
+            }
+        }
         if (l > 0) {
             GemmArgs d{};  // D_l = (r(D_{l+1}) r(W_l)^T) * (1 - Z_l^2)
             d.M = B;
@@ -356,7 +441,7 @@ int backward(lh_mlp* m, const double* T, int B, float* loss, hipStream_t s) {
             d.ldo = m->npad[l];
             d.outb = m->delb[l];
             d.ldob = m->npad[l];
-            rc = gemm(d, s);
+            rc = gemm(d, m->ksplit_ws, m->ksplit_floats, s);
             if (rc) return rc;
         }
     }
@@ -439,6 +524,10 @@ int mlp_create(const lh_mlp_desc* d, int32_t max_batch, lh_mlp** out) {
     if (!rc) rc = alloc(m, &m->s_out, m->sizes[m->L]);
     m->n_loss_part = (int)blocks((int64_t)max_batch * m->npad[m->L]);
     if (!rc) rc = alloc(m, &m->loss_part, m->n_loss_part);
+    int64_t wmax = 0;
+    for (int l = 0; l < m->L; ++l) wmax = std::max<int64_t>(wmax, (int64_t)m->sizes[l] * m->sizes[l + 1]);
+    m->ksplit_floats = std::min<int64_t>(KSPLIT_MAX_FLOATS, wmax * std::min(64, (max_batch + 127) / 128));
+    if (!rc && m->ksplit_floats >= 2 * wmax) rc = alloc(m, &m->ksplit_ws, m->ksplit_floats);
     if (rc) return fail(rc);
     hipLaunchKernelGGL(fill_f64_kernel, dim3(blocks(m->sizes[0])), dim3(BLK), 0, s, m->mu_in, (int64_t)m->sizes[0], 0.0);
     hipLaunchKernelGGL(fill_f64_kernel, dim3(blocks(m->sizes[0])), dim3(BLK), 0, s, m->s_in, (int64_t)m->sizes[0], 1.0);
