@@ -70,6 +70,8 @@ class Operator:
     _me_inv: np.ndarray = field(default=None, repr=False)
 
     def solve_v(self, rhs: np.ndarray) -> np.ndarray:
+        if self._lu is None:  # factorised on first use (force-only uses of large meshes skip it)
+            self._lu = spla.splu(self.Mv_eff)
         r = np.where(self.constrained, 0.0, rhs)
         return self._lu.solve(r)
 
@@ -109,7 +111,6 @@ def build_operator(prob: Problem) -> Operator:
     Meloc = np.einsum("eq,qi,qj->eij", cq, ref.Bt, ref.Bt)
     Me = sp.block_diag(list(Meloc), format="csr")
     op = Operator(prob, mesh, ref, en, et, cq, Ms, Mv, Mv_eff, Me, constrained)
-    op._lu = spla.splu(Mv_eff)
     op._me_inv = np.linalg.inv(Meloc)
     return op
 

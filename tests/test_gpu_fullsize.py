@@ -1,0 +1,114 @@
+"""Parity at the workloads' full sizes, in the launch configurations the bench times (MI355X).
+
+The oracle cannot evaluate whole full-size runs in seconds, so these tests
+compare outputs it can compute one by one:
+
+* full-mesh fom_force at the 2D Sedov 64 x 64, 2D Gresho 48 x 48, 3D
+  Taylor-Green 24^3 and 3D Sedov 32^3 meshes: F^T.v_c on sampled elements, F.1
+  on sampled nodes (from exactly the elements that contain them), and the
+  step estimate (exact in 2D; a bound in 3D);
+* the 64 x 64 Sedov ROM, on a window built by the oracle from a 24-step FOM
+  prefix, with several workgroups per instance as in the bench;
+* two 48 x 48 Gresho instances of the batch, one workgroup each with tiles
+  read from global memory, as in the 256-instance launch.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import fom as F
+from oracle import rom as R
+from oracle.problems import initial_state
+from oracle.windows import windows_physical
+from tests.oracle_adapter import oracle_problem
+from tests.test_gpu_rom import _gpu_rom, _t, gpu_instance, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name,make", [("sedov2d_64", lambda: W.sedov2d(64)), ("gresho2d_48", lambda: W.gresho2d(48)),
+                                       ("tg3d_24", lambda: W.tg3d(24)), ("sedov3d_32", lambda: W.sedov3d(32))])
+def test_full_mesh_force_on_sampled_outputs(gpu_lib, name, make):
+    from paper_2104_11404_amd import lib
+    wl = make()
+    print(f"[case] full-size fom_force {name} ({wl.n_elem} elements)", flush=True)
+    op = F.build_operator(oracle_problem(wl))
+    x, v, e, vc = W.random_state(wl, 11)
+    P = lib.Problem.from_workload(wl)
+    F1, Ftv, tau = P.fom_force(_t(x), _t(v), _t(e), _t(vc))
+    F1, Ftv, tau = F1.cpu().numpy(), Ftv.cpu().numpy(), float(tau)
+    assert P.status() == 0
+    g = np.random.default_rng(3)
+    els = np.sort(g.choice(wl.n_elem, 96, replace=False))
+    st = F.stress(op, x, v, e, elems=els)
+    ftv = F.force_tv(op, st, vc, elems=els)
+    dofs = op.et[els].ravel()
+    assert rel(Ftv[dofs], ftv[dofs]) < 1e-12
+    # F.1 at sampled nodes: every element containing them
+    nodes = g.choice(op.mesh.n_nodes, 64, replace=False)
+    touch = np.where(np.isin(op.en, nodes).any(axis=1))[0]
+    f1 = F.force_one(op, F.stress(op, x, v, e, elems=touch), elems=touch)
+    rows = np.concatenate([c * op.mesh.n_nodes + nodes for c in range(wl.dim)])
+    assert rel(F1[rows], f1[rows]) < 1e-12
+    tmin = float(np.min(st.tau))
+    assert tau <= tmin * (1 + 1e-14)
+    if wl.dim == 2:
+        full = F.stress(op, x, v, e)
+        assert abs(tau - float(np.min(full.tau))) <= 1e-13 * tau
+
+
+def test_full_size_sedov_rom_prefix_window(gpu_lib):
+    """64 x 64 Sedov: one window from a 24-step oracle FOM prefix (energy criterion, lambda 6),
+    the oracle's step sizes replayed, several workgroups per instance."""
+    from paper_2104_11404_amd import lib
+    wl = W.sedov2d()
+    op = F.build_operator(oracle_problem(wl))
+    tr = F.run_fom(op, wl.t_final, max_steps=24)
+    y0 = initial_state(op.prob)
+    rom = R.build_rom(op, [tr], [y0], [tr.t[-1]], energy_frac=wl.energy_frac, n_max=64, lam=wl.lam)
+    run = R.run_rom(op, rom, y0, tr.t[-1], dt_replay=tr.dt)
+    P, G = _gpu_rom(wl, [(rom, tr.t[-1])], [y0])
+    g = lib._I32()
+    lib._check(lib.load().rom_workgroups_per_instance(G.h, lib.C.byref(g)))
+    print(f"[case] full-size sedov rom, dims {rom.windows[0].dims}, {len(rom.windows[0].elems)} sampled elements, "
+          f"G={g.value}", flush=True)
+    assert g.value > 1
+    G.step(flags=lib.LH_REPLAY_DT, dt_replay=_t(np.array(tr.dt)))
+    st = G.states()[0]
+    assert st.status == 0 and st.n_steps == len(tr.dt)
+    for a, b in zip(G.coords(0), run.yhat):
+        assert rel(a, b) < 1e-10
+    for a, b in zip(G.lift(0), R.final_lift(rom, run)):
+        assert rel(a.cpu().numpy(), b) < 1e-10
+
+
+def test_full_size_gresho_batch_instances(gpu_lib, monkeypatch):
+    """Two instances of the 48 x 48 Gresho batch, one workgroup each (tiles from global memory)."""
+    from paper_2104_11404_amd import lib
+    monkeypatch.setenv("LAGROM_ELEMS_PER_WG", "1000000")
+    wl = W.gresho_batch(256)
+    items = []
+    for prm in wl.params[:2]:
+        op = F.build_operator(oracle_problem(wl, amp=prm["amp"], p_bg=prm["p_bg"]))
+        tr = F.run_fom(op, wl.t_final)
+        y0 = initial_state(op.prob)
+        T = windows_physical(wl.t_final, prm["n_windows"])
+        rom = R.build_rom(op, [tr], [y0], T, n_fixed=(prm["n"],) * 3, lam=wl.lam)
+        items.append((rom, R.run_rom(op, rom, y0, wl.t_final), y0))
+    P = lib.Problem.from_workload(wl)
+    G = lib.Rom(P, [gpu_instance(rom, wl.t_final) for rom, _, _ in items])
+    g = lib._I32()
+    lib._check(lib.load().rom_workgroups_per_instance(G.h, lib.C.byref(g)))
+    print(f"[case] full-size gresho batch instances, windows {[len(r.windows) for r, _, _ in items]}, "
+          f"sampled elements {[max(len(w.elems) for w in r.windows) for r, _, _ in items]}, G={g.value}", flush=True)
+    assert g.value == 1
+    G.init_state(torch.cat([_t(y[0]) for _, _, y in items]), torch.cat([_t(y[1]) for _, _, y in items]),
+                 torch.cat([_t(y[2]) for _, _, y in items]))
+    G.step()
+    for i, (rom, run, _) in enumerate(items):
+        st = G.states()[i]
+        assert st.status == 0 and st.done == 1
+        assert st.n_steps == len(run.dt) and st.n_rejected == run.rejections and st.w == run.w
+        for a, b in zip(G.coords(i), run.yhat):
+            assert rel(a, b) < 1e-9
