@@ -164,6 +164,13 @@ def fom_force_rate(lib, wl, reps: int = 20, seed: int = 7):
             "executed_fp64_TFLOPs": EXEC_FLOPS_PER_ELEM[wl.dim] * wl.n_elem / s / 1e12}
 
 
+def autotune(rom, flags, trial_steps):
+    """rom_autotune from the instances' current (initial) state: the launch shape the timed runs use."""
+    t0 = time.perf_counter()
+    g, ms = rom.autotune(trial_steps=trial_steps, flags=flags)
+    return {"G": g, "trial_steps": trial_steps, "trial_ms": ms, "tuning_s": time.perf_counter() - t0}
+
+
 def batched_gresho(lib, pipeline, n_inst: int = 256, reps: int = 3, lam=None):
     """256 parametrised 2D Gresho ROM instances (48 x 48, t = 0.1) in one persistent launch.
 
@@ -185,13 +192,13 @@ def batched_gresho(lib, pipeline, n_inst: int = 256, reps: int = 3, lam=None):
     P = lib.Problem.from_workload(wl)
     rom = lib.Rom(P, insts)
     y0 = [torch.cat([y[f] for y in y0s]) for f in range(3)]
-    g = lib._I32()
-    lib._check(lib.load().rom_workgroups_per_instance(rom.h, lib.C.byref(g)))
     out = {"workload": f"gresho2d_48x48_t0.1_batch{n_inst}_uneven_dims_windows_lambda{lam[0]:g}", "instances": n_inst,
-           "fom_steps_total": int(sum(fom_steps)), "setup_s": t_setup, "workgroups_per_instance": g.value,
-           "windows_total": int(sum(len(i["windows"]) for i in insts))}
+           "fom_steps_total": int(sum(fom_steps)), "setup_s": t_setup, "heuristic_workgroups_per_instance":
+           rom.workgroups(), "windows_total": int(sum(len(i["windows"]) for i in insts))}
     stream = torch.cuda.current_stream()
     for name, flags in (("f64", 0), ("f32_lift", lib.LH_FP32_LIFT)):
+        rom.init_state(*y0)
+        tuned = autotune(rom, flags, trial_steps=100)
         rom.init_state(*y0)
         rom.step(flags=flags)
         torch.cuda.synchronize()
@@ -215,7 +222,7 @@ def batched_gresho(lib, pipeline, n_inst: int = 256, reps: int = 3, lam=None):
                 errs[r, f] = float(torch.linalg.norm(x - y) / torch.linalg.norm(y))
         t = sorted(ms)[len(ms) // 2] / 1e3
         out[name] = {"ms_per_launch": t * 1e3, "rom_steps_per_launch": int(steps), "rom_steps_per_s": steps / t,
-                     "sampled_force_evals_per_s": evals / t,
+                     "sampled_force_evals_per_s": evals / t, "autotune": tuned,
                      "failed_instances": [dict(instance=i, status=sts[i].status, t=sts[i].t, **wl.params[i])
                                           for i in bad],
                      "max_rel_error_vs_fom_completed": dict(zip("xve", errs.max(axis=0).tolist())),
@@ -274,10 +281,8 @@ def surrogate_tg2d(lib, pipeline, n_inst: int = 64, train_steps: int = 4000, rep
     print(f"[bench] surrogate: {int(X.shape[0])} samples, loss {hist[0]:.3e} -> {hist[-1]:.3e} in {t_train:.1f} s",
           file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
-    g = lib._I32()
-    lib._check(lib.load().rom_workgroups_per_instance(rom.h, lib.C.byref(g)))
     out = {"workload": f"tg2d_32x32_param_A0.8-1.2_batch{n_inst}_fixed_dt1e-3_t{wl.t_final:g}_dims20_lambda2",
-           "instances": n_inst, "workgroups_per_instance": g.value, "offline_s": t_offline,
+           "instances": n_inst, "heuristic_workgroups_per_instance": rom.workgroups(), "offline_s": t_offline,
            "training": {"samples": int(X.shape[0]), "steps": train_steps, "seconds": t_train,
                         "loss_first": hist[0], "loss_last": hist[-1],
                         "network": [int(X.shape[1]), 256, 256, 256, int(T.shape[1])]}}
@@ -287,6 +292,8 @@ def surrogate_tg2d(lib, pipeline, n_inst: int = 64, train_steps: int = 4000, rep
     for name, flags, k_audit, tol_run in runs:
         for i in range(n_inst):
             rom.attach_surrogate(i, 0, net if name != "deim" else None, audit_every=k_audit, tol=tol_run)
+        rom.init_state(*y0, wl.fixed_dt)
+        tuned = autotune(rom, flags, trial_steps=50)
         ms = []
         for r in range(reps + 1):
             rom.init_state(*y0, wl.fixed_dt)
@@ -303,7 +310,7 @@ def surrogate_tg2d(lib, pipeline, n_inst: int = 64, train_steps: int = 4000, rep
                          for i in range(n_inst)])
         t = sorted(ms)[len(ms) // 2] / 1e3
         out[name] = {"ms_per_launch": t * 1e3, "rom_steps_per_s": steps / t,
-                     "sampled_force_evals_per_s": sum(st.n_force_evals for st in sts) / t,
+                     "sampled_force_evals_per_s": sum(st.n_force_evals for st in sts) / t, "autotune": tuned,
                      "failed_instances": [i for i, st in enumerate(sts) if st.status != 0 or st.done != 1],
                      "max_rel_error_vs_fom": dict(zip("xve", errs.max(axis=0).tolist())),
                      "median_rel_error_vs_fom": dict(zip("xve", np.median(errs, axis=0).tolist())),
@@ -326,6 +333,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-instance batched Gresho measurement")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate against DEIM measurement")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workgroups", type=int, default=0,
+                    help="workgroups per instance of the headline ROM launch (0: pick with rom_autotune)")
     ap.add_argument("--calibrate-copy", type=int, default=0, help="also run a plain device copy of this many MiB")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -359,6 +368,14 @@ def main():
           f"{[[int(p.shape[0]) for p in wd['phi']] for wd in inst['windows']]}", file=sys.stderr, flush=True)
     rom = lib.Rom(P, [inst])
     flags = lib.LH_FP32_LIFT if args.fp32 else 0
+    heuristic_g = rom.workgroups()
+    rom.init_state(*traj["y0"])
+    if args.workgroups > 0:
+        rom.set_workgroups(args.workgroups, flags)
+        tuned = {"G": args.workgroups, "pinned": True}
+    else:
+        tuned = autotune(rom, flags, trial_steps=200)
+    print(f"[bench] launch shape: {tuned}", file=sys.stderr, flush=True)
 
     # accuracy run (also the first warm-up)
     rom.init_state(*traj["y0"])
@@ -427,7 +444,9 @@ def main():
             "fom_steps": n_t, "windows": len(T), "rom_steps_per_run": st.n_steps,
             "rom_rejections_per_run": st.n_rejected, "dims_per_window": dims,
             "sampled_elements_per_window": n_el, "energy_frac": wl.energy_frac, "lambda": list(wl.lam),
+            "workgroups_per_instance": rom.workgroups(), "heuristic_workgroups_per_instance": heuristic_g,
         },
+        "autotune": tuned,
         "sampled_force_evals_per_s": evals / elapsed,
         "rel_error_vs_fom": {"x": errs[0], "v": errs[1], "e": errs[2]},
         "roofline": {

@@ -311,6 +311,32 @@ int rom_sampled_elements(const lh_rom* r, int32_t inst, int32_t window, int32_t*
  * complete within a few seconds sets LH_FLAG_TIMEOUT and ends the launch. */
 int rom_workgroups_per_instance(const lh_rom* r, int32_t* G);
 
+/* Launch shape of rom_step: split every instance's sampled elements over G
+ * workgroups (1 <= G <= 64) instead of the count rom_create chose.  The
+ * scheme and its results are those of eq. RK2-avg-rom-hr for any G; only the
+ * order in which the workgroups' partial reduced forces are added changes, so
+ * results are bitwise reproducible for a fixed G and agree across G to
+ * rounding.  flags are the rom_step flags the launch will use (LH_FP32_LIFT,
+ * LH_SURROGATE change its LDS size); G > 1 needs n_inst x G workgroups
+ * co-resident, else LH_EINVAL and the previous G is kept.  Waits for the
+ * whole device (no rom_step may be in flight), rebuilds the workgroup tables
+ * (allocates; not a hot call).  Synchronises.  LH_EDEVICE leaves r unusable
+ * except for rom_destroy. */
+int rom_set_workgroups(lh_rom* r, int32_t G, uint32_t flags, hipStream_t stream);
+
+/* Autotuner of the launch shape: for each candidate G in {1, 2, 3, 4, 5, 6,
+ * 8, 10, 12, 16, 20, 24, 32, 40, 48, 64} up to the largest sampled-element
+ * count that can be co-resident, time trial_steps >= 1 steps of rom_step
+ * with these flags / dt_replay from a copy of state (dev, n_inst entries, as
+ * left by rom_init_state or rom_step; state itself is not changed), once
+ * untimed and twice timed with HIP events (the faster of the two counts),
+ * and keep the smallest G whose time is within 2 % of the fastest (*G_best,
+ * host; *ms_best, host, may be NULL: its time in ms).  A
+ * candidate whose launch fails or times out is skipped.  Allocates a scratch
+ * copy of the states (not a hot call).  Synchronises. */
+int rom_autotune(lh_rom* r, const lh_rom_state* state, int32_t trial_steps, uint32_t flags, const double* dt_replay,
+                 int32_t n_replay, int32_t* G_best, float* ms_best, hipStream_t stream);
+
 /* ------------------------------------------------------ offline helpers */
 
 /* Snapshot deviations (Sec. 3.4): out[:, j] = snaps[:, j] - os for j < m.

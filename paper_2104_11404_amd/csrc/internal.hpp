@@ -237,6 +237,7 @@ __device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, int q, co
     for (int c = 0; c < DIM; ++c)
 #pragma unroll
         for (int i = 0; i < DIM; ++i) J[c][i] = G[c][i] = 0.0;
+#pragma unroll 3
     for (int a = 0; a < NK; ++a) {
         int ax, ay, az;
         a_coords<DIM>(a, ax, ay, az);

@@ -1094,6 +1094,7 @@ struct lh_rom {
     int res_max64, res_max32;
     int mlp_floats = 0;  // LDS scratch of the largest attached surrogate
     std::vector<void*> allocs;
+    std::vector<void*> view_allocs;  // workgroup views: rebuilt when G changes
     lh::rom::InstDev* d_inst;
     std::vector<lh::rom::InstDev> h_inst;
     std::vector<std::vector<lh::rom::WinDev>> h_win;
@@ -1104,22 +1105,22 @@ namespace lh {
 namespace rom {
 
 template <class T>
-static int dev_alloc(lh_rom* R, T** out, size_t count) {
+static int dev_alloc(lh_rom* R, T** out, size_t count, std::vector<void*>* list = nullptr) {
     void* p = nullptr;
     if (count == 0) count = 1;
     if (hipMalloc(&p, sizeof(T) * count) != hipSuccess) {
         set_error("rom_create: hipMalloc failed");
         return LH_EDEVICE;
     }
-    R->allocs.push_back(p);
+    (list ? list : &R->allocs)->push_back(p);
     *out = static_cast<T*>(p);
     return LH_OK;
 }
 
 template <class T>
-static int upload(lh_rom* R, const std::vector<T>& h, const T** out) {
+static int upload(lh_rom* R, const std::vector<T>& h, const T** out, std::vector<void*>* list = nullptr) {
     T* d = nullptr;
-    int rc = dev_alloc(R, &d, h.size());
+    int rc = dev_alloc(R, &d, h.size(), list);
     if (rc) return rc;
     // synchronous: the host vectors are temporaries of the caller
     if (!h.empty()) LH_HIP_CHECK(hipMemcpy(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
@@ -1340,7 +1341,8 @@ static int build_views(lh_rom* R, int i, int G) {
             V.nown = (int)own.size();
             V.nth = (int)th.size() / 3;
             int rc;
-            if ((rc = upload(R, kin, &V.kin)) || (rc = upload(R, own, &V.own)) || (rc = upload(R, th, &V.th)))
+            if ((rc = upload(R, kin, &V.kin, &R->view_allocs)) || (rc = upload(R, own, &V.own, &R->view_allocs)) ||
+                (rc = upload(R, th, &V.th, &R->view_allocs)))
                 return rc;
             const int64_t b64 = resident_bytes(dim, H, V.ns, V.nkin, V.nth, 8);
             const int64_t b32 = resident_bytes(dim, H, V.ns, V.nkin, V.nth, 4);
@@ -1352,7 +1354,7 @@ static int build_views(lh_rom* R, int i, int G) {
             R->res_max32 = std::max(R->res_max32, V.res_bytes32);
         }
         const WgView* dv;
-        int rc = upload(R, views, &dv);
+        int rc = upload(R, views, &dv, &R->view_allocs);
         if (rc) return rc;
         wins[w].views = dv;
     }
@@ -1447,9 +1449,9 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
         int ie = 0;
         for (auto& W : R->h_win[i]) ie = std::max(ie, W.n_el);
         if ((rc = dev_alloc(R, &I.sig, (int64_t)ie * NQ * dim * dim)) ||
-            (rc = dev_alloc(R, &I.part, (int64_t)2 * G * PSTRIDE)) || (rc = dev_alloc(R, &I.flag, G)))
+            (rc = dev_alloc(R, &I.part, (int64_t)2 * MAX_G * PSTRIDE)) || (rc = dev_alloc(R, &I.flag, MAX_G)))
             return fail(rc);
-        hipLaunchKernelGGL(zero_int_kernel, dim3((G + 63) / 64), dim3(64), 0, s, I.flag, (int64_t)G);
+        hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, I.flag, (int64_t)MAX_G);
         const WinDev* dw;
         if ((rc = upload(R, R->h_win[i], &dw))) return fail(rc);
         I.win = dw;
@@ -1469,6 +1471,7 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
 void rom_destroy(lh_rom* R) {
     if (!R) return;
     for (void* q : R->allocs) (void)hipFree(q);
+    for (void* q : R->view_allocs) (void)hipFree(q);
     delete R;
 }
 
@@ -1515,17 +1518,77 @@ static int launch_rom(const lh_rom* R, const RomArgs& A, size_t dyn, hipStream_t
     return launch_check("rom_step_kernel");
 }
 
-template <int DIM>
-static int dispatch(const lh_rom* R, const RomArgs& A, bool f32, hipStream_t s) {
-    const size_t entries = 8 * (size_t)(A.nkin_max + A.nth_max + (int64_t)((A.G + 7) / 8) * PSTRIDE) +
-                           4 * (size_t)A.mlp_floats;
+// Dynamic LDS of a launch with G workgroups per instance, and whether every
+// workgroup's window tiles fit in it (otherwise they are read from global memory).
+struct LaunchShape {
+    size_t dyn;
+    bool resident;
+};
+
+static LaunchShape launch_shape(const lh_rom* R, int G, bool f32, int mlp_floats) {
+    const size_t entries = 8 * (size_t)(R->nkin_max + R->nth_max + (int64_t)((G + 7) / 8) * PSTRIDE) +
+                           4 * (size_t)mlp_floats;
     const int budget = lds_budget() - STATIC_LDS_RESERVE;
     const int res = f32 ? R->res_max32 : R->res_max64;
     const bool resident = (int64_t)entries + res <= budget;
-    const size_t dyn = entries + (resident ? (size_t)res : 0);
+    return {entries + (resident ? (size_t)res : 0), resident};
+}
+
+template <int DIM>
+static int dispatch(const lh_rom* R, const RomArgs& A, bool f32, hipStream_t s) {
+    const LaunchShape sh = launch_shape(R, A.G, f32, A.mlp_floats);
+    const size_t dyn = sh.dyn;
     if (f32)
-        return resident ? launch_rom<DIM, float, true>(R, A, dyn, s) : launch_rom<DIM, float, false>(R, A, dyn, s);
-    return resident ? launch_rom<DIM, double, true>(R, A, dyn, s) : launch_rom<DIM, double, false>(R, A, dyn, s);
+        return sh.resident ? launch_rom<DIM, float, true>(R, A, dyn, s) : launch_rom<DIM, float, false>(R, A, dyn, s);
+    return sh.resident ? launch_rom<DIM, double, true>(R, A, dyn, s) : launch_rom<DIM, double, false>(R, A, dyn, s);
+}
+
+template <int DIM, class TT, bool RES>
+static int blocks_per_cu(size_t dyn, int* nb) {
+    auto kern = rom_step_kernel<DIM, TT, RES>;
+    if (dyn > 0) LH_HIP_CHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+    LH_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, (const void*)kern, BLK, dyn));
+    return LH_OK;
+}
+
+// Whether n_inst x R->G workgroups can all be resident at once (needed for the
+// cooperative launch when G > 1) with the launch that `flags` selects.
+static int fits_coresident(const lh_rom* R, uint32_t flags, bool* ok) {
+    const bool f32 = (flags & LH_FP32_LIFT) != 0;
+    const int mlp = (flags & LH_SURROGATE) ? R->mlp_floats : 0;
+    const LaunchShape sh = launch_shape(R, R->G, f32, mlp);
+    int nb = 0, rc;
+    if (R->p->dim == 2)
+        rc = f32 ? (sh.resident ? blocks_per_cu<2, float, true>(sh.dyn, &nb) : blocks_per_cu<2, float, false>(sh.dyn, &nb))
+                 : (sh.resident ? blocks_per_cu<2, double, true>(sh.dyn, &nb) : blocks_per_cu<2, double, false>(sh.dyn, &nb));
+    else
+        rc = f32 ? (sh.resident ? blocks_per_cu<3, float, true>(sh.dyn, &nb) : blocks_per_cu<3, float, false>(sh.dyn, &nb))
+                 : (sh.resident ? blocks_per_cu<3, double, true>(sh.dyn, &nb) : blocks_per_cu<3, double, false>(sh.dyn, &nb));
+    if (rc) return rc;
+    *ok = R->G == 1 || (int64_t)R->n_inst * R->G <= (int64_t)nb * cu_count();
+    return LH_OK;
+}
+
+// Split every window's sampled elements over G workgroups per instance: new
+// workgroup views, the device copies of the window tables updated, exchange
+// sequence numbers reset.  No launch may be using the old views.
+static int repartition(lh_rom* R, int G, hipStream_t s) {
+    for (void* q : R->view_allocs) (void)hipFree(q);
+    R->view_allocs.clear();
+    R->nkin_max = R->nth_max = R->res_max64 = R->res_max32 = 0;
+    for (int i = 0; i < R->n_inst; ++i) {
+        const int rc = build_views(R, i, G);
+        if (rc) return rc;
+    }
+    for (int i = 0; i < R->n_inst; ++i) {
+        const InstDev& I = R->h_inst[i];
+        LH_HIP_CHECK(hipMemcpy(const_cast<WinDev*>(I.win), R->h_win[i].data(), sizeof(WinDev) * R->h_win[i].size(),
+                               hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, I.flag, (int64_t)MAX_G);
+    }
+    R->G = G;
+    LH_HIP_CHECK(hipStreamSynchronize(s));
+    return launch_check("rom_set_workgroups");
 }
 
 }  // namespace rom
@@ -1691,6 +1754,98 @@ int rom_workgroups_per_instance(const lh_rom* R, int32_t* G) {
     using namespace lh;
     LH_REQUIRE(R && G, "rom_workgroups_per_instance: null argument");
     *G = R->G;
+    return LH_OK;
+}
+
+int rom_set_workgroups(lh_rom* R, int32_t G, uint32_t flags, hipStream_t s) {
+    using namespace lh;
+    using namespace lh::rom;
+    LH_REQUIRE(R, "rom_set_workgroups: null argument");
+    LH_REQUIRE(G >= 1 && G <= MAX_G, "rom_set_workgroups: G outside [1, 64]");
+    LH_HIP_CHECK(hipDeviceSynchronize());  // no rom_step may still read the old views
+    const int old = R->G;
+    int rc = repartition(R, G, s);
+    if (rc) return rc;
+    bool ok = false;
+    if ((rc = fits_coresident(R, flags, &ok))) return rc;
+    if (!ok) {
+        if ((rc = repartition(R, old, s))) return rc;
+        set_error("rom_set_workgroups: n_inst x G workgroups cannot all be resident at once");
+        return LH_EINVAL;
+    }
+    return LH_OK;
+}
+
+int rom_autotune(lh_rom* R, const lh_rom_state* state, int32_t trial_steps, uint32_t flags, const double* dt_replay,
+                 int32_t n_replay, int32_t* G_best, float* ms_best, hipStream_t s) {
+    using namespace lh;
+    using namespace lh::rom;
+    LH_REQUIRE(R && state && G_best && trial_steps >= 1, "rom_autotune: bad arguments");
+    LH_REQUIRE(!(flags & LH_REPLAY_DT) || (dt_replay && n_replay >= 0), "rom_autotune: replay needs dt_replay");
+    int max_el = 1;
+    for (auto& wins : R->h_win)
+        for (auto& W : wins) max_el = std::max(max_el, W.n_el);
+    static const int cand[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48, 64};
+    LH_HIP_CHECK(hipDeviceSynchronize());
+    const int old = R->G;
+    lh_rom_state* trial = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipMalloc(&trial, sizeof(lh_rom_state) * R->n_inst) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        if (trial) (void)hipFree(trial);
+        if (e0) (void)hipEventDestroy(e0);
+        set_error("rom_autotune: allocation failed");
+        return LH_EDEVICE;
+    }
+    std::vector<lh_rom_state> h(R->n_inst);
+    std::vector<std::pair<int, float>> timed;
+    int rc = LH_OK;
+    for (int G : cand) {
+        if (G > max_el) break;
+        if ((rc = repartition(R, G, s))) break;
+        bool ok = false;
+        if ((rc = fits_coresident(R, flags, &ok))) break;
+        if (!ok) continue;
+        // one untimed run, then the faster of two timed ones, each from the caller's state
+        float ms = 0.0f;
+        bool good = true;
+        for (int rep = 0; rep < 3 && good; ++rep) {
+            float t = 0.0f;
+            good = hipMemcpyAsync(trial, state, sizeof(lh_rom_state) * R->n_inst, hipMemcpyDeviceToDevice, s) ==
+                       hipSuccess &&
+                   hipEventRecord(e0, s) == hipSuccess &&
+                   rom_step(R, trial, trial_steps, flags, dt_replay, n_replay, s) == LH_OK &&
+                   hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                   hipEventElapsedTime(&t, e0, e1) == hipSuccess;
+            if (rep == 1 || (rep == 2 && t < ms)) ms = t;
+        }
+        if (!good) (void)hipGetLastError();  // a failed candidate leaves no error behind
+        if (good && hipMemcpy(h.data(), trial, sizeof(lh_rom_state) * R->n_inst, hipMemcpyDeviceToHost) == hipSuccess)
+            for (auto& st : h) good = good && !(st.status & LH_FLAG_TIMEOUT);
+        if (good) timed.push_back({G, ms});
+    }
+    // the smallest G within 2 % of the fastest: near-flat optima then give the same shape run to run
+    int best = -1;
+    float best_ms = 0.0f, fastest = 0.0f;
+    for (auto& c : timed) fastest = (fastest == 0.0f || c.second < fastest) ? c.second : fastest;
+    for (auto& c : timed)
+        if (c.second <= 1.02f * fastest) {
+            best = c.first;
+            best_ms = c.second;
+            break;
+        }
+    (void)hipFree(trial);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (best < 0) {
+        (void)repartition(R, old, s);
+        set_error("rom_autotune: no launch shape ran");
+        return LH_EDEVICE;
+    }
+    if ((rc = repartition(R, best, s))) return rc;
+    *G_best = best;
+    if (ms_best) *ms_best = best_ms;
     return LH_OK;
 }
 

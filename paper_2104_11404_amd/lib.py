@@ -97,6 +97,8 @@ _SIGNATURES = {
     "rom_lift": (_I32, [_VP, _VP, _I32, C.POINTER(InstanceDesc), _VP, _VP, _VP, _VP]),
     "rom_sampled_elements": (_I32, [_VP, _I32, _I32, C.POINTER(_I32)]),
     "rom_workgroups_per_instance": (_I32, [_VP, C.POINTER(_I32)]),
+    "rom_set_workgroups": (_I32, [_VP, _I32, _U32, _VP]),
+    "rom_autotune": (_I32, [_VP, _VP, _I32, _U32, _VP, _I32, C.POINTER(_I32), C.POINTER(C.c_float), _VP]),
     "mlp_create": (_I32, [C.POINTER(MlpDesc), _I32, C.POINTER(_VP)]),
     "mlp_destroy": (None, [_VP]),
     "mlp_set_params": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -383,6 +385,23 @@ class Rom:
         self._keep.append(mlp)
         _check(load().rom_attach_surrogate(self.h, int(i), int(w), None if mlp is None else mlp.h, int(audit_every),
                                            float(tol)))
+
+    def workgroups(self):
+        """Workgroups per instance of the rom_step launch."""
+        g = _I32()
+        _check(load().rom_workgroups_per_instance(self.h, C.byref(g)))
+        return g.value
+
+    def set_workgroups(self, G, flags=0):
+        _check(load().rom_set_workgroups(self.h, int(G), int(flags), stream_handle()))
+
+    def autotune(self, trial_steps=200, flags=0, dt_replay=None):
+        """Time the candidate launch shapes from the current state (left unchanged); returns (G, ms)."""
+        g, ms = _I32(), C.c_float()
+        n_rep = 0 if dt_replay is None else int(dt_replay.numel())
+        _check(load().rom_autotune(self.h, ptr(self.state), int(trial_steps), int(flags), ptr(dt_replay), n_rep,
+                                   C.byref(g), C.byref(ms), stream_handle()))
+        return g.value, ms.value
 
     def sampled_elements(self, i, w):
         n = _I32()
