@@ -231,23 +231,22 @@ def batched_gresho(lib, pipeline, n_inst: int = 256, reps: int = 3, lam=None):
     return out
 
 
-def surrogate_tg2d(lib, pipeline, n_inst: int = 64, train_steps: int = 4000, reps: int = 3, audit_every: int = 10,
-                   tol: float = 0.05, n_fixed=None, lam=None, variants=None):
-    """Batched plain DEIM ROM against the surrogate ROM, parametric 2D Taylor-Green.
+def surrogate_param(lib, pipeline, wl, n_train: int = 17, train_steps: int = 4000, reps: int = 3,
+                    audit_every: int = 10, tol: float = 0.05, n_fixed=None, lam=None, variants=None):
+    """Batched plain DEIM ROM against the surrogate ROM, parametric Taylor-Green (2D or 3D).
 
-    32 x 32 mesh, fixed dt = 1e-3 to t = 0.2, amplitude A ~ U[0.8, 1.2] per instance; bases (one
-    window, dims 20/20/20, lambda = 2) from GPU FOM runs at A = 0.8, 1.0, 1.2, relative to the A = 1
-    initial state.  The network (inputs [x^, v^, e^, t], 3 tanh layers of 256, bfloat16 operands)
-    is trained on the GPU on the snapshots of GPU FOM runs at 17 amplitudes in [0.8, 1.2], projected
-    onto those bases; in the surrogate runs every
-    audit_every-th step is a DEIM audit.  Errors: each instance's lifted final state against its own
-    GPU FOM run.
+    Fixed dt, amplitude A ~ U[0.8, 1.2] per instance; bases (one window, dims 20/20/20, lambda = 2)
+    from GPU FOM runs at A = 0.8, 1.0, 1.2, relative to the A = 1 initial state.  The network
+    (inputs [x^, v^, e^, t], 3 tanh layers of 256, bfloat16 operands) is trained on the GPU on the
+    snapshots of GPU FOM runs at n_train amplitudes in [0.8, 1.2], projected onto those bases; in
+    the surrogate runs every audit_every-th step is a DEIM audit.  Errors: each instance's lifted
+    final state against its own GPU FOM run.
     """
     import torch
 
     import workloads as Wl
 
-    wl = Wl.tg2d_param(n_inst=n_inst)
+    n_inst = len(wl.params)
     t0 = time.perf_counter()
     trajs = []
     for A in Wl.TG_TRAIN_AMPS:
@@ -272,7 +271,7 @@ def surrogate_tg2d(lib, pipeline, n_inst: int = 64, train_steps: int = 4000, rep
     t1 = time.perf_counter()
     # network training data: the projected snapshots of FOM runs at 17 amplitudes spread over the range
     ntr = [pipeline.fom_trajectory(lib.Problem.from_workload(wl, amp=float(A)), wl.t_final, fixed_dt=wl.fixed_dt)
-           for A in np.linspace(0.8, 1.2, 17)]
+           for A in np.linspace(0.8, 1.2, n_train)]
     X = pipeline.surrogate_inputs(rom, 0, 0, ntr)
     del ntr
     net, T, hist = pipeline.train_surrogate(rom, 0, 0, X, steps=train_steps, lr=2e-3, lr_final=1e-4)
@@ -281,11 +280,14 @@ def surrogate_tg2d(lib, pipeline, n_inst: int = 64, train_steps: int = 4000, rep
     print(f"[bench] surrogate: {int(X.shape[0])} samples, loss {hist[0]:.3e} -> {hist[-1]:.3e} in {t_train:.1f} s",
           file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
-    out = {"workload": f"tg2d_32x32_param_A0.8-1.2_batch{n_inst}_fixed_dt1e-3_t{wl.t_final:g}_dims20_lambda2",
+    mesh = "x".join(str(n) for n in wl.nel[:wl.dim])
+    out = {"workload": f"tg{wl.dim}d_{mesh}_param_A0.8-1.2_batch{n_inst}_fixed_dt{wl.fixed_dt:g}_t{wl.t_final:g}"
+                       f"_dims{n_fixed[0]}_lambda{lam[0]:g}",
            "instances": n_inst, "heuristic_workgroups_per_instance": rom.workgroups(), "offline_s": t_offline,
            "training": {"samples": int(X.shape[0]), "steps": train_steps, "seconds": t_train,
                         "loss_first": hist[0], "loss_last": hist[-1],
-                        "network": [int(X.shape[1]), 256, 256, 256, int(T.shape[1])]}}
+                        "network": [int(X.shape[1]), 256, 256, 256, int(T.shape[1])]},
+           "sampled_elements": rom.sampled_elements(0, 0)}
     runs = [("deim", lib.LH_FIXED_DT, audit_every, tol), ("surrogate", lib.LH_FIXED_DT | lib.LH_SURROGATE, audit_every, tol)]
     for k_, tol_ in variants or ():
         runs.append((f"surrogate_K{k_}_tol{tol_:g}", lib.LH_FIXED_DT | lib.LH_SURROGATE, k_, tol_))
@@ -316,7 +318,7 @@ def surrogate_tg2d(lib, pipeline, n_inst: int = 64, train_steps: int = 4000, rep
                      "median_rel_error_vs_fom": dict(zip("xve", np.median(errs, axis=0).tolist())),
                      "audits": sum(st.n_audits for st in sts), "surrogate_steps": sum(st.n_surrogate_steps for st in sts),
                      "fallback_windows": sum(st.n_fallbacks for st in sts)}
-        print(f"[bench] {name}: {t * 1e3:.2f} ms, {steps / t:.0f} ROM steps/s, max err "
+        print(f"[bench] {wl.dim}D {name}: {t * 1e3:.2f} ms, {steps / t:.0f} ROM steps/s, max err "
               f"{errs.max(axis=0)}", file=sys.stderr, flush=True)
     out["speedup_surrogate_vs_deim"] = out["surrogate"]["rom_steps_per_s"] / out["deim"]["rom_steps_per_s"]
     return out
@@ -471,7 +473,9 @@ def main():
     if not args.no_batch:
         out["batched"] = batched_gresho(lib, pipeline)
     if not args.no_surrogate:
-        out["surrogate"] = surrogate_tg2d(lib, pipeline, train_steps=10000, variants=[(25, 1e30)])
+        out["surrogate"] = surrogate_param(lib, pipeline, Wl.tg2d_param(), train_steps=10000, variants=[(25, 1e30)])
+        out["surrogate_3d"] = surrogate_param(lib, pipeline, Wl.tg3d_param(), n_train=9, train_steps=10000,
+                                              variants=[(25, 1e30)])
     if not args.no_cpu_baseline:
         med = [int(sorted(d[f] for d in dims)[len(dims) // 2]) for f in range(3)]
         out["cpu_baseline"] = cpu_baseline(wl, med, st.n_force_evals / st.n_steps, args.cpu_seconds)

@@ -77,3 +77,55 @@ def test_surrogate_targets_3d_match_oracle(gpu_lib, tg3):
     Tg = lib.rom_surrogate_targets(G, 0, 0, _t(X[idx])).cpu().numpy()
     for r, i in enumerate(idx):
         assert np.linalg.norm(Tg[r] - T[i]) <= 1e-10 * np.linalg.norm(T[i]), i
+
+
+def _net3d(rom, X, T, seed):
+    from tests.test_gpu_mlp import make_net
+    din, dout = M.layout(rom.windows[0])
+    mu_in, s_in = M.normalisation(X)
+    mu_out, s_out = M.normalisation(T)
+    return make_net([din, 32, 32, dout], seed, scale=0.3, mu_in=mu_in, s_in=s_in, mu_out=mu_out, s_out=0.05 * s_out)
+
+
+def test_surrogate_rom3d_matches_oracle(gpu_lib, tg3):
+    """In-kernel network inference on hexahedra: same audits and surrogate steps as the oracle,
+    reduced state within the bfloat16 bound."""
+    from paper_2104_11404_amd import lib
+    from tests.test_gpu_mlp import gpu_net
+    wl, op, tr, y0, rom = tg3
+    X, T = M.training_set(op, rom, 0, [tr], [[0] * len(tr.snaps)])
+    net = _net3d(rom, X, T, 61)
+    run = M.run_surrogate(op, rom, {0: net}, y0, wl.t_final, audit_every=5, tol=10.0, fixed_dt=2e-4)
+    print(f"[case] surrogate rom 3d tg 4^3: {run.audits} audits, {run.surrogate_steps} surrogate steps", flush=True)
+    assert run.audits >= 2 and run.surrogate_steps >= 10 and not run.fallback_windows
+    P = lib.Problem.from_workload(wl)
+    G = lib.Rom(P, [gpu_instance(rom, wl.t_final)])
+    G.attach_surrogate(0, 0, gpu_net(net, 16), audit_every=5, tol=10.0)
+    G.init_state(_t(y0[0]), _t(y0[1]), _t(y0[2]), 2e-4)
+    G.step(flags=lib.LH_SURROGATE | lib.LH_FIXED_DT)
+    st = G.states()[0]
+    assert st.status == 0 and st.n_steps == len(run.dt)
+    assert st.n_audits == run.audits and st.n_surrogate_steps == run.surrogate_steps and st.n_fallbacks == 0
+    for a, b in zip(G.coords(0), run.yhat):
+        assert rel(a, b) < 1e-3
+
+
+def test_surrogate_rom3d_fallback_is_the_plain_rom(gpu_lib, tg3):
+    from paper_2104_11404_amd import lib
+    from tests.test_gpu_mlp import gpu_net
+    wl, op, tr, y0, rom = tg3
+    print("[case] surrogate fallback 3d tg 4^3", flush=True)
+    X, T = M.training_set(op, rom, 0, [tr], [[0] * len(tr.snaps)])
+    P = lib.Problem.from_workload(wl)
+    G = lib.Rom(P, [gpu_instance(rom, wl.t_final)])
+    G.attach_surrogate(0, 0, gpu_net(_net3d(rom, X, T, 62), 16), audit_every=3, tol=-1.0)
+    G.init_state(_t(y0[0]), _t(y0[1]), _t(y0[2]), 2e-4)
+    G.step(flags=lib.LH_SURROGATE | lib.LH_FIXED_DT)
+    st = G.states()[0]
+    assert st.n_fallbacks == 1 and st.n_audits == 1 and st.n_surrogate_steps == 0
+    G2 = lib.Rom(P, [gpu_instance(rom, wl.t_final)])
+    G2.init_state(_t(y0[0]), _t(y0[1]), _t(y0[2]), 2e-4)
+    G2.step(flags=lib.LH_FIXED_DT)
+    assert G2.states()[0].n_steps == st.n_steps
+    for a, b in zip(G.coords(0), G2.coords(0)):
+        np.testing.assert_array_equal(a, b)
