@@ -1,17 +1,22 @@
 // rom_build_basis: POD by thin SVD of the snapshot matrix (eq. SVD) with the
 // singular-value-sum energy criterion (eq. energy_criteria).
 //
-// S (N x m, N >= m) is factorised by Householder QR in FP64: one reflector
-// per column, each step a norm reduction, a transposed GEMV over the
-// remaining rows and a rank-1 update of the trailing columns, all spread
-// over the whole GPU.  The same GEMV yields the column v_j^T v_k of the
-// triangular factor of the compact representation Q = I - V S^{-1} V^T
-// (S upper triangular, S_jj = 1/tau_j, S_jk = v_j^T v_k).  The m x m factor R
-// is diagonalised from the right by one-sided Jacobi rotations (round-robin
-// pairs, one workgroup per pair), giving R = U_R Sigma W^T; the basis is
-// Phi = Q [U_R(:, :n); 0] = [U_n; 0] - V S^{-1} (V_top^T U_n).
-// Columns are finally signed so that their largest-magnitude entry (first
-// such row) is positive.
+// S (N x m, N >= m) is factorised by blocked Householder QR in FP64.  The
+// columns are taken in panels of NB: inside a panel, one reflector per column
+// (a norm reduction, a transposed GEMV over the panel's columns and a rank-1
+// update of the panel); the same GEMV yields the panel's triangular factor of
+// the compact representation Q_p = I - V_p S_p^{-1} V_p^T (S_p upper
+// triangular, (S_p)_jj = 1/tau_j, (S_p)_jk = v_j^T v_k).  The trailing columns
+// then take the whole panel at once, A <- Q_p^T A = A - V_p S_p^{-T} (V_p^T A):
+// a split-K product V_p^T A (row chunks into partial sums added in a fixed
+// order), an NB x NB triangular solve and a rank-NB update, so the trailing
+// matrix is read and written once per panel instead of once per column.
+// The m x m factor R is diagonalised from the right by one-sided Jacobi
+// rotations (round-robin pairs, one workgroup per pair), giving
+// R = U_R Sigma W^T; the basis Phi = Q [U_R(:, :n); 0] is formed by applying
+// the panels' Q_p to [U_n; 0] from the last panel to the first, with the same
+// three kernels.  Columns are finally signed so that their largest-magnitude
+// entry (first such row) is positive.
 #include <algorithm>
 #include <numeric>
 #include <vector>
@@ -21,7 +26,10 @@
 namespace lh {
 namespace pod {
 
-constexpr int RB = 1024;  // threads of single-workgroup reductions
+constexpr int NB = 32;       // panel width of the blocked QR
+constexpr int SL = 64;       // rows per LDS slice of the panel products
+constexpr int TC = 64;       // columns per tile of the panel products
+constexpr int CHUNK = 2048;  // rows per split-K partial sum of V_p^T X
 
 __device__ double block_sum(double v, double* sh) {
     const int tid = threadIdx.x;
@@ -42,72 +50,207 @@ __global__ void copy_cols_kernel(const double* S, int64_t ldS, double* A, int64_
     if (i < N && j < m) A[(int64_t)j * N + i] = S[(int64_t)j * ldS + i];
 }
 
-// Reflector of column k: H = I - tau v v^T with v_k = 1 mapping A[k:,k] to beta e_k.
-__global__ void __launch_bounds__(RB) house_gen_kernel(double* A, int64_t N, int k, double* v, double* tau,
-                                                       double* beta) {
-    __shared__ double sh[RB];
-    double* col = A + (int64_t)k * N;
-    const double alpha = col[k];  // read before any thread writes the column
-    double acc = 0.0;
-    for (int64_t i = k + 1 + threadIdx.x; i < N; i += RB) acc += col[i] * col[i];
-    const double xnorm2 = block_sum(acc, sh);
-    if (xnorm2 == 0.0) {
-        for (int64_t i = threadIdx.x; i < N; i += RB) v[i] = 0.0;
-        if (threadIdx.x == 0) {
-            tau[k] = 0.0;
-            beta[k] = alpha;
-        }
-        return;
+// One reflector step of a panel, column k of the panel [p, pe).  H = I - tau v v^T with v_k = 1 maps
+// A[k:, k] to beta e_k.  With a_i = A[i, k] (i > k) and v_i = a_i / (alpha - beta), every quantity the
+// step needs is a dot product of the unscaled column k with a panel column, d_j = sum_{i>k} a_i A[i, j]
+// (d_k = |a|^2): w_j = v^T A[:, j] = A[k, j] + d_j / (alpha - beta), which for j < k is v_k^T v_j, the
+// entry of S_p.  So a step is one split-row pass for the d_j, a scalar step, and one row-parallel
+// update that also scales column k in place.
+constexpr int DCH = 2048;  // rows per partial sum of the d_j
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// dpart[b * NB + j] = sum over rows of chunk b (rows > k) of A[i, k] A[i, p + j].
+__global__ void __launch_bounds__(256) panel_dots_kernel(const double* A, int64_t N, int k, int p, int nbp,
+                                                        double* dpart) {
+    __shared__ double sh[4][NB];
+    const int64_t r0 = k + 1 + (int64_t)blockIdx.x * DCH;
+    const int64_t r1 = r0 + DCH < N ? r0 + DCH : N;
+    double acc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) {
+        const double a = A[(int64_t)k * N + i];
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (j < nbp) acc[j] += a * A[(int64_t)(p + j) * N + i];
     }
-    const double b = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-    const double scal = 1.0 / (alpha - b);
-    for (int64_t i = threadIdx.x; i < N; i += RB) {
-        double vi;
-        if (i < k)
-            vi = 0.0;
-        else if (i == k)
-            vi = 1.0;
-        else {
-            vi = col[i] * scal;
-            col[i] = vi;
-        }
-        v[i] = vi;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const double t = wave_sum(acc[j]);
+        if (lane == 0) sh[wv][j] = t;
     }
-    if (threadIdx.x == 0) {
-        tau[k] = (b - alpha) / b;
+    __syncthreads();
+    if ((int)threadIdx.x < nbp) {
+        const int j = threadIdx.x;
+        dpart[(int64_t)blockIdx.x * NB + j] = ((sh[0][j] + sh[1][j]) + sh[2][j]) + sh[3][j];
+    }
+}
+
+// The step's scalars from the partial sums (added in chunk order): tau_k, beta_k, 1/(alpha - beta),
+// w_j for the panel's columns, and column k - p of S_p.  One workgroup of 64 threads.
+__global__ void panel_scalars_kernel(const double* A, int64_t N, int k, int p, int nbp, int nch, const double* dpart,
+                                     double* tau, double* beta, double* scal, double* w, double* Sp) {
+    __shared__ double d[NB];
+    const int j = threadIdx.x;
+    if (j < nbp) {
+        double acc = 0.0;
+        for (int b = 0; b < nch; ++b) acc += dpart[(int64_t)b * NB + j];
+        d[j] = acc;
+    }
+    __syncthreads();
+    const double alpha = A[(int64_t)k * N + k];
+    const double xnorm2 = d[k - p];
+    double t = 0.0, b = alpha, sc = 0.0;
+    if (xnorm2 != 0.0) {
+        b = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+        sc = 1.0 / (alpha - b);
+        t = (b - alpha) / b;
+    }
+    if (j < nbp) {
+        const double wj = xnorm2 != 0.0 ? A[(int64_t)(p + j) * N + k] + sc * d[j] : 0.0;
+        w[p + j] = wj;
+    }
+    if (j < NB) {
+        double val = 0.0;
+        if (j < k - p)
+            val = xnorm2 != 0.0 ? A[(int64_t)(p + j) * N + k] + sc * d[j] : 0.0;
+        else if (j == k - p)
+            val = t != 0.0 ? 1.0 / t : 1.0;
+        Sp[(int64_t)(k - p) * NB + j] = val;
+    }
+    if (j == 0) {
+        tau[k] = t;
         beta[k] = b;
-        col[k] = b;
+        scal[k] = sc;
     }
 }
 
-// w[j] = sum_{i >= k} v[i] A[i, j] for every column j (one workgroup each).
-__global__ void __launch_bounds__(256) house_w_kernel(const double* A, int64_t N, int k, const double* v,
-                                                     double* w) {
-    __shared__ double sh[256];
-    const int j = blockIdx.x;
-    const double* col = A + (int64_t)j * N;
-    double acc = 0.0;
-    for (int64_t i = k + threadIdx.x; i < N; i += 256) acc += v[i] * col[i];
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) w[j] = s;
+// Rows i >= k: A[i, j] -= tau v_i w_j for the panel's columns k < j < pe, then column k becomes
+// (beta, v_{k+1}, ...).  Each thread owns one row, so reading a_i and overwriting it do not race.
+__global__ void panel_house_kernel(double* A, int64_t N, int k, int pe, const double* tau, const double* beta,
+                                   const double* scal, const double* w) {
+    const int64_t i = k + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double t = tau[k];
+    if (i >= N || t == 0.0) return;
+    const double vi = i == k ? 1.0 : scal[k] * A[(int64_t)k * N + i];
+    for (int j = k + 1; j < pe; ++j) A[(int64_t)j * N + i] -= t * vi * w[j];
+    A[(int64_t)k * N + i] = i == k ? beta[k] : vi;
 }
 
-// Trailing update A[i, j] -= tau v[i] w[j] (i >= k, j > k) and column k of S.
-__global__ void house_update_kernel(double* A, int64_t N, int m, int k, const double* v, const double* tau,
-                                    const double* w, double* Sm) {
-    const int64_t i = k + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = k + 1 + blockIdx.y;
-    const double t = tau[k];
-    if (i < N && j < m && t != 0.0) A[(int64_t)j * N + i] -= t * v[i] * w[j];
-    if (blockIdx.x == 0 && blockIdx.y == 0) {
-        for (int r = threadIdx.x; r < m; r += blockDim.x) {
-            double val = 0.0;
-            if (r < k)
-                val = w[r];
-            else if (r == k)
-                val = t != 0.0 ? 1.0 / t : 1.0;
-            Sm[(int64_t)k * m + r] = val;
+// Entry (i, j) of V_p: reflector p + j, unit on the diagonal (zero when tau = 0), stored below the
+// diagonal of A, zero above.
+__device__ __forceinline__ double panel_v(const double* A, int64_t N, int p, int j, int64_t i, const double* tau) {
+    const int k = p + j;
+    if (i < k) return 0.0;
+    if (i == k) return tau[k] != 0.0 ? 1.0 : 0.0;
+    return A[(int64_t)k * N + i];
+}
+
+// Split-K partial sums of W = V_p^T X over rows [row0, N): workgroup (chunk, column tile) adds the
+// CHUNK rows of its chunk, part[(chunk * NB + j) * ncols + c].  Wave g of the workgroup owns
+// rows j = 8g .. 8g + 7 of W; lane l owns column c0 + l.
+__global__ void __launch_bounds__(256) panel_vtx_kernel(const double* A, int64_t N, int p, int nbp,
+                                                       const double* tau, const double* X, int64_t ldx, int ncols,
+                                                       int64_t row0, double* part) {
+    __shared__ double Vs[SL][NB + 1];  // padded: the slice is written row-fastest
+    __shared__ double Xs[SL][TC + 1];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, g = tid >> 6;
+    const int c0 = blockIdx.y * TC;
+    const int64_t r_beg = row0 + (int64_t)blockIdx.x * CHUNK;
+    const int64_t r_end = r_beg + CHUNK < N ? r_beg + CHUNK : N;
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    for (int64_t s0 = r_beg; s0 < r_end; s0 += SL) {
+        for (int t = tid; t < SL * NB; t += 256) {
+            const int r = t % SL, j = t / SL;
+            const int64_t i = s0 + r;
+            Vs[r][j] = (i < r_end && j < nbp) ? panel_v(A, N, p, j, i, tau) : 0.0;
         }
+        for (int t = tid; t < SL * TC; t += 256) {
+            const int r = t % SL, c = t / SL;
+            const int64_t i = s0 + r;
+            Xs[r][c] = (i < r_end && c0 + c < ncols) ? X[(int64_t)(c0 + c) * ldx + i] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int r = 0; r < SL; ++r) {
+            const double x = Xs[r][lane];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] += Vs[r][8 * g + q] * x;
+        }
+        __syncthreads();
+    }
+    if (c0 + lane < ncols)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int j = 8 * g + q;
+            if (j < nbp) part[((int64_t)blockIdx.x * NB + j) * ncols + c0 + lane] = acc[q];
+        }
+}
+
+// W[j * ncols + c] = sum over chunks, in chunk order, of the partial sums.
+__global__ void panel_reduce_kernel(const double* part, int n_chunks, int nbp, int ncols, double* W) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nbp * ncols) return;
+    const int j = (int)(t / ncols), c = (int)(t % ncols);
+    double acc = 0.0;
+    for (int b = 0; b < n_chunks; ++b) acc += part[((int64_t)b * NB + j) * ncols + c];
+    W[t] = acc;
+}
+
+// Column c of W overwritten by S_p^{-T} W (transposed: forward substitution) or S_p^{-1} W (back
+// substitution); one thread per column.
+__global__ void panel_solve_kernel(const double* Sp, int nbp, double* W, int ncols, int transposed) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncols) return;
+    if (transposed) {
+        for (int j = 0; j < nbp; ++j) {
+            double acc = W[(int64_t)j * ncols + c];
+            for (int l = 0; l < j; ++l) acc -= Sp[j * NB + l] * W[(int64_t)l * ncols + c];
+            W[(int64_t)j * ncols + c] = acc / Sp[j * NB + j];
+        }
+    } else {
+        for (int j = nbp - 1; j >= 0; --j) {
+            double acc = W[(int64_t)j * ncols + c];
+            for (int l = j + 1; l < nbp; ++l) acc -= Sp[l * NB + j] * W[(int64_t)l * ncols + c];
+            W[(int64_t)j * ncols + c] = acc / Sp[j * NB + j];
+        }
+    }
+}
+
+// X[i, c] -= sum_j V_p[i, j] Y[j, c] for rows i >= row0: one thread per row holding its row of V_p,
+// a tile of TU columns of Y in LDS.
+constexpr int TU = 32;
+__global__ void __launch_bounds__(256) panel_update_kernel(const double* A, int64_t N, int p, int nbp,
+                                                          const double* tau, const double* Y, int ncols, double* X,
+                                                          int64_t ldx, int64_t row0) {
+    __shared__ double Ys[NB][TU];
+    const int c0 = blockIdx.y * TU;
+    for (int t = threadIdx.x; t < NB * TU; t += 256) {
+        const int j = t / TU, c = t % TU;
+        Ys[j][c] = (j < nbp && c0 + c < ncols) ? Y[(int64_t)j * ncols + c0 + c] : 0.0;
+    }
+    __syncthreads();
+    const int64_t i = row0 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    double v[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) v[j] = j < nbp ? panel_v(A, N, p, j, i, tau) : 0.0;
+    const int nc = ncols - c0 < TU ? ncols - c0 : TU;
+    for (int c = 0; c < nc; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc += v[j] * Ys[j][c];
+        double* x = X + (int64_t)(c0 + c) * ldx + i;
+        *x -= acc;
     }
 }
 
@@ -185,76 +328,11 @@ __global__ void select_kernel(const double* W, int m, const int* perm, const dou
     if (c == 0 && r < m) sig_out[r] = sig_raw[perm[r]];
 }
 
-// X[j, c] = sum_{i=j}^{m-1} V[i, j] Un[i, c]  (V unit lower trapezoidal, stored below the diagonal of A)
-__global__ void __launch_bounds__(256) vtop_t_kernel(const double* A, int64_t N, int m, const double* tau,
-                                                    const double* Un, int n, double* X) {
-    __shared__ double sh[256];
-    const int j = blockIdx.x;
-    const int c = blockIdx.y;
-    const double* col = A + (int64_t)j * N;
-    double acc = 0.0;
-    for (int i = j + threadIdx.x; i < m; i += 256) {
-        const double vij = i == j ? (tau[j] != 0.0 ? 1.0 : 0.0) : col[i];
-        acc += vij * Un[(int64_t)c * m + i];
-    }
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) X[(int64_t)c * m + j] = s;
-}
-
-// Y = S^{-1} X by back substitution, one workgroup per column.
-__global__ void __launch_bounds__(256) back_subst_kernel(const double* Sm, int m, const double* X, double* Y) {
-    __shared__ double sh[256];
-    const int c = blockIdx.x;
-    const double* x = X + (int64_t)c * m;
-    double* y = Y + (int64_t)c * m;
-    for (int j = m - 1; j >= 0; --j) {
-        double acc = 0.0;
-        for (int l = j + 1 + threadIdx.x; l < m; l += 256) acc += Sm[(int64_t)l * m + j] * y[l];
-        const double s = block_sum(acc, sh);
-        if (threadIdx.x == 0) y[j] = (x[j] - s) / Sm[(int64_t)j * m + j];
-        __syncthreads();
-    }
-}
-
-// Phi[i, c] = [i < m] Un[i, c] - sum_{j <= min(i, m-1)} V[i, j] Y[j, c]
-__global__ void __launch_bounds__(256) form_phi_kernel(const double* A, int64_t N, int m, const double* tau,
-                                                      const double* Un, const double* Y, int n, double* Phi,
-                                                      int64_t ldPhi) {
-    constexpr int CH = 64;
-    constexpr int CG = 32;  // basis columns per block
-    __shared__ double sy[CH][CG + 1];
+// Phi[i, c] = [i < m] Un[i, c]
+__global__ void init_phi_kernel(const double* Un, int64_t N, int m, double* Phi, int64_t ldPhi) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c0 = blockIdx.y * CG;
-    const int nc = min(CG, n - c0);
-    double acc[CG];
-#pragma unroll
-    for (int c = 0; c < CG; ++c) acc[c] = 0.0;
-    for (int j0 = 0; j0 < m; j0 += CH) {
-        __syncthreads();
-        for (int t = threadIdx.x; t < CH * nc; t += blockDim.x) {
-            const int jj = t % CH, c = t / CH;
-            sy[jj][c] = (j0 + jj < m) ? Y[(int64_t)(c0 + c) * m + j0 + jj] : 0.0;
-        }
-        __syncthreads();
-        if (i < N) {
-            const int jmax = min(CH, m - j0);
-            for (int jj = 0; jj < jmax; ++jj) {
-                const int j = j0 + jj;
-                if (j > i) break;
-                const double vij = (i == j) ? (tau[j] != 0.0 ? 1.0 : 0.0) : A[(int64_t)j * N + i];
-                if (vij == 0.0) continue;
-#pragma unroll
-                for (int c = 0; c < CG; ++c)
-                    if (c < nc) acc[c] += vij * sy[jj][c];
-            }
-        }
-    }
-    if (i < N) {
-        for (int c = 0; c < nc; ++c) {
-            const double u = i < m ? Un[(int64_t)(c0 + c) * m + i] : 0.0;
-            Phi[(int64_t)(c0 + c) * ldPhi + i] = u - acc[c];
-        }
-    }
+    const int c = blockIdx.y;
+    if (i < N) Phi[(int64_t)c * ldPhi + i] = i < m ? Un[(int64_t)c * m + i] : 0.0;
 }
 
 // Canonical sign of each column: largest |entry|, smallest row on ties, made positive.
@@ -292,10 +370,12 @@ __global__ void __launch_bounds__(256) sign_kernel(double* Phi, int64_t N, int64
 }
 
 struct PodWork {
-    double *A, *v, *w, *tau, *beta, *Sm, *W, *sig_raw, *Un, *X, *Y;
+    double *A, *w, *tau, *beta, *scal, *Sp, *W, *sig_raw, *Un, *part, *Wp;
     int* perm;
     int* rotated;
 };
+
+static int64_t n_chunks(int64_t rows) { return (rows + CHUNK - 1) / CHUNK; }
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -309,20 +389,39 @@ static size_t pod_bytes(int64_t N, int m, PodWork* out, char* base) {
     const size_t D = sizeof(double);
     PodWork w;
     w.A = (double*)take(D * N * m);
-    w.v = (double*)take(D * N);
     w.w = (double*)take(D * m);
+    w.scal = (double*)take(D * m);
     w.tau = (double*)take(D * m);
     w.beta = (double*)take(D * m);
-    w.Sm = (double*)take(D * m * m);
+    w.Sp = (double*)take(D * NB * NB * (size_t)((m + NB - 1) / NB));
     w.W = (double*)take(D * m * m);
     w.sig_raw = (double*)take(D * m);
     w.Un = (double*)take(D * m * m);
-    w.X = (double*)take(D * m * m);
-    w.Y = (double*)take(D * m * m);
+    w.part = (double*)take(D * NB * (size_t)std::max<int64_t>(m * n_chunks(N), (N + DCH - 1) / DCH));
+    w.Wp = (double*)take(D * NB * (size_t)m);
     w.perm = (int*)take(sizeof(int) * m);
     w.rotated = (int*)take(sizeof(int) * 4);
     if (out) *out = w;
     return off;
+}
+
+// X <- Q_p^T X (transposed) or Q_p X, rows [p, N) of the ncols columns of X, with
+// Q_p = I - V_p S_p^{-1} V_p^T the nbp reflectors of the panel starting at column p.
+static int apply_panel(const PodWork& w, int64_t N, int p, int nbp, double* X, int64_t ldx, int ncols,
+                       const double* Sp, bool transposed, hipStream_t s) {
+    if (ncols <= 0) return LH_OK;
+    const int64_t rows = N - p;
+    const int64_t nch = n_chunks(rows);
+    hipLaunchKernelGGL(panel_vtx_kernel, dim3((unsigned)nch, (unsigned)((ncols + TC - 1) / TC)), dim3(256), 0, s, w.A,
+                       N, p, nbp, w.tau, X, ldx, ncols, (int64_t)p, w.part);
+    const int64_t nw = (int64_t)nbp * ncols;
+    hipLaunchKernelGGL(panel_reduce_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, w.part, (int)nch, nbp,
+                       ncols, w.Wp);
+    hipLaunchKernelGGL(panel_solve_kernel, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, s, Sp, nbp, w.Wp,
+                       ncols, transposed ? 1 : 0);
+    hipLaunchKernelGGL(panel_update_kernel, dim3((unsigned)((rows + 255) / 256), (unsigned)((ncols + TU - 1) / TU)),
+                       dim3(256), 0, s, w.A, N, p, nbp, w.tau, w.Wp, ncols, X, ldx, (int64_t)p);
+    return launch_check("blocked QR panel");
 }
 
 }  // namespace pod
@@ -348,16 +447,27 @@ int rom_build_basis(const double* S, int64_t N, int32_t m, int64_t ldS, double e
     LH_REQUIRE(work_bytes >= rom_build_basis_workspace_size(N, m), "rom_build_basis: workspace too small");
     PodWork w;
     pod_bytes(N, m, &w, static_cast<char*>(work));
+    int rc = LH_OK;
     const unsigned rows_blocks = (unsigned)((N + 255) / 256);
     hipLaunchKernelGGL(copy_cols_kernel, dim3(rows_blocks, m), dim3(256), 0, s, S, ldS, w.A, N, m);
-    for (int k = 0; k < m; ++k) {
-        hipLaunchKernelGGL(house_gen_kernel, dim3(1), dim3(RB), 0, s, w.A, N, k, w.v, w.tau, w.beta);
-        hipLaunchKernelGGL(house_w_kernel, dim3(m), dim3(256), 0, s, w.A, N, k, w.v, w.w);
-        const unsigned rb = (unsigned)((N - k + 255) / 256);
-        const unsigned cb = (unsigned)std::max(1, m - k - 1);
-        hipLaunchKernelGGL(house_update_kernel, dim3(rb, cb), dim3(256), 0, s, w.A, N, m, k, w.v, w.tau, w.w, w.Sm);
+    for (int p = 0; p < m; p += NB) {
+        const int pe = std::min(m, p + NB);
+        double* Sp = w.Sp + (int64_t)(p / NB) * NB * NB;
+        for (int k = p; k < pe; ++k) {
+            const int nch = (int)std::max<int64_t>(1, (N - k - 1 + DCH - 1) / DCH);
+            hipLaunchKernelGGL(panel_dots_kernel, dim3(nch), dim3(256), 0, s, w.A, N, k, p, pe - p, w.part);
+            hipLaunchKernelGGL(panel_scalars_kernel, dim3(1), dim3(64), 0, s, w.A, N, k, p, pe - p, nch, w.part, w.tau,
+                               w.beta, w.scal, w.w, Sp);
+            hipLaunchKernelGGL(panel_house_kernel, dim3((unsigned)((N - k + 255) / 256)), dim3(256), 0, s, w.A, N, k,
+                               pe, w.tau, w.beta, w.scal, w.w);
+        }
+        if (pe < m) {
+            const int nt = m - pe;
+            rc = apply_panel(w, N, p, pe - p, w.A + (int64_t)pe * N, N, nt, Sp, true, s);
+            if (rc) return rc;
+        }
     }
-    int rc = launch_check("householder QR");
+    rc = launch_check("householder QR");
     if (rc) return rc;
     hipLaunchKernelGGL(extract_r_kernel, dim3((m + 255) / 256, m), dim3(256), 0, s, w.A, N, m, w.beta, w.W);
     // one-sided Jacobi sweeps until a whole sweep rotates nothing
@@ -422,11 +532,12 @@ int rom_build_basis(const double* S, int64_t N, int32_t m, int64_t ldS, double e
     LH_HIP_CHECK(hipMemcpyAsync(w.perm, perm.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(select_kernel, dim3((m + 255) / 256, std::max(n, 1)), dim3(256), 0, s, w.W, m, w.perm,
                        w.sig_raw, n, w.Un, sigma);
-    hipLaunchKernelGGL(vtop_t_kernel, dim3(m, n), dim3(256), 0, s, w.A, N, m, w.tau, w.Un, n, w.X);
-    hipLaunchKernelGGL(back_subst_kernel, dim3(n), dim3(256), 0, s, w.Sm, m, w.X, w.Y);
-    const unsigned cgroups = (unsigned)((n + 31) / 32);
-    hipLaunchKernelGGL(form_phi_kernel, dim3(rows_blocks, cgroups), dim3(256), 0, s, w.A, N, m, w.tau, w.Un, w.Y, n,
-                       Phi, ldPhi);
+    // Phi = Q_0 Q_1 ... Q_last [U_n; 0]
+    hipLaunchKernelGGL(init_phi_kernel, dim3(rows_blocks, n), dim3(256), 0, s, w.Un, N, m, Phi, ldPhi);
+    for (int p = ((m - 1) / NB) * NB; p >= 0; p -= NB) {
+        rc = apply_panel(w, N, p, std::min(m, p + NB) - p, Phi, ldPhi, n, w.Sp + (int64_t)(p / NB) * NB * NB, false, s);
+        if (rc) return rc;
+    }
     hipLaunchKernelGGL(sign_kernel, dim3(n), dim3(256), 0, s, Phi, N, ldPhi);
     rc = launch_check("POD basis");
     if (rc) return rc;

@@ -112,3 +112,30 @@ def test_full_size_gresho_batch_instances(gpu_lib, monkeypatch):
         assert st.n_steps == len(run.dt) and st.n_rejected == run.rejections and st.w == run.w
         for a, b in zip(G.coords(i), run.yhat):
             assert rel(a, b) < 1e-9
+
+
+@pytest.mark.parametrize("N,m,n", [(352947, 640, 20), (823875, 200, 40)], ids=["tg3d_24_x", "sedov3d_32_x"])
+def test_full_size_pod_of_a_known_factorisation(gpu_lib, N, m, n):
+    """POD at the 3D kinematic sizes: S = U diag(s) V^T with orthonormal cosine columns U (closed
+    form), a seeded random orthogonal V and s = 0.8^k, so the singular values and the leading
+    left singular vectors are known exactly."""
+    from paper_2104_11404_amd import lib
+    print(f"[case] full-size pod N={N} m={m} n={n}", flush=True)
+    s = 0.8 ** np.arange(m)
+    V = np.linalg.qr(W.rng(21).normal(size=(m, m)))[0]
+    i = torch.arange(N, dtype=torch.float64, device="cuda")[:, None]
+    k = torch.arange(1, m + 1, dtype=torch.float64, device="cuda")[None, :]
+    U = np.sqrt(2.0 / N) * torch.cos(np.pi * (i + 0.5) * k / N)  # DCT-II columns 1..m: orthonormal
+    S = ((U * _t(s)[None, :]) @ _t(V).T).T.contiguous()  # (m, N) rows = N x m column-major
+    Phi, sig, got = lib.rom_build_basis(S, n_fixed=n)
+    del S
+    assert got == n
+    sig = sig.cpu().numpy()
+    assert np.max(np.abs(sig - s)) < 1e-12 * s[0]  # backward-stable bound, every singular value
+    P = Phi.T  # N x n
+    for c in range(n):
+        u = U[:, c]
+        d = min(float(torch.linalg.norm(P[:, c] - u)), float(torch.linalg.norm(P[:, c] + u)))
+        assert d < 1e-9, c
+    G = (P.T @ P).cpu().numpy()
+    assert np.max(np.abs(G - np.eye(n))) < 1e-13

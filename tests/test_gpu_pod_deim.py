@@ -43,7 +43,8 @@ def tg_snapshots():
     return op, snapshot_matrices([tr], [initial_state(op.prob)], [wl.t_final])[0]
 
 
-@pytest.mark.parametrize("N,m,seed", [(700, 60, 0), (1031, 33, 1), (257, 257, 2), (300, 1, 3)])
+@pytest.mark.parametrize("N,m,seed", [(700, 60, 0), (1031, 33, 1), (257, 257, 2), (300, 1, 3), (9000, 150, 4),
+                                      (4099, 97, 5)])
 def test_pod_matches_oracle_random(gpu_lib, N, m, seed):
     from paper_2104_11404_amd import lib
     print(f"[case] pod random N={N} m={m}", flush=True)
