@@ -128,8 +128,12 @@ EXEC_FLOPS_PER_ELEM = {2: 1.19e4, 3: 3.81e5}
 FP64_PEAK_TFLOPS = 78.6
 
 
-def fom_force_rate(lib, wl, reps: int = 20, seed: int = 7):
+def fom_force_rate(lib, wl, reps: int = 20, seed: int = 7, n_states: int = 1):
     """Full-mesh fom_force (F.1, F^T.v and tau, artificial viscosity on) on a perturbed state.
+
+    With n_states > 1 the calls cycle over that many distinct states (small seeded perturbations
+    of the first), so the working set can exceed the 256 MB last-level cache as a batch of
+    instances' full-mesh evaluations would.
 
     Algorithmic bytes per call: read x, v, v_c (3 N_V) and e (N_E), write F.1 (N_V) and
     F^T.v (N_E), FP64.  Algorithmic flops: ALG_FLOPS_PER_ELEM per element; the kernel is bound by
@@ -141,22 +145,30 @@ def fom_force_rate(lib, wl, reps: int = 20, seed: int = 7):
 
     P = lib.Problem.from_workload(wl)
     x, v, e, vc = (torch.from_numpy(a).cuda() for a in Wl.random_state(wl, seed))
+    states = [(x, v, e, vc)]
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    h = min((hi - lo) / n for lo, hi, n in zip(wl.lo, wl.hi, wl.nel))
+    for _ in range(n_states - 1):
+        r = lambda a: torch.randn(a.shape, dtype=a.dtype, device="cuda", generator=g)
+        states.append((x + 1e-3 * h * r(x), v + 0.01 * r(v), e * torch.exp(0.01 * r(e)), vc + 0.01 * r(vc)))
     F1, Ftv, tau = P.fom_force(x, v, e, vc)
-    for _ in range(3):
-        P.fom_force(x, v, e, vc, F1=F1, Ftv=Ftv, tau=tau)
+    for st in states[:3]:
+        P.fom_force(*st, F1=F1, Ftv=Ftv, tau=tau)
+    reps = max(reps, n_states)
     stream = torch.cuda.current_stream()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     a.record(stream)
-    for _ in range(reps):
-        P.fom_force(x, v, e, vc, F1=F1, Ftv=Ftv, tau=tau)
+    for k in range(reps):
+        P.fom_force(*states[k % n_states], F1=F1, Ftv=Ftv, tau=tau)
     b.record(stream)
     torch.cuda.synchronize()
     P.status()
     s = a.elapsed_time(b) / 1e3 / reps
     nbytes = 8 * (4 * P.NV + 2 * P.NE)
     flops = ALG_FLOPS_PER_ELEM[wl.dim] * wl.n_elem
-    return {"mesh": list(wl.nel[: wl.dim]), "elements": wl.n_elem, "avg_us_per_call": s * 1e6,
+    return {"mesh": list(wl.nel[: wl.dim]), "elements": wl.n_elem, "states": n_states,
+            "working_set_bytes": n_states * 8 * (3 * P.NV + P.NE), "avg_us_per_call": s * 1e6,
             "elements_per_s": wl.n_elem / s, "algorithmic_bytes": nbytes, "achieved_GBs": nbytes / s / 1e9,
             "hbm_frac": nbytes / s / 1e9 / HBM_PEAK_GBS, "bound": "alu (FP64)",
             "algorithmic_flops": flops, "achieved_TFLOPs": flops / s / 1e12,
@@ -324,6 +336,94 @@ def surrogate_param(lib, pipeline, wl, n_train: int = 17, train_steps: int = 400
     return out
 
 
+def sedov3d_batch(lib, pipeline, n_inst: int = 64, n_err: int = 8, reps: int = 2, lam=None, n_windows=None,
+                  verbose=True):
+    """64 parametrised 3D Sedov ROM instances (32^3, E ~ U[0.2, 0.3], t = 0.8) on shared bases.
+
+    Bases, SNS and DEIM from GPU FOM runs at E = 0.2, 0.25, 0.3 with 20 windows by snapshot count;
+    every instance starts from its own initial state projected on the nominal offset.  Timed: one
+    launch advancing every instance to t = 0.8 (launch shape by rom_autotune).  Errors: the lifted
+    final states of the first n_err instances against their own GPU FOM runs.
+    """
+    import torch
+
+    import workloads as Wl
+
+    wl = Wl.sedov3d_param(n_inst=n_inst) if lam is None else Wl.sedov3d_param(n_inst=n_inst, lam=lam)
+    if n_windows:
+        wl = Wl.replace(wl, n_windows=n_windows)
+    t0 = time.perf_counter()
+    trajs = [pipeline.fom_trajectory(lib.Problem.from_workload(wl, energy=E), wl.t_final)
+             for E in Wl.SEDOV_TRAIN_ENERGIES]
+    t_fom = time.perf_counter() - t0
+    nominal = trajs[1]["y0"]
+    n_t = max(tr["n_steps"] for tr in trajs)
+    T = pipeline.windows_by_samples([tr["t"] for tr in trajs], 2 * math.ceil(n_t / wl.n_windows))
+    P = lib.Problem.from_workload(wl, energy=0.25)
+    t1 = time.perf_counter()
+    inst = pipeline.build_offline(P, trajs, T, nominal, energy_frac=wl.energy_frac, n_max=64, lam=wl.lam,
+                                  t_final=wl.t_final, snapshot_offsets=nominal)
+    torch.cuda.synchronize()
+    t_off = time.perf_counter() - t1
+    fom_steps = [tr["n_steps"] for tr in trajs]
+    del trajs
+    torch.cuda.empty_cache()
+    dims = [[int(p.shape[0]) for p in wd["phi"]] for wd in inst["windows"]]
+    if verbose:
+        print(f"[bench] sedov3d: FOMs {fom_steps} steps in {t_fom:.1f} s, offline {t_off:.1f} s, {len(T)} windows, "
+              f"dims {dims}", file=sys.stderr, flush=True)
+    y0s = []
+    for prm in wl.params:
+        x, v, e = lib.Problem.from_workload(wl, energy=prm["energy"]).initial_state()
+        y0s.append((x, v, e))
+    y0 = [torch.cat([y[f] for y in y0s]) for f in range(3)]
+    rom = lib.Rom(P, [inst] * n_inst)
+    n_el = [rom.sampled_elements(0, w) for w in range(len(T))]
+    out = {"workload": f"sedov3d_32x32x32_param_E0.2-0.3_batch{n_inst}_t0.8_{len(T)}windows_shared_bases"
+                       f"_lambda{wl.lam[0]:g}",
+           "instances": n_inst, "training_fom_steps": fom_steps, "fom_s": t_fom, "offline_s": t_off,
+           "dims_per_window": dims, "sampled_elements_per_window": n_el,
+           "device_bytes": rom.device_bytes(), "heuristic_workgroups_per_instance": rom.workgroups()}
+    stream = torch.cuda.current_stream()
+    rom.init_state(*y0)
+    out["autotune"] = autotune(rom, 0, trial_steps=50)
+    ms = []
+    for r in range(reps + 1):
+        rom.init_state(*y0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        rom.step()
+        b.record(stream)
+        torch.cuda.synchronize()
+        if r:
+            ms.append(a.elapsed_time(b))
+    sts = rom.states()
+    steps = sum(st.n_steps for st in sts)
+    t = min(ms) / 1e3
+    errs = []
+    for i in range(min(n_err, n_inst)):
+        Pi = lib.Problem.from_workload(wl, energy=wl.params[i]["energy"])
+        x, v, e = (a.clone() for a in y0s[i])
+        Pi.fom_run(x, v, e, wl.t_final, record=False)
+        errs.append([float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(rom.lift(i), (x, v, e))])
+    errs = np.array(errs)
+    failed = [i for i, st in enumerate(sts) if st.status != 0 or st.done != 1]
+    # a run in which instances stop early is no throughput measurement of the workload
+    out["valid"] = not failed
+    out.update({"ms_per_launch": t * 1e3, "rom_steps_per_launch": int(steps), "rom_steps_per_s": steps / t,
+                "sampled_force_evals_per_s": sum(st.n_force_evals for st in sts) / t,
+                "rejected_steps": int(sum(st.n_rejected for st in sts)),
+                "failed_instances": failed,
+                "failure_times": sorted({round(st.t, 4) for st in sts if st.status != 0 or st.done != 1}),
+                "errors_on_instances": int(len(errs)),
+                "max_rel_error_vs_fom": dict(zip("xve", errs.max(axis=0).tolist())),
+                "median_rel_error_vs_fom": dict(zip("xve", np.median(errs, axis=0).tolist()))})
+    if verbose:
+        print(f"[bench] sedov3d batch: {t * 1e3:.1f} ms, {steps / t:.0f} ROM steps/s, max err {errs.max(axis=0)}",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -334,6 +434,8 @@ def main():
     ap.add_argument("--no-force", action="store_true", help="skip the full-mesh fom_force measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-instance batched Gresho measurement")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate against DEIM measurement")
+    ap.add_argument("--sedov3d", action="store_true",
+                    help="also run the 64-instance 3D Sedov batch on shared bases (several minutes of set-up)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workgroups", type=int, default=0,
                     help="workgroups per instance of the headline ROM launch (0: pick with rom_autotune)")
@@ -468,6 +570,7 @@ def main():
         out["copy_calibration"] = calib
     if not args.no_force:
         out["fom_force"] = [fom_force_rate(lib, w) for w in (wl, Wl.sedov2d(512), Wl.sedov3d(32))]
+        out["fom_force"].append(fom_force_rate(lib, Wl.sedov3d(32), reps=128, n_states=64))
         print(f"[bench] fom_force {[(r['mesh'], round(r['avg_us_per_call'], 1)) for r in out['fom_force']]}",
               file=sys.stderr, flush=True)
     if not args.no_batch:
@@ -476,6 +579,8 @@ def main():
         out["surrogate"] = surrogate_param(lib, pipeline, Wl.tg2d_param(), train_steps=10000, variants=[(25, 1e30)])
         out["surrogate_3d"] = surrogate_param(lib, pipeline, Wl.tg3d_param(), n_train=9, train_steps=10000,
                                               variants=[(25, 1e30)])
+    if args.sedov3d:
+        out["sedov3d_batch"] = sedov3d_batch(lib, pipeline)
     if not args.no_cpu_baseline:
         med = [int(sorted(d[f] for d in dims)[len(dims) // 2]) for f in range(3)]
         out["cpu_baseline"] = cpu_baseline(wl, med, st.n_force_evals / st.n_steps, args.cpu_seconds)

@@ -257,7 +257,8 @@ enum { LH_FP32_LIFT = 1, LH_REPLAY_DT = 2, LH_FIXED_DT = 4, LH_SURROGATE = 8 };
 /* Build the online data of n_inst instances sharing one problem: element
  * closure of the sampled rows, element-local tiles of the sampled basis
  * rows and offsets, B_xv = Phi_x^T Phi_v, b_x = Phi_x^T v_os and the window
- * transition maps of eq. ic-tw.  Also fixes G, the workgroups that advance
+ * transition maps of eq. ic-tw (built once for instances whose window
+ * descriptions are equal field by field).  Also fixes G, the workgroups that advance
  * each instance (1 <= G <= 64, at most 10 sampled elements per workgroup, no
  * more than fit in LDS and no more than the compute units allow for n_inst
  * co-resident instances; the environment variable LAGROM_ELEMS_PER_WG, read
@@ -310,6 +311,13 @@ int rom_sampled_elements(const lh_rom* r, int32_t inst, int32_t window, int32_t*
  * instance meet at a barrier after every pass; a barrier that does not
  * complete within a few seconds sets LH_FLAG_TIMEOUT and ends the launch. */
 int rom_workgroups_per_instance(const lh_rom* r, int32_t* G);
+
+/* Device memory held by r (host query, bytes): window tables, workgroup
+ * tables and per-instance exchange buffers.  Instances whose window
+ * descriptions are equal field by field (same pointers, sizes and times)
+ * share one copy of the window tables, so a batch of instances on shared
+ * bases costs little more than one instance. */
+int rom_device_bytes(const lh_rom* r, int64_t* bytes);
 
 /* Launch shape of rom_step: split every instance's sampled elements over G
  * workgroups (1 <= G <= 64) instead of the count rom_create chose.  The

@@ -1095,6 +1095,8 @@ struct lh_rom {
     int mlp_floats = 0;  // LDS scratch of the largest attached surrogate
     std::vector<void*> allocs;
     std::vector<void*> view_allocs;  // workgroup views: rebuilt when G changes
+    std::vector<int> alias;          // alias[i] = j < i: instance i shares instance j's window tables
+    int64_t bytes = 0, view_bytes = 0;  // device memory held (tables and state, workgroup views)
     lh::rom::InstDev* d_inst;
     std::vector<lh::rom::InstDev> h_inst;
     std::vector<std::vector<lh::rom::WinDev>> h_win;
@@ -1113,6 +1115,7 @@ static int dev_alloc(lh_rom* R, T** out, size_t count, std::vector<void*>* list 
         return LH_EDEVICE;
     }
     (list ? list : &R->allocs)->push_back(p);
+    (list ? R->view_bytes : R->bytes) += (int64_t)(sizeof(T) * count);
     *out = static_cast<T*>(p);
     return LH_OK;
 }
@@ -1305,6 +1308,10 @@ static int64_t resident_bytes(int dim, const HostWin& H, int ns, int nkin, int n
 static int build_views(lh_rom* R, int i, int G) {
     const int dim = R->p->dim;
     auto& wins = R->h_win[i];
+    if (R->alias[i] >= 0) {  // the views of the instance whose tables it shares
+        for (size_t w = 0; w < wins.size(); ++w) wins[w].views = R->h_win[R->alias[i]][w].views;
+        return LH_OK;
+    }
     auto& hs = R->h_struct[i];
     for (size_t w = 0; w < wins.size(); ++w) {
         const HostWin& H = hs[w];
@@ -1373,6 +1380,21 @@ static int cu_count() {
     return v;
 }
 
+// Two instances with field-by-field equal window descriptions read the same device data at
+// rom_create, so their window tables are equal and are built once.
+static bool same_windows(const lh_instance_desc& a, const lh_instance_desc& b) {
+    if (a.n_windows != b.n_windows) return false;
+    for (int w = 0; w < a.n_windows; ++w) {
+        const lh_window_desc &x = a.windows[w], &y = b.windows[w];
+        if (x.t_end != y.t_end || x.z1 != y.z1 || x.n_s1 != y.n_s1 || x.z2 != y.z2 || x.n_s2 != y.n_s2 || x.a1 != y.a1 ||
+            x.a2 != y.a2)
+            return false;
+        for (int f = 0; f < 3; ++f)
+            if (x.n[f] != y.n[f] || x.phi[f] != y.phi[f] || x.os[f] != y.os[f]) return false;
+    }
+    return true;
+}
+
 constexpr int STATIC_LDS_RESERVE = 24 * 1024;  // node buffers, reduced vectors, state (bytes, upper bound)
 constexpr int MAX_G = 64;                      // workgroups per instance (bounds the share staging in LDS)
 constexpr int ELEMS_PER_WG = 10;               // default cap on sampled elements per workgroup
@@ -1401,11 +1423,18 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
         return rc;
     };
     int max_el = 0;
+    R->alias.assign(n_inst, -1);
     for (int i = 0; i < n_inst; ++i) {
         const lh_instance_desc& d = inst[i];
         if (d.n_windows < 1 || !d.windows || !(d.t_final > 0.0)) {
             set_error("rom_create: instance needs >= 1 window and t_final > 0");
             return fail(LH_EINVAL);
+        }
+        for (int j = 0; j < i && R->alias[i] < 0; ++j)
+            if (R->alias[j] < 0 && same_windows(d, inst[j])) R->alias[i] = j;
+        if (R->alias[i] >= 0) {  // same descriptions: share the device tables, keep a private copy of the headers
+            R->h_win[i] = R->h_win[R->alias[i]];
+            continue;
         }
         R->h_win[i].resize(d.n_windows);
         R->h_struct[i].resize(d.n_windows);
@@ -1575,6 +1604,7 @@ static int fits_coresident(const lh_rom* R, uint32_t flags, bool* ok) {
 static int repartition(lh_rom* R, int G, hipStream_t s) {
     for (void* q : R->view_allocs) (void)hipFree(q);
     R->view_allocs.clear();
+    R->view_bytes = 0;
     R->nkin_max = R->nth_max = R->res_max64 = R->res_max32 = 0;
     for (int i = 0; i < R->n_inst; ++i) {
         const int rc = build_views(R, i, G);
@@ -1754,6 +1784,13 @@ int rom_workgroups_per_instance(const lh_rom* R, int32_t* G) {
     using namespace lh;
     LH_REQUIRE(R && G, "rom_workgroups_per_instance: null argument");
     *G = R->G;
+    return LH_OK;
+}
+
+int rom_device_bytes(const lh_rom* R, int64_t* bytes) {
+    using namespace lh;
+    LH_REQUIRE(R && bytes, "rom_device_bytes: null argument");
+    *bytes = R->bytes + R->view_bytes;
     return LH_OK;
 }
 

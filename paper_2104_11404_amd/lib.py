@@ -98,6 +98,7 @@ _SIGNATURES = {
     "rom_sampled_elements": (_I32, [_VP, _I32, _I32, C.POINTER(_I32)]),
     "rom_workgroups_per_instance": (_I32, [_VP, C.POINTER(_I32)]),
     "rom_set_workgroups": (_I32, [_VP, _I32, _U32, _VP]),
+    "rom_device_bytes": (_I32, [_VP, C.POINTER(_I64)]),
     "rom_autotune": (_I32, [_VP, _VP, _I32, _U32, _VP, _I32, C.POINTER(_I32), C.POINTER(C.c_float), _VP]),
     "mlp_create": (_I32, [C.POINTER(MlpDesc), _I32, C.POINTER(_VP)]),
     "mlp_destroy": (None, [_VP]),
@@ -391,6 +392,11 @@ class Rom:
         g = _I32()
         _check(load().rom_workgroups_per_instance(self.h, C.byref(g)))
         return g.value
+
+    def device_bytes(self):
+        b = _I64()
+        _check(load().rom_device_bytes(self.h, C.byref(b)))
+        return b.value
 
     def set_workgroups(self, G, flags=0):
         _check(load().rom_set_workgroups(self.h, int(G), int(flags), stream_handle()))

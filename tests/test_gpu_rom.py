@@ -215,3 +215,32 @@ def test_rom_multi_workgroup_instance_matches_oracle(gpu_lib, sedov_windows, tg,
     G4.step(flags=lib.LH_FIXED_DT | lib.LH_FP32_LIFT)
     for a, b in zip(G4.lift(0), R.final_lift(rom, run)):
         assert rel(a.cpu().numpy(), b) < 1e-5
+
+
+def test_instances_on_shared_bases_share_their_tables(gpu_lib, tg):
+    """Instances built from the same window tensors share one copy of the window tables: each
+    extra instance costs only its state buffers, and every instance runs bitwise like a lone one."""
+    from paper_2104_11404_amd import lib
+    wl, op, tr, y0 = tg
+    print("[case] rom shared-basis instances", flush=True)
+    rom = R.build_rom(op, [tr], [y0], [wl.t_final], n_fixed=wl.n_fixed, lam=wl.lam)
+    P = lib.Problem.from_workload(wl)
+    inst = gpu_instance(rom, wl.t_final)
+    roms = {k: lib.Rom(P, [inst] * k) for k in (1, 2, 16)}
+    distinct = lib.Rom(P, [gpu_instance(rom, wl.t_final) for _ in range(16)])
+    for r in (*roms.values(), distinct):
+        r.set_workgroups(1)
+    b = {k: r.device_bytes() for k, r in roms.items()}
+    per_instance = b[2] - b[1]
+    assert 0 < per_instance < b[1]
+    assert b[16] == b[1] + 15 * per_instance
+    assert distinct.device_bytes() == 16 * b[1]
+    x0, v0, e0 = (torch.cat([_t(y0[f])] * 16) for f in range(3))
+    one = roms[1]
+    one.init_state(_t(y0[0]), _t(y0[1]), _t(y0[2]), wl.fixed_dt)
+    one.step(flags=lib.LH_FIXED_DT)
+    many = roms[16]
+    many.init_state(x0, v0, e0, wl.fixed_dt)
+    many.step(flags=lib.LH_FIXED_DT)
+    for i in range(16):
+        assert torch.equal(many.state[i], one.state[0]), i

@@ -42,8 +42,10 @@ def test_rom3d_fixed_dt_matches_oracle(gpu_lib, tg3):
         assert rel(a.cpu().numpy(), b) < 1e-5
 
 
-@pytest.mark.parametrize("per_wg", [None, "2"])
+@pytest.mark.parametrize("per_wg", [None, "2", "1000000"], ids=["default", "2-per-wg", "one-wg-global-tiles"])
 def test_rom3d_sedov_windows_adaptive(gpu_lib, monkeypatch, per_wg):
+    """Three launch shapes; with one workgroup per instance the hexahedral tiles exceed LDS and are
+    read from global memory."""
     from paper_2104_11404_amd import lib
     if per_wg:
         monkeypatch.setenv("LAGROM_ELEMS_PER_WG", per_wg)
@@ -129,3 +131,30 @@ def test_surrogate_rom3d_fallback_is_the_plain_rom(gpu_lib, tg3):
     assert G2.states()[0].n_steps == st.n_steps
     for a, b in zip(G.coords(0), G2.coords(0)):
         np.testing.assert_array_equal(a, b)
+
+
+def test_rom3d_sedov_full_run_ten_windows(gpu_lib):
+    """3D Sedov 4^3 from t = 0 to 0.8 through 10 windows (energy criterion, lambda 6, adaptive steps
+    with rejections): the same accepted and rejected steps and final window as the oracle, reduced
+    state to 1e-9, with the default launch shape and with one workgroup per instance."""
+    from paper_2104_11404_amd import lib
+    wl = W.sedov3d(4)
+    op = F.build_operator(oracle_problem(wl))
+    tr = F.run_fom(op, wl.t_final)
+    y0 = initial_state(op.prob)
+    T = windows_by_samples([tr.t], 2 * int(np.ceil(len(tr.dt) / 10)))
+    rom = R.build_rom(op, [tr], [y0], T, energy_frac=0.9999, n_max=64, lam=(6, 6))
+    run = R.run_rom(op, rom, y0, wl.t_final)
+    assert len(rom.windows) == 10 and run.rejections > 0
+    for G in (0, 1):
+        P, Gr = _gpu_rom(wl, [(rom, wl.t_final)], [y0])
+        if G:
+            Gr.set_workgroups(G)
+            Gr.init_state(_t(y0[0]), _t(y0[1]), _t(y0[2]))
+        print(f"[case] rom 3d sedov 4^3 full run, 10 windows, G={Gr.workgroups()}, {len(run.dt)} steps", flush=True)
+        Gr.step()
+        st = Gr.states()[0]
+        assert st.status == 0 and st.done == 1
+        assert st.n_steps == len(run.dt) and st.n_rejected == run.rejections and st.w == run.w
+        for a, b in zip(Gr.coords(0), run.yhat):
+            assert rel(a, b) < 1e-9

@@ -127,6 +127,21 @@ def tg3d_param(n: int = 24, t_final: float = 0.05, n_inst: int = 64, seed: int =
                     params=tuple(dict(amp=float(a)) for a in amps))
 
 
+def sedov3d_param(n: int = 32, n_inst: int = 64, seed: int = SEED, lam: tuple = (6.0, 6.0)) -> Workload:
+    """Parametric 3D Sedov blast on [0,1]^3: deposited energy E ~ U[0.2, 0.3] per instance, training
+    at E = 0.2, 0.25, 0.3; adaptive dt (alpha = 0.5) to t = 0.8.
+
+    20 windows by snapshot count over the training set, POD dims by the 0.9999 criterion (at most
+    64), bases shared by every instance with the nominal (E = 0.25) initial state as offset, so the
+    reduced initial state carries the energy.
+    """
+    energies = rng(seed).uniform(0.2, 0.3, n_inst)
+    return Workload("sedov3d_param", SEDOV, 3, (n, n, n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), 1.4, True, 0.5, 0.8,
+                    n_windows=20, energy=0.25, lam=tuple(lam), params=tuple(dict(energy=float(E)) for E in energies))
+
+
+SEDOV_TRAIN_ENERGIES = (0.2, 0.25, 0.3)  # training energies of the parametric Sedov problem
+
 TG_TRAIN_AMPS = (0.8, 1.0, 1.2)  # training amplitudes of the parametric Taylor-Green problems
 
 
