@@ -244,3 +244,35 @@ def test_instances_on_shared_bases_share_their_tables(gpu_lib, tg):
     many.step(flags=lib.LH_FIXED_DT)
     for i in range(16):
         assert torch.equal(many.state[i], one.state[0]), i
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (64, 64, 64), (64, 3, 17)], ids=["min", "max", "mixed"])
+def test_rom_extreme_dimensions_match_oracle(gpu_lib, tg, dims):
+    """Basis sizes at both ends of the supported range (1 and LH_NMAX = 64 per field)."""
+    from paper_2104_11404_amd import lib
+    wl, op, tr, y0 = tg
+    print(f"[case] rom tg2d dims {dims}", flush=True)
+    rom = R.build_rom(op, [tr], [y0], [wl.t_final], n_fixed=dims, lam=(2, 2))
+    run = R.run_rom(op, rom, y0, wl.t_final, fixed_dt=wl.fixed_dt)
+    P, G = _gpu_rom(wl, [(rom, wl.t_final)], [y0], dt0=wl.fixed_dt)
+    G.step(flags=lib.LH_FIXED_DT)
+    st = G.states()[0]
+    assert st.status == 0 and st.done == 1 and st.n_steps == len(run.dt)
+    for a, b in zip(G.coords(0), run.yhat):
+        assert rel(a, b) < 1e-10
+
+
+def test_rom_zero_steps_and_oversized_bases(gpu_lib, tg):
+    from paper_2104_11404_amd import lib
+    wl, op, tr, y0 = tg
+    print("[case] rom zero steps, oversized basis rejected", flush=True)
+    rom = R.build_rom(op, [tr], [y0], [wl.t_final], n_fixed=wl.n_fixed, lam=wl.lam)
+    P, G = _gpu_rom(wl, [(rom, wl.t_final)], [y0], dt0=wl.fixed_dt)
+    before = G.state.clone()
+    G.step(max_steps=0, flags=lib.LH_FIXED_DT)
+    assert torch.equal(G.state, before)
+    inst = gpu_instance(rom, wl.t_final)
+    big = torch.zeros((65, P.NV), dtype=torch.float64, device="cuda")
+    inst["windows"][0]["phi"][0] = big
+    with pytest.raises(lib.LagromError, match="64"):
+        lib.Rom(P, [inst])
