@@ -53,17 +53,18 @@ def rom_step_bytes(inst, st_counts, dim=2):
     return out
 
 
-def measured_traffic():
+def measured_traffic(workgroups: int):
     """HBM bytes per rom_step_kernel launch from the committed counter runs, or None when the
-    kernel's sources have changed since those counters were taken."""
+    kernel's sources have changed since those counters were taken or the launch shape differs
+    from the profiled one (the exchange traffic grows with the workgroups per instance)."""
     import hashlib
     import re
 
     prof = os.path.join(ROOT, "profiles", "rom_step_kernel_sedov2d_64x64_traffic.md")
     if not os.path.exists(prof):
         return None
-    m = re.search(r"traffic_bytes_per_launch=(\d+) source_sha1=([0-9a-f]+)", open(prof).read())
-    if not m:
+    m = re.search(r"traffic_bytes_per_launch=(\d+) source_sha1=([0-9a-f]+) workgroups=(\d+)", open(prof).read())
+    if not m or int(m.group(3)) != workgroups:
         return None
     h = hashlib.sha1()
     for f in ("rom.hip", "internal.hpp"):
@@ -560,7 +561,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic(rom.workgroups()),
             "bytes_per_launch": bytes_per_launch,
             "avg_kernel_ms": avg_kernel_s * 1e3,
         },

@@ -18,7 +18,7 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_traffic_is_reported_only_for_the_profiled_sources(tmp_path, monkeypatch):
+def test_traffic_is_reported_only_for_the_profiled_sources_and_shape(tmp_path, monkeypatch):
     import shutil
     root = tmp_path / "repo"
     (root / "profiles").mkdir(parents=True)
@@ -30,12 +30,13 @@ def test_traffic_is_reported_only_for_the_profiled_sources(tmp_path, monkeypatch
     for f in ("rom.hip", "internal.hpp"):
         h.update((root / "paper_2104_11404_amd" / "csrc" / f).read_bytes())
     prof = root / "profiles" / "rom_step_kernel_sedov2d_64x64_traffic.md"
-    prof.write_text(f"machine-readable: traffic_bytes_per_launch=123456 source_sha1={h.hexdigest()}\n")
+    prof.write_text(f"machine-readable: traffic_bytes_per_launch=123456 source_sha1={h.hexdigest()} workgroups=20\n")
     monkeypatch.setattr(bench, "ROOT", str(root))
-    assert bench.measured_traffic() == 123456.0
+    assert bench.measured_traffic(20) == 123456.0
+    assert bench.measured_traffic(24) is None  # another launch shape: other exchange traffic
     with open(root / "paper_2104_11404_amd" / "csrc" / "rom.hip", "a") as fh:
         fh.write("// changed\n")
-    assert bench.measured_traffic() is None
+    assert bench.measured_traffic(20) is None
 
 
 def test_rom_step_bytes_counts_tiles_offsets_and_operators():
