@@ -127,6 +127,14 @@ ALG_FLOPS_PER_ELEM = {2: 5.0e3, 3: 1.26e5}
 # FP64 flops per element the kernel executes, from SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 x 64 lanes
 EXEC_FLOPS_PER_ELEM = {2: 1.19e4, 3: 3.81e5}
 FP64_PEAK_TFLOPS = 78.6
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
+
+
+def mlp_step_flops(batch: int, sizes) -> float:
+    """Algorithmic flops of one full-batch training step: the forward product (2 per weight and
+    sample) and the two backward products (input gradients and weight gradients)."""
+    w = sum(a * b for a, b in zip(sizes[:-1], sizes[1:]))
+    return 6.0 * batch * w
 
 
 def fom_force_rate(lib, wl, reps: int = 20, seed: int = 7, n_states: int = 1):
@@ -344,7 +352,10 @@ def surrogate_param(lib, pipeline, wl, n_train: int = 17, train_steps: int = 400
            "instances": n_inst, "heuristic_workgroups_per_instance": rom.workgroups(), "offline_s": t_offline,
            "training": {"samples": int(X.shape[0]), "steps": train_steps, "seconds": t_train,
                         "loss_first": hist[0], "loss_last": hist[-1],
-                        "network": [int(X.shape[1]), 256, 256, 256, int(T.shape[1])]},
+                        "network": [int(X.shape[1]), 256, 256, 256, int(T.shape[1])],
+                        "achieved_TFLOPs": mlp_step_flops(int(X.shape[0]), [int(X.shape[1]), 256, 256, 256,
+                                                                               int(T.shape[1])]) * train_steps
+                        / t_train / 1e12},
            "sampled_elements": rom.sampled_elements(0, 0)}
     runs = [("deim", lib.LH_FIXED_DT, audit_every, tol), ("surrogate", lib.LH_FIXED_DT | lib.LH_SURROGATE, audit_every, tol)]
     for k_, tol_ in variants or ():
@@ -378,6 +389,7 @@ def surrogate_param(lib, pipeline, wl, n_train: int = 17, train_steps: int = 400
                      "fallback_windows": sum(st.n_fallbacks for st in sts)}
         print(f"[bench] {wl.dim}D {name}: {t * 1e3:.2f} ms, {steps / t:.0f} ROM steps/s, max err "
               f"{errs.max(axis=0)}", file=sys.stderr, flush=True)
+    out["training"]["bf16_mfma_frac"] = out["training"]["achieved_TFLOPs"] / BF16_MFMA_PEAK_TFLOPS
     out["speedup_surrogate_vs_deim"] = out["surrogate"]["rom_steps_per_s"] / out["deim"]["rom_steps_per_s"]
     return out
 
@@ -479,7 +491,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-force", action="store_true", help="skip the full-mesh fom_force measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-instance batched Gresho measurement")
-    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate against DEIM measurement")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate against DEIM measurements")
+    ap.add_argument("--train-steps", type=int, default=10000,
+                    help="full-batch training steps of each surrogate network (fewer for profiling runs)")
+    ap.add_argument("--no-surrogate-3d", action="store_true", help="skip the 3D surrogate against DEIM measurement")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the headline's cold-cache, FP32-lift and FOM speed-up runs (profiling runs)")
     ap.add_argument("--sedov3d", action="store_true",
@@ -627,9 +642,11 @@ def main():
     if not args.no_batch:
         out["batched"] = batched_gresho(lib, pipeline)
     if not args.no_surrogate:
-        out["surrogate"] = surrogate_param(lib, pipeline, Wl.tg2d_param(), train_steps=10000, variants=[(25, 1e30)])
-        out["surrogate_3d"] = surrogate_param(lib, pipeline, Wl.tg3d_param(), n_train=9, train_steps=10000,
-                                              variants=[(25, 1e30)])
+        out["surrogate"] = surrogate_param(lib, pipeline, Wl.tg2d_param(), train_steps=args.train_steps,
+                                           variants=[(25, 1e30)])
+        if not args.no_surrogate_3d:
+            out["surrogate_3d"] = surrogate_param(lib, pipeline, Wl.tg3d_param(), n_train=9, train_steps=args.train_steps,
+                                                  variants=[(25, 1e30)])
     if args.sedov3d:
         out["sedov3d_batch"] = sedov3d_batch(lib, pipeline)
     if not args.no_cpu_baseline:

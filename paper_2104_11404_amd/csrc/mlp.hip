@@ -55,7 +55,8 @@ typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int BLK = 256;
-constexpr int TM = 64, TN = 64, TK = 16;
+constexpr int TM = 64, TN = 64, TK = 64;
+constexpr int KP = TK + 8;  // LDS row length (bf16) of the operand tiles: 144 bytes, 16-byte aligned rows
 
 enum { ACT_NONE = 0, ACT_TANH = 1, ACT_DTANH = 2 };
 
@@ -77,31 +78,84 @@ struct GemmArgs {
     float* part;    // ... and writes its raw tile to part[z][M][N] (no epilogue)
 };
 
+// One operand tile T[r][k] = P(row0 + r, k0 + k) (r < 64, k < TK) into LDS, zero outside the matrix
+// (rows >= nrow or k >= kend).  P(row, k) = P[row * srow + k * sk].  When k or the row index is the
+// contiguous dimension and rows start on 16-byte boundaries, 8 bf16 move per load; otherwise one.
+__device__ __forceinline__ void load_tile(uint16_t (*T)[KP], const uint16_t* __restrict__ P, int64_t srow, int64_t sk,
+                                          int row0, int nrow, int k0, int kend) {
+    const int tid = threadIdx.x;
+    const bool aligned = (reinterpret_cast<uintptr_t>(P) & 15) == 0;
+    if (sk == 1 && aligned && (srow & 7) == 0) {
+        for (int v = tid; v < 64 * (TK / 8); v += BLK) {
+            const int r = v / (TK / 8), kq = (v % (TK / 8)) * 8;
+            const int row = row0 + r, k = k0 + kq;
+            uint4 val = make_uint4(0u, 0u, 0u, 0u);
+            if (row < nrow) {
+                const uint16_t* src = P + (int64_t)row * srow + k;
+                if (k + 8 <= kend) {
+                    val = *reinterpret_cast<const uint4*>(src);
+                } else {
+                    uint32_t w[4] = {0u, 0u, 0u, 0u};
+                    for (int e = 0; e < 8; ++e)
+                        if (k + e < kend) w[e >> 1] |= (uint32_t)src[e] << (16 * (e & 1));
+                    val = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+            }
+            *reinterpret_cast<uint4*>(&T[r][kq]) = val;
+        }
+    } else if (srow == 1 && aligned && (sk & 7) == 0) {
+        for (int v = tid; v < TK * 8; v += BLK) {
+            const int kk = v / 8, rq = (v % 8) * 8;
+            const int k = k0 + kk, row = row0 + rq;
+            uint16_t e8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (k < kend) {
+                const uint16_t* src = P + (int64_t)k * sk + row;
+                if (row + 8 <= nrow) {
+                    const uint4 val = *reinterpret_cast<const uint4*>(src);
+                    const uint32_t w[4] = {val.x, val.y, val.z, val.w};
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) e8[e] = (uint16_t)(w[e >> 1] >> (16 * (e & 1)));
+                } else {
+                    for (int e = 0; e < 8; ++e)
+                        if (row + e < nrow) e8[e] = src[e];
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) T[rq + e][kk] = e8[e];
+        }
+    } else {
+        for (int v = tid; v < 64 * TK; v += BLK) {
+            const int r = v / TK, kk = v % TK;
+            const int row = row0 + r, k = k0 + kk;
+            T[r][kk] = (row < nrow && k < kend) ? P[(int64_t)row * srow + (int64_t)k * sk] : (uint16_t)0;
+        }
+    }
+}
+
+// C tile (64 x 64) = A B over k in [kbeg, kend): K tiles of 64 through LDS, four
+// v_mfma_f32_16x16x16_bf16 steps per tile and output sub-tile, k ascending.
 __global__ void __launch_bounds__(BLK) gemm_bf16_kernel(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[TM][TK];  // [m][k]
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][TK];  // [n][k]
+    __shared__ __attribute__((aligned(16))) uint16_t As[TM][KP];  // [m][k]
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][KP];  // [n][k]
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
     f4 acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
-    const int r = tid >> 2, kk = (tid & 3) * 4;
     const int kbeg = g.part ? blockIdx.z * g.kchunk : 0;
     const int kend = g.part ? min(g.K, kbeg + g.kchunk) : g.K;
     for (int k0 = kbeg; k0 < kend; k0 += TK) {
-        const int m = m0 + r, n = n0 + r;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int k = k0 + kk + i;
-            As[r][kk + i] = (m < g.M && k < kend) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : (uint16_t)0;
-            Bs[r][kk + i] = (n < g.N && k < kend) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : (uint16_t)0;
-        }
+        load_tile(As, g.A, g.sam, g.sak, m0, g.M, k0, kend);
+        load_tile(Bs, g.B, g.sbn, g.sbk, n0, g.N, k0, kend);
         __syncthreads();
-        const s4 a = *reinterpret_cast<const s4*>(&As[wave * 16 + (lane & 15)][(lane >> 4) * 4]);
+        const int nks = min(TK, kend - k0);
+        for (int ks = 0; ks < nks; ks += 16) {
+            const s4 a = *reinterpret_cast<const s4*>(&As[wave * 16 + (lane & 15)][ks + (lane >> 4) * 4]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const s4 b = *reinterpret_cast<const s4*>(&Bs[j * 16 + (lane & 15)][(lane >> 4) * 4]);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+            for (int j = 0; j < 4; ++j) {
+                const s4 b = *reinterpret_cast<const s4*>(&Bs[j * 16 + (lane & 15)][ks + (lane >> 4) * 4]);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
@@ -211,14 +265,26 @@ __global__ void __launch_bounds__(BLK) loss_reduce_kernel(const float* part, int
 
 // Partial column sums: block (x, y) sums rows [256 y, 256 y + 256) of columns [64 x, 64 x + 64);
 // thread (j, ry) takes every fourth row from ry, the four are added in order.
+constexpr int CR = 64;  // rows per partial column sum
+
+// part[chunk][j] = sum of D[i][j] over the chunk's CR rows: row group ry of the workgroup takes rows
+// ry, ry + 4, ... (all loads issued before the adds), then the four groups are added in order.
 __global__ void __launch_bounds__(BLK) colsum_part_kernel(const float* D, int B, int N, int ld, float* part) {
     __shared__ float red[4][64];
     const int jx = threadIdx.x & 63, ry = threadIdx.x >> 6;
     const int j = blockIdx.x * 64 + jx;
-    const int r0 = blockIdx.y * 256;
+    const int r0 = blockIdx.y * CR;
     float a = 0.0f;
-    if (j < N)
-        for (int r = r0 + ry; r < min(B, r0 + 256); r += 4) a += D[(int64_t)r * ld + j];
+    if (j < N) {
+        float v[CR / 4];
+#pragma unroll
+        for (int i = 0; i < CR / 4; ++i) {
+            const int r = r0 + ry + 4 * i;
+            v[i] = r < B ? D[(int64_t)r * ld + j] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < CR / 4; ++i) a += v[i];
+    }
     red[ry][jx] = a;
     __syncthreads();
     if (ry == 0 && j < N) part[(int64_t)blockIdx.y * N + j] = ((red[0][jx] + red[1][jx]) + red[2][jx]) + red[3][jx];
@@ -228,7 +294,15 @@ __global__ void colsum_final_kernel(const float* part, int chunks, int N, float*
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
     float a = 0.0f;
-    for (int c = 0; c < chunks; ++c) a += part[(int64_t)c * N + j];
+    int c = 0;
+    for (; c + 8 <= chunks; c += 8) {  // eight loads in flight, added in chunk order
+        float v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = part[(int64_t)(c + i) * N + j];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a += v[i];
+    }
+    for (; c < chunks; ++c) a += part[(int64_t)c * N + j];
     gb[j] = a;
 }
 
@@ -241,19 +315,32 @@ __global__ void colsum_kernel(const float* D, int B, int N, int ld, float* gb) {
     gb[j] = a;
 }
 
-// Adam on n entries; refreshes the bfloat16 copy when wb is given.
-__global__ void adam_kernel(float* w, uint16_t* wb, float* m, float* v, const float* g, int64_t n, float lr,
-                            float c1, float c2) {
+// Every parameter array of the network in one launch: entry t of the concatenation belongs to the
+// array a with off[a] <= t < off[a + 1].
+struct AdamSet {
+    float* w[2 * LH_MLP_MAX_LAYERS];
+    uint16_t* wb[2 * LH_MLP_MAX_LAYERS];
+    float* m[2 * LH_MLP_MAX_LAYERS];
+    float* v[2 * LH_MLP_MAX_LAYERS];
+    const float* g[2 * LH_MLP_MAX_LAYERS];
+    int64_t off[2 * LH_MLP_MAX_LAYERS + 1];
+    int count;
+};
+
+__global__ void adam_all_kernel(AdamSet S, float lr, float c1, float c2) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const float gi = g[t];
-    const float mi = 0.9f * m[t] + 0.1f * gi;
-    const float vi = 0.999f * v[t] + 0.001f * gi * gi;
-    m[t] = mi;
-    v[t] = vi;
-    const float wi = w[t] - lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
-    w[t] = wi;
-    if (wb) wb[t] = f32_to_bf16(wi);
+    if (t >= S.off[S.count]) return;
+    int a = 0;
+    while (t >= S.off[a + 1]) ++a;
+    const int64_t i = t - S.off[a];
+    const float gi = S.g[a][i];
+    const float mi = 0.9f * S.m[a][i] + 0.1f * gi;
+    const float vi = 0.999f * S.v[a][i] + 0.001f * gi * gi;
+    S.m[a][i] = mi;
+    S.v[a][i] = vi;
+    const float wi = S.w[a][i] - lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+    S.w[a][i] = wi;
+    if (S.wb[a]) S.wb[a][i] = f32_to_bf16(wi);
 }
 
 // dst[r][c] (ld ldd) = src[r][c] (ld lds) as FP32 (+ bfloat16 copy); padding columns zero.
@@ -323,8 +410,8 @@ int gemm(const GemmArgs& a0, float* ws, int64_t ws_floats, hipStream_t s) {
     a.kchunk = a.K;
     const int tiles = ((a.N + TN - 1) / TN) * ((a.M + TM - 1) / TM);
     int splits = 1;
-    if (ws && tiles < 256 && a.K > 8 * TK) {
-        splits = (int)std::min<int64_t>((a.K + 8 * TK - 1) / (8 * TK), 512 / tiles + 1);
+    if (ws && tiles < 256 && a.K > 4 * TK) {
+        splits = (int)std::min<int64_t>((a.K + 4 * TK - 1) / (4 * TK), 512 / tiles + 1);
         splits = (int)std::min<int64_t>(splits, ws_floats / ((int64_t)a.M * a.N));
     }
     if (splits > 1) {
@@ -412,7 +499,7 @@ int backward(lh_mlp* m, const double* T, int B, float* loss, hipStream_t s) {
         int rc = gemm(a, m->ksplit_ws, m->ksplit_floats, s);
         if (rc) return rc;
         {
-            const int N = m->sizes[l + 1], chunks = (B + 255) / 256;
+            const int N = m->sizes[l + 1], chunks = (B + CR - 1) / CR;
             if (m->ksplit_ws && (int64_t)chunks * N <= m->ksplit_floats) {
                 hipLaunchKernelGGL(colsum_part_kernel, dim3((N + 63) / 64, chunks), dim3(BLK), 0, s, m->del32[l + 1], B,
                                    N, m->npad[l + 1], m->ksplit_ws);
@@ -654,14 +741,18 @@ int mlp_train_step(lh_mlp* m, const double* X, const double* T, int32_t B, doubl
     m->step += 1;
     const float c1 = (float)(1.0 - std::pow(0.9, m->step));
     const float c2 = (float)(1.0 - std::pow(0.999, m->step));
+    // every weight and bias array in one launch; padding entries have zero gradient and stay zero
+    AdamSet S{};
+    S.off[0] = 0;
     for (int l = 0; l < m->L; ++l) {
-        // padding entries have zero gradient and stay zero
-        const int64_t nw = (int64_t)m->sizes[l] * m->npad[l + 1];
-        hipLaunchKernelGGL(adam_kernel, dim3(blocks(nw)), dim3(BLK), 0, s, m->W32[l], m->Wb[l], m->mW[l], m->vW[l],
-                           m->gW[l], nw, (float)lr, c1, c2);
-        hipLaunchKernelGGL(adam_kernel, dim3(blocks(m->npad[l + 1])), dim3(BLK), 0, s, m->b32[l], (uint16_t*)nullptr,
-                           m->mb[l], m->vb[l], m->gb[l], (int64_t)m->npad[l + 1], (float)lr, c1, c2);
+        const int a = 2 * l, b = 2 * l + 1;
+        S.w[a] = m->W32[l], S.wb[a] = m->Wb[l], S.m[a] = m->mW[l], S.v[a] = m->vW[l], S.g[a] = m->gW[l];
+        S.off[a + 1] = S.off[a] + (int64_t)m->sizes[l] * m->npad[l + 1];
+        S.w[b] = m->b32[l], S.wb[b] = nullptr, S.m[b] = m->mb[l], S.v[b] = m->vb[l], S.g[b] = m->gb[l];
+        S.off[b + 1] = S.off[b] + m->npad[l + 1];
     }
+    S.count = 2 * m->L;
+    hipLaunchKernelGGL(adam_all_kernel, dim3(blocks(S.off[S.count])), dim3(BLK), 0, s, S, (float)lr, c1, c2);
     return launch_check("mlp_train_step");
 }
 
