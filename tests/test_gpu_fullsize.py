@@ -74,13 +74,19 @@ def test_full_size_sedov_rom_prefix_window(gpu_lib):
     print(f"[case] full-size sedov rom, dims {rom.windows[0].dims}, {len(rom.windows[0].elems)} sampled elements, "
           f"G={g.value}", flush=True)
     assert g.value > 1
-    G.step(flags=lib.LH_REPLAY_DT, dt_replay=_t(np.array(tr.dt)))
-    st = G.states()[0]
-    assert st.status == 0 and st.n_steps == len(tr.dt)
-    for a, b in zip(G.coords(0), run.yhat):
-        assert rel(a, b) < 1e-10
-    for a, b in zip(G.lift(0), R.final_lift(rom, run)):
-        assert rel(a.cpu().numpy(), b) < 1e-10
+    # the creation heuristic's shape, then 20 workgroups (the shape the bench's tuner picks for this workload)
+    for shape in (g.value, 20):
+        if shape != g.value:
+            G.set_workgroups(shape)
+            G.init_state(_t(y0[0]), _t(y0[1]), _t(y0[2]))
+        print(f"[case]   G={G.workgroups()}", flush=True)
+        G.step(flags=lib.LH_REPLAY_DT, dt_replay=_t(np.array(tr.dt)))
+        st = G.states()[0]
+        assert st.status == 0 and st.n_steps == len(tr.dt)
+        for a, b in zip(G.coords(0), run.yhat):
+            assert rel(a, b) < 1e-10
+        for a, b in zip(G.lift(0), R.final_lift(rom, run)):
+            assert rel(a.cpu().numpy(), b) < 1e-10
 
 
 def test_full_size_gresho_batch_instances(gpu_lib, monkeypatch):
@@ -103,15 +109,19 @@ def test_full_size_gresho_batch_instances(gpu_lib, monkeypatch):
     print(f"[case] full-size gresho batch instances, windows {[len(r.windows) for r, _, _ in items]}, "
           f"sampled elements {[max(len(w.elems) for w in r.windows) for r, _, _ in items]}, G={g.value}", flush=True)
     assert g.value == 1
-    G.init_state(torch.cat([_t(y[0]) for _, _, y in items]), torch.cat([_t(y[1]) for _, _, y in items]),
-                 torch.cat([_t(y[2]) for _, _, y in items]))
-    G.step()
-    for i, (rom, run, _) in enumerate(items):
-        st = G.states()[i]
-        assert st.status == 0 and st.done == 1
-        assert st.n_steps == len(run.dt) and st.n_rejected == run.rejections and st.w == run.w
-        for a, b in zip(G.coords(i), run.yhat):
-            assert rel(a, b) < 1e-9
+    # one workgroup per instance (tiles from global memory), then two (the bench's tuned shape)
+    for shape in (1, 2):
+        G.set_workgroups(shape)
+        G.init_state(torch.cat([_t(y[0]) for _, _, y in items]), torch.cat([_t(y[1]) for _, _, y in items]),
+                     torch.cat([_t(y[2]) for _, _, y in items]))
+        print(f"[case]   G={G.workgroups()}", flush=True)
+        G.step()
+        for i, (rom, run, _) in enumerate(items):
+            st = G.states()[i]
+            assert st.status == 0 and st.done == 1
+            assert st.n_steps == len(run.dt) and st.n_rejected == run.rejections and st.w == run.w
+            for a, b in zip(G.coords(i), run.yhat):
+                assert rel(a, b) < 1e-9
 
 
 @pytest.mark.parametrize("N,m,n", [(352947, 640, 20), (823875, 200, 40)], ids=["tg3d_24_x", "sedov3d_32_x"])
