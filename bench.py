@@ -131,10 +131,11 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
 
 
 def mlp_step_flops(batch: int, sizes) -> float:
-    """Algorithmic flops of one full-batch training step: the forward product (2 per weight and
-    sample) and the two backward products (input gradients and weight gradients)."""
-    w = sum(a * b for a, b in zip(sizes[:-1], sizes[1:]))
-    return 6.0 * batch * w
+    """Algorithmic flops of one full-batch training step: the forward product and the weight
+    gradients (2 per weight and sample each), and the input gradients of every layer but the first
+    (its input is the data, whose gradient is not needed)."""
+    w = [a * b for a, b in zip(sizes[:-1], sizes[1:])]
+    return 2.0 * batch * (2 * sum(w) + sum(w[1:]))
 
 
 def fom_force_rate(lib, wl, reps: int = 20, seed: int = 7, n_states: int = 1):
