@@ -76,6 +76,51 @@ def greedy_deim(U: np.ndarray, ns: int) -> np.ndarray:
     return np.array(Z, dtype=np.int64)
 
 
+def qdeim(U: np.ndarray, ns: int) -> np.ndarray:
+    """Q-DEIM row indices (Sec. 3.6 names it as the alternative to the greedy choice): the pivots of
+    the QR factorisation with column pivoting of U^T.
+
+    Column j of U^T is row j of U.  Step k of the pivoted QR takes the unselected row j of largest
+    norm of W[j, k:], where W is U with the reflectors of the previous steps applied to its columns
+    k.., then applies the Householder reflector that maps the pivot row's W[p, k:] to a multiple of
+    e_1 to every row.  The norm is compared through the same quantised key as the greedy choice
+    (2^-40 of the largest norm over all rows, ties to the smallest row index).
+
+    Reading for n_s > n (the paper does not say how Q-DEIM oversamples): the pivoted QR is run in
+    rounds, each restarting from U and skipping the rows chosen in earlier rounds, until n_s rows
+    are chosen; each round adds up to n rows that span the row space of U well among those left.
+    n_s = N returns all rows in order.
+    """
+    N, n = U.shape
+    ns = min(ns, N)
+    if ns == N:
+        return np.arange(N, dtype=np.int64)
+    if ns < n:
+        raise ValueError("n_s must be at least n")
+    Z: list[int] = []
+    chosen = np.zeros(N, dtype=bool)
+    while len(Z) < ns:
+        W = U.astype(np.float64).copy()
+        for k in range(n):
+            if len(Z) == ns:
+                break
+            norms = np.sqrt(np.sum(W[:, k:] ** 2, axis=1))
+            key = residual_keys(norms)
+            j = int(np.argmax(np.where(chosen, -1, key)))
+            Z.append(j)
+            chosen[j] = True
+            x = W[j, k:].copy()
+            alpha, xn2 = x[0], float(np.sum(x[1:] ** 2))
+            if xn2 == 0.0:
+                continue
+            beta = -np.copysign(np.sqrt(alpha * alpha + xn2), alpha)
+            v = x / (alpha - beta)
+            v[0] = 1.0
+            tau = (beta - alpha) / beta
+            W[:, k:] -= tau * np.outer(W[:, k:] @ v, v)
+    return np.array(Z, dtype=np.int64)
+
+
 def deim_pinv(U: np.ndarray, Z: np.ndarray) -> np.ndarray:
     """(Z^T U)^+ (n x n_s) through a QR factorisation of Z^T U."""
     ZU = U[Z, :]

@@ -74,7 +74,10 @@ def sampled_rows(op: F.Operator, elems: np.ndarray):
     return np.sort(rows_k), np.sort(rows_t)
 
 
-def build_window(op, S_list, os_list, T_end, energy_frac, n_fixed, lam, n_max=0) -> WindowROM:
+SAMPLERS = {"deim": D.greedy_deim, "qdeim": D.qdeim}
+
+
+def build_window(op, S_list, os_list, T_end, energy_frac, n_fixed, lam, n_max=0, sampler="deim") -> WindowROM:
     Phis, sigmas = [], []
     for f in range(3):
         nf = n_fixed[f] if n_fixed else 0
@@ -83,8 +86,9 @@ def build_window(op, S_list, os_list, T_end, energy_frac, n_fixed, lam, n_max=0)
         sigmas.append(sigma)
     PF1, PFtv = sns_bases(op, Phis[1], Phis[2])
     nv, ne = Phis[1].shape[1], Phis[2].shape[1]
-    Z1 = D.greedy_deim(PF1, int(round(lam[0] * nv)))
-    Z2 = D.greedy_deim(PFtv, int(round(lam[1] * ne)))
+    pick = SAMPLERS[sampler]
+    Z1 = pick(PF1, int(round(lam[0] * nv)))
+    Z2 = pick(PFtv, int(round(lam[1] * ne)))
     A1 = D.deim_pinv(PF1, Z1)
     A2 = D.deim_pinv(PFtv, Z2)
     elems = D.closure_elements(op.mesh, op.en, Z1, Z2)
@@ -95,13 +99,14 @@ def build_window(op, S_list, os_list, T_end, energy_frac, n_fixed, lam, n_max=0)
 
 
 def build_rom(op, trajs, offsets, T_ends, energy_frac=0.9999, n_fixed=None, lam=(2.0, 2.0),
-              n_max=0, online_offsets=None) -> ROM:
-    """Offline phase: per-window POD, SNS, DEIM and reduced operators."""
+              n_max=0, online_offsets=None, sampler="deim") -> ROM:
+    """Offline phase: per-window POD, SNS, DEIM (greedy, or Q-DEIM with sampler="qdeim") and
+    reduced operators."""
     mats = snapshot_matrices(trajs, offsets, T_ends)
     os_on = offsets[0] if online_offsets is None else online_offsets
     wins = []
     for w, Tw in enumerate(T_ends):
-        win = build_window(op, mats[w], os_on, Tw, energy_frac, n_fixed, lam, n_max)
+        win = build_window(op, mats[w], os_on, Tw, energy_frac, n_fixed, lam, n_max, sampler)
         if w > 0:
             prev = wins[-1]
             win.trans = [(win.Phi[f].T @ prev.Phi[f], win.Phi[f].T @ (prev.os[f] - win.os[f])) for f in range(3)]

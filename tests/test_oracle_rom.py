@@ -256,3 +256,47 @@ def test_rom_second_order_in_time(tg_fom):
         sols.append(np.concatenate(run.yhat))
     e = [np.linalg.norm(s - sols[-1]) for s in sols[:3]]
     assert 3.3 < e[0] / e[1] < 4.8 and 3.3 < e[1] / e[2] < 4.8, e
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_qdeim_equals_lapack_column_pivoted_qr(seed):
+    """n_s = n: the pivots of the QR with column pivoting of U^T (LAPACK geqp3 through SciPy)."""
+    rng = np.random.default_rng(seed)
+    N, n = 70, 9
+    U = rng.normal(size=(N, n))
+    piv = sla.qr(U.T, pivoting=True, mode="r")[1]
+    np.testing.assert_array_equal(D.qdeim(U, n), piv[:n])
+
+
+def test_qdeim_meets_its_a_priori_bound_and_finds_a_permuted_identity():
+    """||(Z^T U)^{-1}||_2 <= sqrt(n (N - n + 1)) sqrt(4^n + 6n - 1) / 3 for orthonormal U (the bound
+    of QR with column pivoting that Q-DEIM inherits), and a basis of unit vectors is sampled at its
+    unit entries."""
+    rng = np.random.default_rng(11)
+    for N, n in ((200, 6), (120, 10)):
+        U = np.linalg.qr(rng.normal(size=(N, n)))[0]
+        Z = D.qdeim(U, n)
+        bound = np.sqrt(n * (N - n + 1)) * np.sqrt(4.0 ** n + 6 * n - 1) / 3
+        assert np.linalg.norm(np.linalg.inv(U[Z, :]), 2) <= bound
+    perm = np.array([17, 3, 40, 8, 29])
+    E = np.eye(50)[:, perm]
+    assert set(D.qdeim(E, 5).tolist()) == set(perm.tolist())
+
+
+@pytest.mark.parametrize("ns", [12, 17, 25])
+def test_qdeim_rounds_oversample_with_disjoint_well_posed_rows(ns):
+    """n_s > n: rounds of pivoted QR restarted from U, each skipping the rows already chosen; every
+    full round's rows alone interpolate (U[Z_round, :] invertible) and the projector is exact on
+    range(U)."""
+    rng = np.random.default_rng(13)
+    N, n = 90, 6
+    U = rng.normal(size=(N, n))
+    Z = D.qdeim(U, ns)
+    assert len(Z) == ns and len(set(Z.tolist())) == ns
+    np.testing.assert_array_equal(Z[:n], D.qdeim(U, n))
+    for r in range(ns // n):
+        assert np.linalg.cond(U[Z[r * n:(r + 1) * n], :]) < 1e8
+    A = D.deim_pinv(U, Z)
+    g = U @ rng.normal(size=n)
+    np.testing.assert_allclose(U @ (A @ g[Z]), g, atol=1e-10)
+    np.testing.assert_array_equal(D.qdeim(U, N), np.arange(N))
