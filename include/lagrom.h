@@ -203,6 +203,22 @@ size_t rom_sample_deim_workspace_size(int64_t N, int32_t n, int32_t n_s);
 int rom_sample_deim(const double* U, int64_t N, int32_t n, int64_t ld, int32_t n_s, int32_t* idx, double* pinv,
                     void* work, size_t work_bytes, hipStream_t stream);
 
+size_t rom_sample_qdeim_workspace_size(int64_t N, int32_t n, int32_t n_s);
+
+/* Q-DEIM (Sec. 3.6, the sampler based on QR with column pivoting): the
+ * same outputs as rom_sample_deim, with the rows taken as the pivots of the
+ * QR factorisation with column pivoting of U^T.  Step k takes the unselected
+ * row j of largest ||W[j, k:]|| (W = U with the previous steps' Householder
+ * reflectors applied to its columns k..), compared through the quantised
+ * key floor(||.|| / max ||.|| * 2^40) with ties to the smallest index.  For
+ * n_s > n the pivoted QR is run again from U, skipping the rows already
+ * chosen, until n_s rows are chosen (the paper gives no oversampling rule
+ * for Q-DEIM).  U (dev, N x n, ld) is not modified; idx (dev, n_s, selection
+ * order); pinv (dev, n x n_s, ld n).  Needs N < 2^23.  Returns LH_ERANK when
+ * cond(Z^T U) > 1e12.  Synchronises (reads the condition). */
+int rom_sample_qdeim(const double* U, int64_t N, int32_t n, int64_t ld, int32_t n_s, int32_t* idx, double* pinv,
+                     void* work, size_t work_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------------ ROM */
 
 /* One time window of one ROM instance (Sec. 4): bases, offsets, sampling

@@ -10,6 +10,13 @@
 // bits, inverted row index in the low 23 bits), so the choice is exact and
 // independent of the reduction order.  The pseudo-inverse comes from a
 // Householder QR of Z^T U: (Z^T U)^+ = R^{-1} Q_n^T.
+//
+// rom_sample_qdeim takes the rows instead from the QR factorisation with
+// column pivoting of U^T (Q-DEIM): W = U in workspace; step k takes the
+// unselected row j of largest ||W[j, k:]|| (same quantised key and pick
+// reduction as above) and applies that row's Householder reflector to
+// columns k.. of every row.  For n_s > n the pivoted QR runs again from U,
+// skipping the rows already chosen, until n_s rows are chosen.
 #include <algorithm>
 #include <vector>
 
@@ -243,17 +250,80 @@ __global__ void __launch_bounds__(TB) pinv_kernel(const double* U, int64_t ld, i
     }
 }
 
+// r[j] = ||W[j, k:]|| (components added in order), per-block max.  W is N x n, column-major.
+__global__ void __launch_bounds__(TB) qr_norm_kernel(const double* W, int64_t N, int n, int k, double* r,
+                                                    double* part_max) {
+    __shared__ double sh[TB];
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < N; i += (int64_t)gridDim.x * TB) {
+        double acc = 0.0;
+        for (int c = k; c < n; ++c) {
+            const double w = W[(int64_t)c * N + i];
+            acc += w * w;
+        }
+        const double nr = sqrt(acc);
+        r[i] = nr;
+        m = fmax(m, nr);
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = TB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part_max[blockIdx.x] = sh[0];
+}
+
+// Householder reflector of the pivot row p = Z[pos]: H = I - tau v v^T (v_0 = 1) maps W[p, k:] to a
+// multiple of e_0.  hv[0 .. n-k-1] = v, hv[n] = tau (0: nothing to reflect).  One thread.
+__global__ void qr_reflect_kernel(const double* W, int64_t N, int n, int k, const int32_t* Z, int pos, double* hv) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t p = Z[pos];
+    const double alpha = W[(int64_t)k * N + p];
+    double xn2 = 0.0;
+    for (int c = k + 1; c < n; ++c) {
+        const double w = W[(int64_t)c * N + p];
+        xn2 += w * w;
+    }
+    if (xn2 == 0.0) {
+        hv[n] = 0.0;
+        return;
+    }
+    const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+    const double scal = 1.0 / (alpha - beta);
+    hv[0] = 1.0;
+    for (int c = k + 1; c < n; ++c) hv[c - k] = W[(int64_t)c * N + p] * scal;
+    hv[n] = (beta - alpha) / beta;
+}
+
+// W[j, k:] -= tau (W[j, k:] . v) v^T for every row j.
+__global__ void __launch_bounds__(TB) qr_apply_kernel(double* W, int64_t N, int n, int k, const double* hv) {
+    const double t = hv[n];
+    if (t == 0.0) return;
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < N; i += (int64_t)gridDim.x * TB) {
+        double s = 0.0;
+        for (int c = k; c < n; ++c) s += hv[c - k] * W[(int64_t)c * N + i];
+        for (int c = k; c < n; ++c) W[(int64_t)c * N + i] -= t * s * hv[c - k];
+    }
+}
+
+__global__ void copy_cols_kernel(const double* U, int64_t ld, int64_t N, int n, double* W) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) W[(int64_t)blockIdx.y * N + i] = U[(int64_t)blockIdx.y * ld + i];
+}
+
 struct DeimWork {
     double *r, *c, *part_max, *M, *tau, *y, *Rinv, *Q, *cond;
     unsigned long long* part_key;
     uint8_t* chosen;
+    double *W, *hv;  // Q-DEIM only
 };
 
 constexpr int NPARTS = 512;
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-static size_t deim_bytes(int64_t N, int n, int ns, DeimWork* out, char* base) {
+static size_t deim_bytes(int64_t N, int n, int ns, DeimWork* out, char* base, bool qr = false) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char* p = base ? base + off : nullptr;
@@ -273,6 +343,8 @@ static size_t deim_bytes(int64_t N, int n, int ns, DeimWork* out, char* base) {
     w.cond = (double*)take(D);
     w.part_key = (unsigned long long*)take(8 * NPARTS);
     w.chosen = (uint8_t*)take(N);
+    w.W = qr ? (double*)take(D * (size_t)N * n) : nullptr;
+    w.hv = qr ? (double*)take(D * (n + 1)) : nullptr;
     if (out) *out = w;
     return off;
 }
@@ -332,6 +404,60 @@ int rom_sample_deim(const double* U, int64_t N, int32_t n, int64_t ld, int32_t n
     LH_HIP_CHECK(hipStreamSynchronize(s));
     if (!(cond <= 1e12)) {
         set_error("rom_sample_deim: Z^T U is numerically rank deficient");
+        return LH_ERANK;
+    }
+    return LH_OK;
+}
+
+size_t rom_sample_qdeim_workspace_size(int64_t N, int32_t n, int32_t n_s) {
+    if (N <= 0 || n <= 0) return 0;
+    const int ns = (int)std::min<int64_t>(N, std::max(n_s, n));
+    return lh::deim::deim_bytes(N, n, ns, nullptr, nullptr, true);
+}
+
+int rom_sample_qdeim(const double* U, int64_t N, int32_t n, int64_t ld, int32_t n_s, int32_t* idx, double* pinv,
+                     void* work, size_t work_bytes, hipStream_t s) {
+    using namespace lh;
+    using namespace lh::deim;
+    LH_REQUIRE(U && idx && pinv && work, "rom_sample_qdeim: null argument");
+    LH_REQUIRE(n >= 1 && N >= n && ld >= N, "rom_sample_qdeim: need N >= n >= 1 and ld >= N");
+    LH_REQUIRE(N < (1 << ROW_BITS), "rom_sample_qdeim: N must be below 2^23");
+    LH_REQUIRE(n_s >= n, "rom_sample_qdeim: n_s must be at least n");
+    const int ns = (int)std::min<int64_t>(N, n_s);
+    LH_REQUIRE(work_bytes >= rom_sample_qdeim_workspace_size(N, n, n_s), "rom_sample_qdeim: workspace too small");
+    DeimWork w;
+    deim_bytes(N, n, ns, &w, static_cast<char*>(work), true);
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    if (ns == N) {
+        hipLaunchKernelGGL(iota_kernel, dim3(nb), dim3(256), 0, s, idx, N);
+    } else {
+        hipLaunchKernelGGL(fill_u8_kernel, dim3(nb), dim3(256), 0, s, w.chosen, N);
+        const int parts = (int)std::min<int64_t>(NPARTS, (N + TB - 1) / TB);
+        int nsel = 0;
+        while (nsel < ns) {  // one round of pivoted QR from U per pass
+            hipLaunchKernelGGL(copy_cols_kernel, dim3(nb, n), dim3(256), 0, s, U, ld, N, n, w.W);
+            for (int k = 0; k < n && nsel < ns; ++k, ++nsel) {
+                hipLaunchKernelGGL(qr_norm_kernel, dim3(parts), dim3(TB), 0, s, w.W, N, n, k, w.r, w.part_max);
+                hipLaunchKernelGGL(pick_kernel, dim3(parts), dim3(TB), 0, s, w.r, N, w.chosen, w.part_max, parts,
+                                   w.part_key);
+                hipLaunchKernelGGL(finalize_pick_kernel, dim3(1), dim3(64), 0, s, w.part_key, parts, w.chosen, idx,
+                                   nsel);
+                hipLaunchKernelGGL(qr_reflect_kernel, dim3(1), dim3(64), 0, s, w.W, N, n, k, idx, nsel, w.hv);
+                hipLaunchKernelGGL(qr_apply_kernel, dim3(parts), dim3(TB), 0, s, w.W, N, n, k, w.hv);
+            }
+        }
+    }
+    int rc = launch_check("Q-DEIM selection");
+    if (rc) return rc;
+    hipLaunchKernelGGL(pinv_kernel, dim3(1), dim3(TB), 0, s, U, ld, n, idx, ns, w.M, w.tau, w.Rinv, w.Q, pinv,
+                       w.cond);
+    rc = launch_check("Q-DEIM pseudo-inverse");
+    if (rc) return rc;
+    double cond = 0.0;
+    LH_HIP_CHECK(hipMemcpyAsync(&cond, w.cond, sizeof(double), hipMemcpyDeviceToHost, s));
+    LH_HIP_CHECK(hipStreamSynchronize(s));
+    if (!(cond <= 1e12)) {
+        set_error("rom_sample_qdeim: Z^T U is numerically rank deficient");
         return LH_ERANK;
     }
     return LH_OK;

@@ -90,6 +90,8 @@ _SIGNATURES = {
                                _VP]),
     "rom_sample_deim_workspace_size": (_SZ, [_I64, _I32, _I32]),
     "rom_sample_deim": (_I32, [_VP, _I64, _I32, _I64, _I32, _VP, _VP, _VP, _SZ, _VP]),
+    "rom_sample_qdeim_workspace_size": (_SZ, [_I64, _I32, _I32]),
+    "rom_sample_qdeim": (_I32, [_VP, _I64, _I32, _I64, _I32, _VP, _VP, _VP, _SZ, _VP]),
     "rom_create": (_I32, [_VP, _I32, C.POINTER(InstanceDesc), C.POINTER(_VP), _VP]),
     "rom_destroy": (None, [_VP]),
     "rom_init_state": (_I32, [_VP, C.POINTER(InstanceDesc), _VP, _VP, _VP, _D, _VP, _VP]),
@@ -295,15 +297,22 @@ def rom_build_basis(S, energy_frac=0.9999, n_fixed=0, n_max=0):
     return Phi[: n_out.value], sigma, n_out.value
 
 
-def rom_sample_deim(U, n_s):
+def rom_sample_qdeim(U, n_s):
+    """Q-DEIM sampling, same conventions as rom_sample_deim."""
+    return rom_sample_deim(U, n_s, method="qdeim")
+
+
+def rom_sample_deim(U, n_s, method="deim"):
     """U: (n, N) row-major tensor = N x n column-major basis.  Returns (idx int32 (n_s), pinv (n_s, n) rows)."""
     lib = load()
     n, N = U.shape
     n_s = min(int(n_s), N)
     idx = torch.empty(n_s, dtype=torch.int32, device="cuda")
     pinv = torch.empty((n_s, n), dtype=torch.float64, device="cuda")  # column-major n x n_s
-    ws = torch.empty(int(lib.rom_sample_deim_workspace_size(N, n, n_s)), dtype=torch.uint8, device="cuda")
-    _check(lib.rom_sample_deim(ptr(U), N, n, N, n_s, ptr(idx), ptr(pinv), ptr(ws), ws.numel(), stream_handle()))
+    size, call = ((lib.rom_sample_qdeim_workspace_size, lib.rom_sample_qdeim) if method == "qdeim" else
+                  (lib.rom_sample_deim_workspace_size, lib.rom_sample_deim))
+    ws = torch.empty(int(size(N, n, n_s)), dtype=torch.uint8, device="cuda")
+    _check(call(ptr(U), N, n, N, n_s, ptr(idx), ptr(pinv), ptr(ws), ws.numel(), stream_handle()))
     return idx, pinv
 
 

@@ -55,8 +55,9 @@ def fom_trajectory(P: lib.Problem, t_final: float, fixed_dt: float = 0.0, max_st
 
 
 def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_frac=0.9999, n_fixed=(), n_max=64,
-                  lam=(2.0, 2.0), t_final=None, verbose=False, snapshot_offsets=None):
-    """Per-window POD, SNS and DEIM on the GPU; returns a lib.Rom instance description.
+                  lam=(2.0, 2.0), t_final=None, verbose=False, snapshot_offsets=None, sampler="deim"):
+    """Per-window POD, SNS and DEIM (greedy, or Q-DEIM with sampler="qdeim") on the GPU; returns a lib.Rom
+    instance description.
 
     Snapshots are taken relative to each trajectory's own initial state, or to snapshot_offsets
     (one (x, v, e) for every trajectory) when given.
@@ -94,8 +95,8 @@ def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_f
             lib._check(so.lh_mass_apply_v(P.h, lib.ptr(phis[1][k]), lib.ptr(PF1[k]), stream))
         for k in range(dims[2]):
             lib._check(so.lh_mass_apply_e(P.h, lib.ptr(phis[2][k]), lib.ptr(PFtv[k]), stream))
-        z1, a1 = lib.rom_sample_deim(PF1, int(round(lam[0] * dims[1])))
-        z2, a2 = lib.rom_sample_deim(PFtv, int(round(lam[1] * dims[2])))
+        z1, a1 = lib.rom_sample_deim(PF1, int(round(lam[0] * dims[1])), method=sampler)
+        z2, a2 = lib.rom_sample_deim(PFtv, int(round(lam[1] * dims[2])), method=sampler)
         windows.append(dict(t_end=Tw, phi=phis, os=list(online_offsets), z1=z1, z2=z2, a1=a1, a2=a2))
     return dict(t_final=t_final if t_final is not None else T[-1], windows=windows)
 

@@ -127,3 +127,33 @@ def test_deim_rank_deficiency_reported(gpu_lib):
     with pytest.raises(lib.LagromError) as ei:
         lib.rom_sample_deim(_rows(U), 8)
     assert ei.value.code == -7
+
+
+@pytest.mark.parametrize("N,n,ns,seed", [(500, 8, 8, 0), (500, 8, 19, 1), (731, 12, 30, 2), (300, 5, 300, 3),
+                                         (4099, 20, 123, 4)])
+def test_qdeim_matches_oracle_random(gpu_lib, N, n, ns, seed):
+    """Q-DEIM indices bit-exact with the oracle: one round (n_s = n), ragged rounds, all rows."""
+    from paper_2104_11404_amd import lib
+    print(f"[case] qdeim random N={N} n={n} ns={ns}", flush=True)
+    rng = np.random.default_rng(seed)
+    U = np.linalg.qr(rng.normal(size=(N, n)))[0]
+    idx, pinv = lib.rom_sample_qdeim(_rows(U), ns)
+    Zo = D.qdeim(U, ns)
+    np.testing.assert_array_equal(idx.cpu().numpy(), Zo)
+    Ao = D.deim_pinv(U, Zo)
+    assert np.linalg.norm(pinv.cpu().numpy().T - Ao) <= 1e-10 * np.linalg.norm(Ao)
+
+
+def test_qdeim_sns_basis_with_zero_rows_and_ties(gpu_lib, tg_snapshots):
+    from paper_2104_11404_amd import lib
+    op, mats = tg_snapshots
+    for f, lam in ((1, 1), (2, 2), (1, 5)):
+        Phi, _, _ = pod_basis(mats[f], n_fixed=6)
+        U = op.Mv_eff @ Phi if f == 1 else op.Me @ Phi
+        ns = lam * 6
+        print(f"[case] qdeim sns field {f} ns={ns}", flush=True)
+        idx, pinv = lib.rom_sample_qdeim(_rows(U), ns)
+        Zo = D.qdeim(U, ns)
+        np.testing.assert_array_equal(idx.cpu().numpy(), Zo)
+        Ao = D.deim_pinv(U, Zo)
+        assert np.linalg.norm(pinv.cpu().numpy().T - Ao) <= 1e-10 * np.linalg.norm(Ao)

@@ -276,3 +276,30 @@ def test_rom_zero_steps_and_oversized_bases(gpu_lib, tg):
     inst["windows"][0]["phi"][0] = big
     with pytest.raises(lib.LagromError, match="64"):
         lib.Rom(P, [inst])
+
+
+def test_rom_on_qdeim_sampling_matches_oracle(gpu_lib, tg):
+    """The windowed ROM with Q-DEIM rows and pseudo-inverses built by the GPU offline chain matches
+    the oracle's ROM built with its own Q-DEIM."""
+    from paper_2104_11404_amd import lib, pipeline
+    wl, op, tr, y0 = tg
+    print("[case] rom tg2d on q-deim sampling", flush=True)
+    rom = R.build_rom(op, [tr], [y0], [wl.t_final], n_fixed=wl.n_fixed, lam=(2, 2), sampler="qdeim")
+    run = R.run_rom(op, rom, y0, wl.t_final, fixed_dt=wl.fixed_dt)
+    P, G = _gpu_rom(wl, [(rom, wl.t_final)], [y0], dt0=wl.fixed_dt)
+    G.step(flags=lib.LH_FIXED_DT)
+    for a, b in zip(G.coords(0), run.yhat):
+        assert rel(a, b) < 1e-10
+    # the GPU offline chain with Q-DEIM, end to end: its ROM reaches the oracle's accuracy against the FOM
+    Pg = lib.Problem.from_workload(wl)
+    traj = pipeline.fom_trajectory(Pg, wl.t_final, fixed_dt=wl.fixed_dt)
+    inst = pipeline.build_offline(Pg, [traj], [wl.t_final], traj["y0"], n_fixed=wl.n_fixed, lam=(2, 2),
+                                  t_final=wl.t_final, sampler="qdeim")
+    assert int(inst["windows"][0]["z1"].numel()) == len(rom.windows[0].Z1)
+    G2 = lib.Rom(Pg, [inst])
+    G2.init_state(*traj["y0"], wl.fixed_dt)
+    G2.step(flags=lib.LH_FIXED_DT)
+    gpu_err = [rel(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip(G2.lift(0), traj["y_final"])]
+    ora_err = R.relative_errors((tr.x, tr.v, tr.e), R.final_lift(rom, run))
+    for a, b in zip(gpu_err, ora_err):
+        assert a < 10 * b + 1e-8 and b < 10 * a + 1e-8
