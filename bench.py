@@ -193,6 +193,41 @@ def autotune(rom, flags, trial_steps):
     return {"G": g, "trial_steps": trial_steps, "trial_ms": ms, "tuning_s": time.perf_counter() - t0}
 
 
+def sampler_comparison(lib, pipeline, torch, P, traj, T, wl, reps=3):
+    """The headline workload with Q-DEIM rows instead of the greedy DEIM rows (same bases, same
+    lambda): sampled elements, errors against the FOM and ROM steps/s at the tuned launch shape."""
+    out = {}
+    for name in ("deim", "qdeim"):
+        t0 = time.perf_counter()
+        inst = pipeline.build_offline(P, [traj], T, traj["y0"], energy_frac=wl.energy_frac, n_max=64, lam=wl.lam,
+                                      t_final=wl.t_final, sampler=name)
+        torch.cuda.synchronize()
+        t_off = time.perf_counter() - t0
+        rom = lib.Rom(P, [inst])
+        rom.init_state(*traj["y0"])
+        g, _ = rom.autotune(trial_steps=200)
+        ms = []
+        for _ in range(reps):
+            rom.init_state(*traj["y0"])
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            rom.step()
+            b.record()
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        st = rom.states()[0]
+        rec = {"offline_s": t_off, "workgroups": g, "sampled_elements_per_window":
+               [rom.sampled_elements(0, w) for w in range(len(T))], "status": st.status, "t": st.t}
+        if st.status == 0 and st.done == 1:
+            t = float(np.median(ms)) / 1e3
+            rec.update({"ms_per_run": t * 1e3, "rom_steps_per_s": st.n_steps / t, "rom_steps": st.n_steps,
+                        "rel_error_vs_fom": dict(zip("xve", [float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+                                                             for a, b in zip(rom.lift(0), traj["y_final"])]))})
+        out[name] = rec
+        del rom, inst
+    return out
+
+
 def headline_variants(lib, torch, rom, traj, flags, kern_ms, reps):
     """Timing statistics of the headline launch and its variants, all untimed by the contract's clock:
     per-launch median and interquartile range of the timed launches; cold launches, each after a
@@ -648,6 +683,11 @@ def main():
         if not args.no_surrogate_3d:
             out["surrogate_3d"] = surrogate_param(lib, pipeline, Wl.tg3d_param(), n_train=9, train_steps=args.train_steps,
                                                   variants=[(25, 1e30)])
+    if not args.no_variants:
+        out["samplers"] = sampler_comparison(lib, pipeline, torch, P, traj, T, wl)
+        print(f"[bench] samplers: " + ", ".join(f"{k} {v.get('ms_per_run', float('nan')):.1f} ms err "
+                                                  f"{v.get('rel_error_vs_fom')}" for k, v in out["samplers"].items()),
+              file=sys.stderr, flush=True)
     if args.sedov3d:
         out["sedov3d_batch"] = sedov3d_batch(lib, pipeline)
     if not args.no_cpu_baseline:
