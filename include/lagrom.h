@@ -356,8 +356,10 @@ int rom_set_workgroups(lh_rom* r, int32_t G, uint32_t flags, hipStream_t stream)
  * untimed and twice timed with HIP events (the faster of the two counts),
  * and keep the smallest G whose time is within 2 % of the fastest (*G_best,
  * host; *ms_best, host, may be NULL: its time in ms).  A
- * candidate whose launch fails or times out is skipped.  Allocates a scratch
- * copy of the states (not a hot call).  Synchronises. */
+ * candidate whose launch fails or times out is skipped; if none runs, the
+ * previous G is restored and LH_EDEVICE returned.  Allocates a scratch copy
+ * of the states (not a hot call).  Synchronises.  A failure to rebuild the
+ * workgroup tables (LH_EDEVICE) leaves r usable only by rom_destroy. */
 int rom_autotune(lh_rom* r, const lh_rom_state* state, int32_t trial_steps, uint32_t flags, const double* dt_replay,
                  int32_t n_replay, int32_t* G_best, float* ms_best, hipStream_t stream);
 

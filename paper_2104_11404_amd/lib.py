@@ -309,6 +309,8 @@ def rom_sample_deim(U, n_s, method="deim"):
     n_s = min(int(n_s), N)
     idx = torch.empty(n_s, dtype=torch.int32, device="cuda")
     pinv = torch.empty((n_s, n), dtype=torch.float64, device="cuda")  # column-major n x n_s
+    if method not in ("deim", "qdeim"):
+        raise ValueError(f"unknown sampler {method!r}: 'deim' or 'qdeim'")
     size, call = ((lib.rom_sample_qdeim_workspace_size, lib.rom_sample_qdeim) if method == "qdeim" else
                   (lib.rom_sample_deim_workspace_size, lib.rom_sample_deim))
     ws = torch.empty(int(size(N, n, n_s)), dtype=torch.uint8, device="cuda")
