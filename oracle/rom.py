@@ -98,10 +98,26 @@ def build_window(op, S_list, os_list, T_end, energy_frac, n_fixed, lam, n_max=0,
     return WindowROM(T_end, Phis, list(os_list), Z1, Z2, A1, A2, elems, rows_k, rows_t, Bxv, bx, sigmas)
 
 
+def window_transition(Phi_new, os_new, Phi_old, os_old, M=None):
+    """Reduced initial condition of a window from the previous window's coordinates,
+    yhat_new = T yhat_old + c.  M None: orthogonal projection of the lifted state os_old + Phi_old
+    yhat_old onto the new window (eq. ic-tw).  M given: the projection oblique in the M inner product,
+    T = Mhat^{-1} Phi_new^T M Phi_old, c = Mhat^{-1} Phi_new^T M (os_old - os_new), Mhat = Phi_new^T M
+    Phi_new (eq. ic2-tw), which minimises the M-norm of the error of the lifted initial state."""
+    if M is None:
+        return Phi_new.T @ Phi_old, Phi_new.T @ (os_old - os_new)
+    MP = M @ Phi_new
+    Mhat = Phi_new.T @ MP
+    return np.linalg.solve(Mhat, MP.T @ Phi_old), np.linalg.solve(Mhat, MP.T @ (os_old - os_new))
+
+
 def build_rom(op, trajs, offsets, T_ends, energy_frac=0.9999, n_fixed=None, lam=(2.0, 2.0),
-              n_max=0, online_offsets=None, sampler="deim") -> ROM:
+              n_max=0, online_offsets=None, sampler="deim", window_ic="orthogonal") -> ROM:
     """Offline phase: per-window POD, SNS, DEIM (greedy, or Q-DEIM with sampler="qdeim") and
-    reduced operators."""
+    reduced operators.  window_ic: "orthogonal" (eq. ic-tw) or "oblique" (eq. ic2-tw: velocity and
+    energy projected in the M_V and M_E inner products, position as in eq. ic-tw)."""
+    if window_ic not in ("orthogonal", "oblique"):
+        raise ValueError(window_ic)
     mats = snapshot_matrices(trajs, offsets, T_ends)
     os_on = offsets[0] if online_offsets is None else online_offsets
     wins = []
@@ -109,7 +125,8 @@ def build_rom(op, trajs, offsets, T_ends, energy_frac=0.9999, n_fixed=None, lam=
         win = build_window(op, mats[w], os_on, Tw, energy_frac, n_fixed, lam, n_max, sampler)
         if w > 0:
             prev = wins[-1]
-            win.trans = [(win.Phi[f].T @ prev.Phi[f], win.Phi[f].T @ (prev.os[f] - win.os[f])) for f in range(3)]
+            mass = [None, op.Mv_eff, op.Me] if window_ic == "oblique" else [None, None, None]
+            win.trans = [window_transition(win.Phi[f], win.os[f], prev.Phi[f], prev.os[f], mass[f]) for f in range(3)]
         wins.append(win)
     return ROM(wins)
 

@@ -300,3 +300,40 @@ def test_qdeim_rounds_oversample_with_disjoint_well_posed_rows(ns):
     g = U @ rng.normal(size=n)
     np.testing.assert_allclose(U @ (A @ g[Z]), g, atol=1e-10)
     np.testing.assert_array_equal(D.qdeim(U, N), np.arange(N))
+
+
+def test_oblique_window_initial_condition():
+    """eq. ic2-tw: with M = I it is eq. ic-tw; a lifted state inside the new window's affine space is
+    recovered exactly by both; otherwise it gives the smallest M-norm error of the lifted initial
+    state, which the orthogonal projection does not."""
+    rng = np.random.default_rng(17)
+    N, n_old, n_new = 60, 5, 7
+    Phi_old = np.linalg.qr(rng.normal(size=(N, n_old)))[0]
+    Phi_new = np.linalg.qr(rng.normal(size=(N, n_new)))[0]
+    os_old, os_new = rng.normal(size=N), rng.normal(size=N)
+    B = rng.normal(size=(N, N))
+    M = B @ B.T + N * np.eye(N)  # symmetric positive definite
+    T0, c0 = R.window_transition(Phi_new, os_new, Phi_old, os_old)
+    T1, c1 = R.window_transition(Phi_new, os_new, Phi_old, os_old, np.eye(N))
+    np.testing.assert_allclose(T1, T0, atol=1e-13)
+    np.testing.assert_allclose(c1, c0, atol=1e-13)
+    # a lifted state in os_new + span(Phi_new): offsets that differ inside the new span, an old window
+    # that contains the new one
+    a = rng.normal(size=n_new)
+    z = rng.normal(size=n_new)
+    os_in = os_new + Phi_new @ a
+    Phi_in = np.column_stack([Phi_old, Phi_new])
+    coef = np.concatenate([np.zeros(n_old), z - a])  # os_in + Phi_in coef = os_new + Phi_new z
+    for Mx in (None, M):
+        T2, c2 = R.window_transition(Phi_new, os_new, Phi_in, os_in, Mx)
+        np.testing.assert_allclose(T2 @ coef + c2, z, atol=1e-10)
+    # generic state: the oblique coordinates minimise the M-norm of the error
+    yh = rng.normal(size=n_old)
+    y = os_old + Phi_old @ yh
+    Tm, cm = R.window_transition(Phi_new, os_new, Phi_old, os_old, M)
+    Mnorm = lambda e: float(np.sqrt(e @ M @ e))
+    best = Mnorm(y - os_new - Phi_new @ (Tm @ yh + cm))
+    for _ in range(20):
+        d = 1e-3 * rng.normal(size=n_new)
+        assert Mnorm(y - os_new - Phi_new @ (Tm @ yh + cm + d)) >= best
+    assert Mnorm(y - os_new - Phi_new @ (T0 @ yh + c0)) > best
