@@ -237,10 +237,17 @@ typedef struct {
     const double* a2;             /* (Z2^T M_E Phi_e)^+ : n_e x n_s2, ld n_e       */
 } lh_window_desc;
 
+enum { LH_WINDOW_IC_ORTHOGONAL = 0, LH_WINDOW_IC_OBLIQUE = 1 };
+
 typedef struct {
     int32_t n_windows;
     const lh_window_desc* windows; /* (host) array of n_windows                   */
     double t_final;
+    int32_t window_ic;             /* reduced initial condition of windows w >= 1:
+                                      LH_WINDOW_IC_ORTHOGONAL, eq. ic-tw; LH_WINDOW_IC_OBLIQUE,
+                                      eq. ic2-tw (velocity and energy projected in the M_V and M_E
+                                      inner products, position as in eq. ic-tw) */
+    int32_t reserved_;
 } lh_instance_desc;
 
 #define LH_NMAX 64

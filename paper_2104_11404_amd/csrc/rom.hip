@@ -1134,8 +1134,11 @@ static int upload(lh_rom* R, const std::vector<T>& h, const T** out, std::vector
 static unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // Build the device tables of one window and its host structure.
+static int oblique_transition(lh_rom* R, const lh_problem* p, int f, const lh_window_desc& wd,
+                              const lh_window_desc* prev, double* T, double* c, hipStream_t s);
+
 static int build_window(lh_rom* R, const lh_problem* p, const lh_window_desc& wd, const lh_window_desc* prev,
-                        WinDev& W, HostWin& H, hipStream_t s) {
+                        int window_ic, WinDev& W, HostWin& H, hipStream_t s) {
     const int dim = p->dim;
     const int NK = dim == 3 ? 27 : 9, NT = dim == 3 ? 8 : 4, NKD = NK * dim;
     const int64_t NV = p->NV, NE = p->NE, nn = p->n_nodes;
@@ -1282,16 +1285,101 @@ static int build_window(lh_rom* R, const lh_problem* p, const lh_window_desc& wd
             if ((rc = dev_alloc(R, &T, (int64_t)W.n[f] * prev->n[f])) || (rc = dev_alloc(R, &c, W.n[f])) ||
                 (rc = dev_alloc(R, &dos, N)))
                 return rc;
-            hipLaunchKernelGGL(gemm_tn_kernel, dim3(W.n[f], prev->n[f]), dim3(256), 0, s, wd.phi[f], prev->phi[f], N,
-                               N, N, W.n[f], T);
             hipLaunchKernelGGL(sub_kernel, dim3(nb(N)), dim3(256), 0, s, prev->os[f], wd.os[f], dos, N);
-            hipLaunchKernelGGL(gemm_tn_kernel, dim3(W.n[f], 1), dim3(256), 0, s, wd.phi[f], dos, N, N, N, W.n[f], c);
+            if (window_ic == LH_WINDOW_IC_OBLIQUE && f > 0) {
+                if ((rc = oblique_transition(R, p, f, wd, prev, T, c, s))) return rc;
+            } else {
+                hipLaunchKernelGGL(gemm_tn_kernel, dim3(W.n[f], prev->n[f]), dim3(256), 0, s, wd.phi[f], prev->phi[f],
+                                   N, N, N, W.n[f], T);
+                hipLaunchKernelGGL(gemm_tn_kernel, dim3(W.n[f], 1), dim3(256), 0, s, wd.phi[f], dos, N, N, N, W.n[f], c);
+            }
             W.T[f] = T;
             W.c[f] = c;
         }
     }
     W.views = nullptr;
     return launch_check("rom_create window tables");
+}
+
+// Transition of field f (1: velocity, 2: energy) oblique in the mass inner product (eq. ic2-tw):
+// with P = M Phi_new (M = M_V in the eliminated form of the SNS bases, or M_E), Mhat = P^T Phi_new,
+// T = Mhat^{-1} P^T Phi_old and c = Mhat^{-1} P^T (os_old - os_new).  The products are formed on the
+// device; Mhat (symmetric positive definite, at most 64 x 64) is factorised on the host by Cholesky.
+static int oblique_transition(lh_rom* R, const lh_problem* p, int f, const lh_window_desc& wd,
+                              const lh_window_desc* prev, double* T, double* c, hipStream_t s) {
+    (void)R;
+    const int64_t N = f == 2 ? p->NE : p->NV;
+    const int nn = wd.n[f], no = prev->n[f];
+    double *P = nullptr, *G = nullptr, *dos = nullptr;
+    auto cleanup = [&]() {
+        if (P) (void)hipFree(P);
+        if (G) (void)hipFree(G);
+        if (dos) (void)hipFree(dos);
+    };
+    if (hipMalloc(&P, sizeof(double) * N * nn) != hipSuccess ||
+        hipMalloc(&G, sizeof(double) * (size_t)nn * (nn + no + 1)) != hipSuccess ||
+        hipMalloc(&dos, sizeof(double) * N) != hipSuccess) {
+        cleanup();
+        set_error("rom_create: device allocation failed (oblique window transition)");
+        return LH_EDEVICE;
+    }
+    int rc = LH_OK;
+    for (int k = 0; k < nn && rc == LH_OK; ++k)
+        rc = f == 1 ? lh_mass_apply_v(p, wd.phi[f] + (int64_t)k * N, P + (int64_t)k * N, s)
+                    : lh_mass_apply_e(p, wd.phi[f] + (int64_t)k * N, P + (int64_t)k * N, s);
+    if (rc) {
+        cleanup();
+        return rc;
+    }
+    // G = [Mhat | P^T Phi_old | P^T (os_old - os_new)], column-major nn x (nn + no + 1)
+    hipLaunchKernelGGL(sub_kernel, dim3(nb(N)), dim3(256), 0, s, prev->os[f], wd.os[f], dos, N);
+    hipLaunchKernelGGL(gemm_tn_kernel, dim3(nn, nn), dim3(256), 0, s, P, wd.phi[f], N, N, N, nn, G);
+    hipLaunchKernelGGL(gemm_tn_kernel, dim3(nn, no), dim3(256), 0, s, P, prev->phi[f], N, N, N, nn,
+                       G + (int64_t)nn * nn);
+    hipLaunchKernelGGL(gemm_tn_kernel, dim3(nn, 1), dim3(256), 0, s, P, dos, N, N, N, nn,
+                       G + (int64_t)nn * (nn + no));
+    std::vector<double> h((size_t)nn * (nn + no + 1));
+    if ((rc = launch_check("rom_create oblique transition")) ||
+        hipMemcpyAsync(h.data(), G, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        cleanup();
+        if (!rc) set_error("rom_create: copy of the oblique transition failed");
+        return rc ? rc : LH_EDEVICE;
+    }
+    cleanup();
+    // Cholesky Mhat = L L^T (lower triangle overwritten), then solve for the no + 1 right-hand sides
+    double* A = h.data();
+    for (int j = 0; j < nn; ++j) {
+        double d = A[(int64_t)j * nn + j];
+        for (int k = 0; k < j; ++k) d -= A[(int64_t)k * nn + j] * A[(int64_t)k * nn + j];
+        if (!(d > 0.0)) {
+            set_error("rom_create: reduced mass matrix not positive definite (oblique window transition)");
+            return LH_ERANK;
+        }
+        const double l = std::sqrt(d);
+        A[(int64_t)j * nn + j] = l;
+        for (int i = j + 1; i < nn; ++i) {
+            double v = A[(int64_t)j * nn + i];
+            for (int k = 0; k < j; ++k) v -= A[(int64_t)k * nn + i] * A[(int64_t)k * nn + j];
+            A[(int64_t)j * nn + i] = v / l;
+        }
+    }
+    for (int r = 0; r <= no; ++r) {
+        double* b = A + (int64_t)nn * (nn + r);
+        for (int i = 0; i < nn; ++i) {  // L y = b
+            double v = b[i];
+            for (int k = 0; k < i; ++k) v -= A[(int64_t)k * nn + i] * b[k];
+            b[i] = v / A[(int64_t)i * nn + i];
+        }
+        for (int i = nn - 1; i >= 0; --i) {  // L^T x = y
+            double v = b[i];
+            for (int k = i + 1; k < nn; ++k) v -= A[(int64_t)i * nn + k] * b[k];
+            b[i] = v / A[(int64_t)i * nn + i];
+        }
+    }
+    LH_HIP_CHECK(hipMemcpy(T, A + (int64_t)nn * nn, sizeof(double) * nn * no, hipMemcpyHostToDevice));
+    LH_HIP_CHECK(hipMemcpy(c, A + (int64_t)nn * (nn + no), sizeof(double) * nn, hipMemcpyHostToDevice));
+    return LH_OK;
 }
 
 // Resident LDS bytes of a view: kept stress, offsets (FP64), tiles and A columns (tb bytes per value).
@@ -1383,7 +1471,7 @@ static int cu_count() {
 // Two instances with field-by-field equal window descriptions read the same device data at
 // rom_create, so their window tables are equal and are built once.
 static bool same_windows(const lh_instance_desc& a, const lh_instance_desc& b) {
-    if (a.n_windows != b.n_windows) return false;
+    if (a.n_windows != b.n_windows || a.window_ic != b.window_ic) return false;
     for (int w = 0; w < a.n_windows; ++w) {
         const lh_window_desc &x = a.windows[w], &y = b.windows[w];
         if (x.t_end != y.t_end || x.z1 != y.z1 || x.n_s1 != y.n_s1 || x.z2 != y.z2 || x.n_s2 != y.n_s2 || x.a1 != y.a1 ||
@@ -1430,6 +1518,10 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
             set_error("rom_create: instance needs >= 1 window and t_final > 0");
             return fail(LH_EINVAL);
         }
+        if (d.window_ic != LH_WINDOW_IC_ORTHOGONAL && d.window_ic != LH_WINDOW_IC_OBLIQUE) {
+            set_error("rom_create: window_ic must be LH_WINDOW_IC_ORTHOGONAL or LH_WINDOW_IC_OBLIQUE");
+            return fail(LH_EINVAL);
+        }
         for (int j = 0; j < i && R->alias[i] < 0; ++j)
             if (R->alias[j] < 0 && same_windows(d, inst[j])) R->alias[i] = j;
         if (R->alias[i] >= 0) {  // same descriptions: share the device tables, keep a private copy of the headers
@@ -1439,8 +1531,8 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
         R->h_win[i].resize(d.n_windows);
         R->h_struct[i].resize(d.n_windows);
         for (int w = 0; w < d.n_windows; ++w) {
-            int rc = build_window(R, p, d.windows[w], w > 0 ? &d.windows[w - 1] : nullptr, R->h_win[i][w],
-                                  R->h_struct[i][w], s);
+            int rc = build_window(R, p, d.windows[w], w > 0 ? &d.windows[w - 1] : nullptr, d.window_ic,
+                                  R->h_win[i][w], R->h_struct[i][w], s);
             if (rc) return fail(rc);
             max_el = std::max(max_el, R->h_win[i][w].n_el);
         }

@@ -54,7 +54,8 @@ class WindowDesc(C.Structure):
 
 
 class InstanceDesc(C.Structure):
-    _fields_ = [("n_windows", C.c_int32), ("windows", C.POINTER(WindowDesc)), ("t_final", C.c_double)]
+    _fields_ = [("n_windows", C.c_int32), ("windows", C.POINTER(WindowDesc)), ("t_final", C.c_double),
+                ("window_ic", C.c_int32), ("reserved_", C.c_int32)]
 
 
 class MlpDesc(C.Structure):
@@ -349,6 +350,7 @@ class Rom:
             descs[i].n_windows = len(inst["windows"])
             descs[i].windows = C.cast(ws, C.POINTER(WindowDesc))
             descs[i].t_final = float(inst["t_final"])
+            descs[i].window_ic = {"orthogonal": 0, "oblique": 1}[inst.get("window_ic", "orthogonal")]
         self.descs = descs
         h = C.c_void_p()
         _check(lib.rom_create(problem.h, len(instances), descs, C.byref(h), stream_handle()))

@@ -55,7 +55,8 @@ def fom_trajectory(P: lib.Problem, t_final: float, fixed_dt: float = 0.0, max_st
 
 
 def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_frac=0.9999, n_fixed=(), n_max=64,
-                  lam=(2.0, 2.0), t_final=None, verbose=False, snapshot_offsets=None, sampler="deim"):
+                  lam=(2.0, 2.0), t_final=None, verbose=False, snapshot_offsets=None, sampler="deim",
+                  window_ic="orthogonal"):
     """Per-window POD, SNS and DEIM (greedy, or Q-DEIM with sampler="qdeim") on the GPU; returns a lib.Rom
     instance description.
 
@@ -98,7 +99,7 @@ def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_f
         z1, a1 = lib.rom_sample_deim(PF1, int(round(lam[0] * dims[1])), method=sampler)
         z2, a2 = lib.rom_sample_deim(PFtv, int(round(lam[1] * dims[2])), method=sampler)
         windows.append(dict(t_end=Tw, phi=phis, os=list(online_offsets), z1=z1, z2=z2, a1=a1, a2=a2))
-    return dict(t_final=t_final if t_final is not None else T[-1], windows=windows)
+    return dict(t_final=t_final if t_final is not None else T[-1], windows=windows, window_ic=window_ic)
 
 
 def build_batch(wl, lam=(2.0, 2.0), energy_frac=0.9999, verbose=False):
