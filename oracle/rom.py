@@ -31,7 +31,7 @@ import numpy as np
 from . import deim as D
 from . import fom as F
 from .pod import pod_basis
-from .windows import snapshot_matrices
+from .windows import snapshot_matrices, window_start_states
 
 
 @dataclass
@@ -59,6 +59,7 @@ class WindowROM:
 @dataclass
 class ROM:
     windows: list
+    train_offsets: list = field(default_factory=list)  # [window][trajectory] (x, v, e) snapshot offsets
 
 
 def sns_bases(op: F.Operator, Phi_v: np.ndarray, Phi_e: np.ndarray):
@@ -111,24 +112,63 @@ def window_transition(Phi_new, os_new, Phi_old, os_old, M=None):
     return np.linalg.solve(Mhat, MP.T @ Phi_old), np.linalg.solve(Mhat, MP.T @ (os_old - os_new))
 
 
+def idw_weights(params, mu, r: float = 2.0) -> np.ndarray:
+    """Inverse distance weights of eq. interpolate_os: w_k = d(mu, mu_k)^-r / sum_j d(mu, mu_j)^-r with
+    the Euclidean distance, or the unit weight of the first training parameter at distance 0."""
+    P = np.atleast_2d(np.asarray(params, dtype=np.float64).reshape(len(params), -1))
+    d = np.linalg.norm(P - np.asarray(mu, dtype=np.float64).reshape(1, -1), axis=1)
+    w = np.zeros(len(d))
+    zero = np.nonzero(d == 0.0)[0]
+    if len(zero):
+        w[zero[0]] = 1.0
+        return w
+    w = d ** (-r)
+    return w / np.sum(w)
+
+
+def interpolated_offsets(train_offsets: list, params, mu, r: float = 2.0) -> list:
+    """eq. interpolate_os for every window: train_offsets[w][k] is the offset (x, v, e) of window w
+    at training parameter k; returns one (x, v, e) per window for the parameter mu."""
+    w = idw_weights(params, mu, r)
+    return [tuple(sum(wk * np.asarray(o[f]) for wk, o in zip(w, per_k)) for f in range(3)) for per_k in train_offsets]
+
+
 def build_rom(op, trajs, offsets, T_ends, energy_frac=0.9999, n_fixed=None, lam=(2.0, 2.0),
-              n_max=0, online_offsets=None, sampler="deim", window_ic="orthogonal") -> ROM:
+              n_max=0, online_offsets=None, sampler="deim", window_ic="orthogonal",
+              window_offsets="initial") -> ROM:
     """Offline phase: per-window POD, SNS, DEIM (greedy, or Q-DEIM with sampler="qdeim") and
     reduced operators.  window_ic: "orthogonal" (eq. ic-tw) or "oblique" (eq. ic2-tw: velocity and
-    energy projected in the M_V and M_E inner products, position as in eq. ic-tw)."""
+    energy projected in the M_V and M_E inner products, position as in eq. ic-tw).
+
+    window_offsets (Sec. 4.5): "initial", every window's snapshots relative to offsets (one initial
+    state per trajectory); "window_start", window w's snapshots of trajectory k relative to that
+    trajectory's state at the window's start.  online_offsets: one (x, v, e) for every window, or a
+    list with one per window (for instance the interpolated offsets of eq. interpolate_os).
+    The training offsets per window and trajectory are kept in ROM.train_offsets."""
     if window_ic not in ("orthogonal", "oblique"):
         raise ValueError(window_ic)
-    mats = snapshot_matrices(trajs, offsets, T_ends)
+    if window_offsets == "initial":
+        by_window = [list(offsets)] * len(T_ends)
+    elif window_offsets == "window_start":
+        starts = [window_start_states(tr, y0, T_ends) for tr, y0 in zip(trajs, offsets)]
+        by_window = [[starts[k][w] for k in range(len(trajs))] for w in range(len(T_ends))]
+    else:
+        raise ValueError(window_offsets)
+    mats = snapshot_matrices(trajs, offsets, T_ends, offsets_by_window=by_window)
     os_on = offsets[0] if online_offsets is None else online_offsets
+    per_window_os = isinstance(os_on, list)
     wins = []
     for w, Tw in enumerate(T_ends):
-        win = build_window(op, mats[w], os_on, Tw, energy_frac, n_fixed, lam, n_max, sampler)
+        win = build_window(op, mats[w], os_on[w] if per_window_os else os_on, Tw, energy_frac, n_fixed, lam, n_max,
+                           sampler)
         if w > 0:
             prev = wins[-1]
             mass = [None, op.Mv_eff, op.Me] if window_ic == "oblique" else [None, None, None]
             win.trans = [window_transition(win.Phi[f], win.os[f], prev.Phi[f], prev.os[f], mass[f]) for f in range(3)]
         wins.append(win)
-    return ROM(wins)
+    rom = ROM(wins)
+    rom.train_offsets = by_window
+    return rom
 
 
 def lift_rows(win: WindowROM, f: int, yhat: np.ndarray, rows: np.ndarray, N: int) -> np.ndarray:

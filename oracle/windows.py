@@ -82,13 +82,29 @@ def window_columns(traj, T_ends: list):
     return out
 
 
-def snapshot_matrices(trajs: list, offsets: list, T_ends: list):
-    """Per window, per field (x, v, e): N x m matrices of deviations from offsets."""
+def window_start_states(traj, y0, T_ends: list) -> list:
+    """The trajectory's state at the start of each window (Sec. 4.5, the offset choice of the
+    previous and the interpolated offsets): y0 for the first window, then the step state at which the
+    previous window closed (the window's 'init' column)."""
+    out = []
+    for w, cols in enumerate(window_columns(traj, T_ends)):
+        if w > 0 and cols and cols[0][0] == "init":
+            s = cols[0][1]
+            out.append(tuple(np.array(a) for a in traj.snaps[2 * (s - 1) + 1]))
+        else:
+            out.append(tuple(np.array(a) for a in y0))
+    return out
+
+
+def snapshot_matrices(trajs: list, offsets: list, T_ends: list, offsets_by_window: list = None):
+    """Per window, per field (x, v, e): N x m matrices of deviations from offsets (one (x, v, e)
+    per trajectory), or from offsets_by_window[w][k] when given (one per window and trajectory)."""
     per_window = []
     cols_per_traj = [window_columns(tr, T_ends) for tr in trajs]
     for w in range(len(T_ends)):
         mats = [[], [], []]
-        for tr, os_, cols in zip(trajs, offsets, cols_per_traj):
+        offs = offsets if offsets_by_window is None else offsets_by_window[w]
+        for tr, os_, cols in zip(trajs, offs, cols_per_traj):
             for kind, idx in cols[w]:
                 if kind == "init":
                     y = tr.snaps[2 * (idx - 1) + 1]

@@ -13,7 +13,7 @@ from oracle import fom as F
 from oracle import rom as R
 from oracle.pod import canonical_signs, energy_dimension, pod_basis
 from oracle.problems import initial_state
-from oracle.windows import first_reaching, snapshot_matrices, window_columns, windows_by_samples
+from oracle.windows import first_reaching, snapshot_matrices, window_columns, window_start_states, windows_by_samples
 from tests.oracle_adapter import oracle_problem
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -337,3 +337,41 @@ def test_oblique_window_initial_condition():
         d = 1e-3 * rng.normal(size=n_new)
         assert Mnorm(y - os_new - Phi_new @ (Tm @ yh + cm + d)) >= best
     assert Mnorm(y - os_new - Phi_new @ (T0 @ yh + c0)) > best
+
+
+def test_idw_weights_of_the_interpolated_offsets():
+    """eq. interpolate_os with r = 2: hand values for three scalar parameters, a convex combination,
+    exact at training parameters, symmetric between two equidistant ones."""
+    w = R.idw_weights([0.8, 1.0, 1.2], 0.9)
+    np.testing.assert_allclose(w, np.array([100.0, 100.0, 1 / 0.09]) / (200.0 + 1 / 0.09), rtol=1e-14)
+    np.testing.assert_array_equal(R.idw_weights([0.8, 1.0, 1.2], 1.2), [0.0, 0.0, 1.0])
+    w = R.idw_weights([[0.0, 0.0], [2.0, 0.0]], [1.0, 3.0])
+    np.testing.assert_allclose(w, [0.5, 0.5], rtol=1e-15)
+    assert abs(R.idw_weights([0.8, 1.0, 1.2], 1.37).sum() - 1.0) < 1e-15
+    offs = [[(np.full(3, k + 1.0), np.zeros(3), np.ones(2)) for k in range(3)] for _ in range(2)]
+    got = R.interpolated_offsets(offs, [0.8, 1.0, 1.2], 0.9)
+    np.testing.assert_allclose(got[1][0], np.full(3, w_dot := float(np.dot(R.idw_weights([0.8, 1.0, 1.2], 0.9),
+                                                                          [1.0, 2.0, 3.0]))), rtol=1e-15)
+    np.testing.assert_allclose(got[0][2], np.ones(2), rtol=1e-15)
+
+
+def test_window_start_offsets_are_the_trajectory_states_at_window_starts():
+    """The window-start offsets are the step states that close the previous windows, so each window's
+    first snapshot column (that state) is the zero deviation; the first window starts at y0."""
+    wl = W.tg2d(4)
+    op = F.build_operator(oracle_problem(wl))
+    tr = F.run_fom(op, 0.02, fixed_dt=1e-3)
+    y0 = initial_state(op.prob)
+    T = [0.007, 0.014, 0.02]
+    starts = window_start_states(tr, y0, T)
+    for f in range(3):
+        np.testing.assert_array_equal(starts[0][f], y0[f])
+    mats = snapshot_matrices([tr], [y0], T, offsets_by_window=[[s] for s in starts])
+    for w in (1, 2):
+        for f in range(3):
+            assert np.abs(mats[w][f][:, 0]).max() == 0.0
+    rom = R.build_rom(op, [tr], [y0], T, n_fixed=(3, 3, 3), lam=(2, 2), window_offsets="window_start",
+                      online_offsets=starts)
+    for w in range(3):
+        for f in range(3):
+            np.testing.assert_array_equal(rom.windows[w].os[f], starts[w][f])
