@@ -372,6 +372,18 @@ int rom_autotune(lh_rom* r, const lh_rom_state* state, int32_t trial_steps, uint
 
 /* ------------------------------------------------------ offline helpers */
 
+/* Inverse distance weights of the parametric offset interpolation
+ * (eq. interpolate_os), host only: params (host, K x d row-major training
+ * parameters), mu (host, d), r >= 1 the power; w (host, K) receives
+ * d(mu, mu_k)^-r / sum_j d(mu, mu_j)^-r with the Euclidean distance, or the
+ * unit weight of the first training parameter at distance 0. */
+int lh_idw_weights(const double* params, int32_t K, int32_t d, const double* mu, double r, double* w);
+
+/* out = sum_k w[k] x[k] (k in order) for the interpolated offsets of
+ * eq. interpolate_os: x (host array of K <= 16 dev vectors of length N),
+ * w (host, K), out (dev, N; may not alias any x[k]). */
+int lh_weighted_sum(const double* const* x, const double* w, int32_t K, int64_t N, double* out, hipStream_t stream);
+
 /* Snapshot deviations (Sec. 3.4): out[:, j] = snaps[:, j] - os for j < m.
  * snaps (dev, N x m, ld), os (dev, N), out (dev, N x m, ldo); out may be a
  * column block of a larger matrix holding several parameters' snapshots. */

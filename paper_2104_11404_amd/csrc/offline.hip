@@ -102,6 +102,23 @@ __global__ void __launch_bounds__(256) project_kernel(const double* Phi, int64_t
 }  // namespace off
 }  // namespace lh
 
+constexpr int WSUM_MAX = 16;  // vectors combined by one lh_weighted_sum call
+
+struct WsumArgs {
+    const double* x[WSUM_MAX];
+    double w[WSUM_MAX];
+    int K;
+};
+
+// out[i] = sum_k w_k x_k[i], k in order.
+__global__ void weighted_sum_kernel(WsumArgs a, int64_t N, double* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double acc = 0.0;
+    for (int k = 0; k < a.K; ++k) acc += a.w[k] * a.x[k][i];
+    out[i] = acc;
+}
+
 extern "C" {
 
 int lh_snapshot_deviation(const double* snaps, int64_t N, int32_t m, int64_t ld, const double* os, double* out,
@@ -212,6 +229,46 @@ int lh_mass_apply_e(const lh_problem* p, const double* in, double* out, hipStrea
     hipLaunchKernelGGL(off::diag_mul_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out,
                        ex->d_mediag, p->dim == 3 ? 8 : 4, n);
     return launch_check("lh_mass_apply_e");
+}
+
+int lh_idw_weights(const double* params, int32_t K, int32_t d, const double* mu, double r, double* w) {
+    using namespace lh;
+    LH_REQUIRE(params && mu && w && K >= 1 && d >= 1, "lh_idw_weights: bad arguments");
+    LH_REQUIRE(r >= 1.0, "lh_idw_weights: the power r must be at least 1");
+    std::vector<double> dist(K);
+    for (int k = 0; k < K; ++k) {
+        double s2 = 0.0;
+        for (int j = 0; j < d; ++j) {
+            const double t = mu[j] - params[(int64_t)k * d + j];
+            s2 += t * t;
+        }
+        dist[k] = std::sqrt(s2);
+    }
+    for (int k = 0; k < K; ++k)
+        if (dist[k] == 0.0) {  // a training parameter: its own offsets
+            for (int l = 0; l < K; ++l) w[l] = l == k ? 1.0 : 0.0;
+            return LH_OK;
+        }
+    double tot = 0.0;
+    for (int k = 0; k < K; ++k) tot += (w[k] = std::pow(dist[k], -r));
+    for (int k = 0; k < K; ++k) w[k] /= tot;
+    return LH_OK;
+}
+
+int lh_weighted_sum(const double* const* x, const double* w, int32_t K, int64_t N, double* out, hipStream_t s) {
+    using namespace lh;
+    LH_REQUIRE(x && w && out && K >= 1 && N >= 0, "lh_weighted_sum: bad arguments");
+    LH_REQUIRE(K <= WSUM_MAX, "lh_weighted_sum: at most 16 vectors");
+    if (N == 0) return LH_OK;
+    WsumArgs a{};
+    a.K = K;
+    for (int k = 0; k < K; ++k) {
+        LH_REQUIRE(x[k], "lh_weighted_sum: null vector");
+        a.x[k] = x[k];
+        a.w[k] = w[k];
+    }
+    hipLaunchKernelGGL(weighted_sum_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, a, N, out);
+    return launch_check("lh_weighted_sum");
 }
 
 }  // extern "C"

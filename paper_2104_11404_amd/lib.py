@@ -115,6 +115,8 @@ _SIGNATURES = {
     "lh_project_snapshots": (_I32, [_VP, _I32, _I64, _I64, _VP, _I32, _I64, _VP, _VP, _I64, _VP]),
     "rom_attach_surrogate": (_I32, [_VP, _I32, _I32, _VP, _I32, _D]),
     "lh_snapshot_deviation": (_I32, [_VP, _I64, _I32, _I64, _VP, _VP, _I64, _VP]),
+    "lh_idw_weights": (_I32, [C.POINTER(_D), _I32, _I32, C.POINTER(_D), _D, C.POINTER(_D)]),
+    "lh_weighted_sum": (_I32, [C.POINTER(_VP), C.POINTER(_D), _I32, _I64, _VP, _VP]),
     "lh_mass_apply_v": (_I32, [_VP, _VP, _VP, _VP]),
     "lh_mass_apply_e": (_I32, [_VP, _VP, _VP, _VP]),
     "lh_windows_by_samples": (_I32, [_I32, C.POINTER(C.POINTER(_D)), C.POINTER(_I32), _I32, C.POINTER(_D), _I32,
@@ -296,6 +298,29 @@ def rom_build_basis(S, energy_frac=0.9999, n_fixed=0, n_max=0):
     _check(lib.rom_build_basis(ptr(S), N, m, N, float(energy_frac), int(n_fixed), int(n_cap), ptr(Phi), N,
                                ptr(sigma), C.byref(n_out), ptr(ws), ws.numel(), stream_handle()))
     return Phi[: n_out.value], sigma, n_out.value
+
+
+def idw_weights(params, mu, r=2.0):
+    """Weights of eq. interpolate_os (lh_idw_weights); params: K training parameters (scalars or
+    d-vectors), mu: the parameter to interpolate at."""
+    import numpy as np
+
+    P = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(len(params), -1))
+    m = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1))
+    K, d = P.shape
+    w = (_D * K)()
+    _check(load().lh_idw_weights(P.ctypes.data_as(C.POINTER(_D)), K, d, m.ctypes.data_as(C.POINTER(_D)),
+                                 float(r), w))
+    return list(w)
+
+
+def weighted_sum(xs, w):
+    """sum_k w[k] xs[k] of equal-length device vectors (lh_weighted_sum)."""
+    out = torch.empty_like(xs[0])
+    ptrs = (_VP * len(xs))(*[x.data_ptr() for x in xs])
+    ws = (_D * len(xs))(*[float(v) for v in w])
+    _check(load().lh_weighted_sum(ptrs, ws, len(xs), int(xs[0].numel()), ptr(out), stream_handle()))
+    return out
 
 
 def rom_sample_qdeim(U, n_s):

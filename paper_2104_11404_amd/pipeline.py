@@ -56,28 +56,41 @@ def fom_trajectory(P: lib.Problem, t_final: float, fixed_dt: float = 0.0, max_st
 
 def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_frac=0.9999, n_fixed=(), n_max=64,
                   lam=(2.0, 2.0), t_final=None, verbose=False, snapshot_offsets=None, sampler="deim",
-                  window_ic="orthogonal"):
+                  window_ic="orthogonal", window_offsets="initial"):
     """Per-window POD, SNS and DEIM (greedy, or Q-DEIM with sampler="qdeim") on the GPU; returns a lib.Rom
     instance description.
 
-    Snapshots are taken relative to each trajectory's own initial state, or to snapshot_offsets
-    (one (x, v, e) for every trajectory) when given.
+    Offsets (Sec. 4.5): with window_offsets="initial", snapshots are taken relative to each
+    trajectory's own initial state, or to snapshot_offsets (one (x, v, e) for every trajectory) when
+    given; with "window_start", window w's snapshots of each trajectory are taken relative to that
+    trajectory's state at the window's start (the step state that closed window w - 1).  The offsets
+    used are returned as train_offsets[w][k].  online_offsets: one (x, v, e) for every window, or one
+    per window (see interpolated_instance).
     """
+    if window_offsets not in ("initial", "window_start"):
+        raise ValueError(window_offsets)
     so = lib.load()
     stream = lib.stream_handle()
     sizes = (P.NV, P.NV, P.NE)
     cols = [window_columns(tr["t"], T) for tr in trajs]
-    windows = []
+    windows, train_offsets = [], []
     for w, Tw in enumerate(T):
         m_tot = sum(c[1][w] for c in cols)
         phis, dims = [], []
+        offs = []
+        for tr, (first, ncol) in zip(trajs, cols):
+            if window_offsets == "window_start" and w > 0:
+                offs.append(tuple(tr["snaps"][f][first[w]] for f in range(3)))  # the window's first column
+            else:
+                offs.append(tuple(tr["y0"]) if snapshot_offsets is None else tuple(snapshot_offsets))
+        train_offsets.append(offs)
         for f in range(3):
             N = sizes[f]
             S = torch.empty((m_tot, N), dtype=torch.float64, device="cuda")
             off = 0
-            for tr, (first, ncol) in zip(trajs, cols):
+            for k, (tr, (first, ncol)) in enumerate(zip(trajs, cols)):
                 snaps = tr["snaps"][f]
-                os_ = tr["y0"][f] if snapshot_offsets is None else snapshot_offsets[f]
+                os_ = offs[k][f]
                 lib._check(so.lh_snapshot_deviation(lib.ptr(snaps[first[w]:first[w] + ncol[w]]) if ncol[w] else
                                                     lib.ptr(snaps), N, ncol[w], N, lib.ptr(os_),
                                                     C.c_void_p(S.data_ptr() + 8 * off * N), N, stream))
@@ -98,8 +111,23 @@ def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_f
             lib._check(so.lh_mass_apply_e(P.h, lib.ptr(phis[2][k]), lib.ptr(PFtv[k]), stream))
         z1, a1 = lib.rom_sample_deim(PF1, int(round(lam[0] * dims[1])), method=sampler)
         z2, a2 = lib.rom_sample_deim(PFtv, int(round(lam[1] * dims[2])), method=sampler)
-        windows.append(dict(t_end=Tw, phi=phis, os=list(online_offsets), z1=z1, z2=z2, a1=a1, a2=a2))
-    return dict(t_final=t_final if t_final is not None else T[-1], windows=windows, window_ic=window_ic)
+        os_on = online_offsets[w] if isinstance(online_offsets, list) else online_offsets
+        windows.append(dict(t_end=Tw, phi=phis, os=list(os_on), z1=z1, z2=z2, a1=a1, a2=a2))
+    return dict(t_final=t_final if t_final is not None else T[-1], windows=windows, window_ic=window_ic,
+                train_offsets=train_offsets)
+
+
+def interpolated_instance(inst: dict, params, mu, r: float = 2.0) -> dict:
+    """The instance description for the parameter mu with the offsets of eq. interpolate_os: window w's
+    offset is the inverse-distance-weighted combination (power r) of its training offsets
+    inst["train_offsets"][w][k] at the training parameters params[k].  Bases, samples and operators
+    are shared with inst."""
+    wts = lib.idw_weights(params, mu, r)
+    wins = []
+    for wd, offs in zip(inst["windows"], inst["train_offsets"]):
+        os_mu = [lib.weighted_sum([o[f] for o in offs], wts) for f in range(3)]
+        wins.append(dict(wd, os=os_mu))
+    return dict(inst, windows=wins)
 
 
 def build_batch(wl, lam=(2.0, 2.0), energy_frac=0.9999, verbose=False):

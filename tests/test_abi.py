@@ -111,3 +111,13 @@ def test_window_logic_rejects_bad_arguments(so_path):
 
     with pytest.raises(lib.LagromError):
         pipeline.windows_by_samples([[0.0, 1.0, 2.0]], 1)
+
+
+def test_idw_weights_of_the_library_match_the_oracle():
+    """lh_idw_weights (host only) against the oracle's eq. interpolate_os weights."""
+    from oracle import rom as R
+    from paper_2104_11404_amd import lib
+    for params, mu in (([0.8, 1.0, 1.2], 0.9), ([0.8, 1.0, 1.2], 1.2), ([0.8, 1.0, 1.2], 1.37),
+                       ([[0.0, 0.0], [2.0, 0.0], [0.5, 1.5]], [1.0, 3.0])):
+        for r in (1.0, 2.0, 3.5):
+            np.testing.assert_allclose(lib.idw_weights(params, mu, r), R.idw_weights(params, mu, r), rtol=1e-14)

@@ -12,7 +12,7 @@ import workloads as W
 from oracle import fom as F
 from oracle import rom as R
 from oracle.problems import initial_state
-from oracle.windows import snapshot_matrices, windows_by_samples
+from oracle.windows import snapshot_matrices, window_start_states, windows_by_samples
 from tests.oracle_adapter import oracle_problem
 
 pytestmark = pytest.mark.gpu
@@ -330,3 +330,52 @@ def test_rom_oblique_window_initial_condition_matches_oracle(gpu_lib, sedov_wind
         assert st.n_steps == len(run.dt) and st.n_rejected == run.rejections and st.w == run.w
         for a, b in zip(G.coords(i), run.yhat):
             assert rel(a, b) < 1e-9, i
+
+
+def test_rom_with_interpolated_window_offsets_matches_oracle(gpu_lib):
+    """Parametric Sedov 8 x 8, energies 0.25 mu at mu = 0.8 and 1.2, three windows with window-start
+    offsets; the ROM at mu = 1.0 uses the offsets of eq. interpolate_os and starts from its own initial
+    state.  GPU against the oracle through the windows; lh_weighted_sum against numpy."""
+    from paper_2104_11404_amd import lib, pipeline
+    wl = W.sedov2d(8, t_final=0.15)
+    params, mu = [0.8, 1.2], 1.0
+    ops = [F.build_operator(oracle_problem(wl, energy=0.25 * p)) for p in params]
+    trs = [F.run_fom(o, wl.t_final) for o in ops]
+    y0s = [initial_state(o.prob) for o in ops]
+    T = windows_by_samples([tr.t for tr in trs], 2 * int(np.ceil(max(len(tr.dt) for tr in trs) / 3)))
+    starts = [window_start_states(tr, y0, T) for tr, y0 in zip(trs, y0s)]
+    train = [[starts[k][w] for k in range(len(params))] for w in range(len(T))]
+    online = R.interpolated_offsets(train, params, mu)
+    op_mu = F.build_operator(oracle_problem(wl, energy=0.25 * mu))
+    y0_mu = initial_state(op_mu.prob)
+    rom = R.build_rom(op_mu, trs, y0s, T, energy_frac=0.9999, n_max=24, lam=(3, 3), window_offsets="window_start",
+                      online_offsets=online)
+    run = R.run_rom(op_mu, rom, y0_mu, wl.t_final)
+    print(f"[case] rom interpolated offsets, {len(T)} windows, {len(run.dt)} steps", flush=True)
+    P = lib.Problem.from_workload(wl, energy=0.25 * mu)
+    G = lib.Rom(P, [gpu_instance(rom, wl.t_final)])
+    G.init_state(_t(y0_mu[0]), _t(y0_mu[1]), _t(y0_mu[2]))
+    G.step()
+    st = G.states()[0]
+    assert st.status == 0 and st.done == 1
+    assert st.n_steps == len(run.dt) and st.n_rejected == run.rejections and st.w == run.w
+    for a, b in zip(G.coords(0), run.yhat):
+        assert rel(a, b) < 1e-9
+    # the device combination of the offsets
+    wts = lib.idw_weights(params, mu)
+    for f in range(3):
+        got = lib.weighted_sum([_t(train[2][k][f]) for k in range(2)], wts).cpu().numpy()
+        np.testing.assert_allclose(got, online[2][f], rtol=1e-14, atol=1e-14 * np.abs(online[2][f]).max())
+    # the GPU offline chain with window-start offsets and an interpolated instance runs to t_final
+    Ps = [lib.Problem.from_workload(wl, energy=0.25 * p) for p in params]
+    gtr = [pipeline.fom_trajectory(Pk, wl.t_final) for Pk in Ps]
+    inst = pipeline.build_offline(P, gtr, T, gtr[0]["y0"], energy_frac=0.9999, n_max=24, lam=(3, 3),
+                                  t_final=wl.t_final, window_offsets="window_start")
+    for w in range(1, len(T)):
+        for k in range(2):
+            assert rel(inst["train_offsets"][w][k][1].cpu().numpy(), train[w][k][1]) < 1e-10
+    G2 = lib.Rom(P, [pipeline.interpolated_instance(inst, params, mu)])
+    x0, v0, e0 = P.initial_state()
+    G2.init_state(x0, v0, e0)
+    G2.step()
+    assert G2.states()[0].status == 0 and G2.states()[0].done == 1
