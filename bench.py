@@ -522,6 +522,75 @@ def sedov3d_batch(lib, pipeline, n_inst: int = 64, n_err: int = 8, reps: int = 2
     return out
 
 
+def param_sedov(lib, pipeline, mus=(0.7, 0.8, 0.9, 1.0, 1.1, 1.2, 1.3), n_sample=20, lam=(6.0, 6.0), verbose=True):
+    """The paper's parametric Sedov study on the 2D 64 x 64 problem: deposited energy 0.25 mu, FOM
+    snapshots at mu = 0.8, 1.0, 1.2, windows of n_sample snapshots, and a ROM at each mu with the
+    offsets of the initial states (each instance's own, every window) or with the offsets of eq.
+    interpolate_os (window-start training offsets interpolated at mu).  Both choices run as one batch
+    each; errors against each mu's own FOM.  Hyper-reduced with lambda (the paper's comparison is
+    without hyper-reduction)."""
+    import torch
+
+    import workloads as Wl
+
+    wl = Wl.sedov2d()
+    params = [0.8, 1.0, 1.2]
+    t0 = time.perf_counter()
+    trajs = [pipeline.fom_trajectory(lib.Problem.from_workload(wl, energy=0.25 * p), wl.t_final) for p in params]
+    T = pipeline.windows_by_samples([tr["t"] for tr in trajs], n_sample)
+    P = lib.Problem.from_workload(wl)
+    finals, y0s = [], []
+    for mu in mus:
+        Pm = lib.Problem.from_workload(wl, energy=0.25 * mu)
+        x, v, e = Pm.initial_state()
+        y0s.append((x.clone(), v.clone(), e.clone()))
+        Pm.fom_run(x, v, e, wl.t_final, record=False)
+        finals.append((x, v, e))
+    out = {"workload": f"sedov2d_64x64_param_energy0.25mu_train0.8-1.0-1.2_nsample{n_sample}_lambda{lam[0]:g}",
+           "windows": len(T), "mu": list(mus), "fom_s": time.perf_counter() - t0}
+    stream = torch.cuda.current_stream()
+    for choice in ("initial", "interpolate"):
+        t1 = time.perf_counter()
+        if choice == "initial":
+            base = pipeline.build_offline(P, trajs, T, trajs[1]["y0"], energy_frac=wl.energy_frac, n_max=64, lam=lam,
+                                          t_final=wl.t_final)
+            insts = [dict(base, windows=[dict(wd, os=list(y0)) for wd in base["windows"]]) for y0 in y0s]
+        else:
+            base = pipeline.build_offline(P, trajs, T, trajs[1]["y0"], energy_frac=wl.energy_frac, n_max=64, lam=lam,
+                                          t_final=wl.t_final, window_offsets="window_start")
+            insts = [pipeline.interpolated_instance(base, params, mu) for mu in mus]
+        torch.cuda.synchronize()
+        t_off = time.perf_counter() - t1
+        rom = lib.Rom(P, insts)
+        y0 = [torch.cat([y[f] for y in y0s]) for f in range(3)]
+        rom.init_state(*y0)
+        g, _ = rom.autotune(trial_steps=100)
+        rom.init_state(*y0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        rom.step()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        sts = rom.states()
+        per_mu = []
+        for i, mu in enumerate(mus):
+            st = sts[i]
+            rec = {"mu": mu, "status": st.status, "t": st.t, "steps": st.n_steps}
+            if st.status == 0 and st.done == 1:
+                rec["rel_error_vs_fom"] = dict(zip("xve", [float(torch.linalg.norm(a_ - b_) / torch.linalg.norm(b_))
+                                                          for a_, b_ in zip(rom.lift(i), finals[i])]))
+            per_mu.append(rec)
+        out[choice] = {"offline_s": t_off, "workgroups": g, "ms_per_launch": ms,
+                       "rom_steps_per_s": sum(st.n_steps for st in sts) / (ms / 1e3), "per_mu": per_mu}
+        if verbose:
+            print(f"[bench] param sedov {choice}: {ms:.1f} ms, " + ", ".join(
+                f"{r['mu']}: {r.get('rel_error_vs_fom', {}).get('v', float('nan')):.2e}" for r in per_mu),
+                  file=sys.stderr, flush=True)
+        del rom, insts, base
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -537,6 +606,8 @@ def main():
     ap.add_argument("--no-surrogate-3d", action="store_true", help="skip the 3D surrogate against DEIM measurement")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the headline's cold-cache, FP32-lift and FOM speed-up runs (profiling runs)")
+    ap.add_argument("--param-sedov", action="store_true",
+                    help="also run the parametric 2D Sedov study of offset choices (about a minute of set-up)")
     ap.add_argument("--sedov3d", action="store_true",
                     help="also run the 64-instance 3D Sedov batch on shared bases (several minutes of set-up)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -693,6 +764,8 @@ def main():
                                                           f"{v.get('rel_error_vs_fom')}"
                                                           for k, v in out["offline_variants"].items()),
               file=sys.stderr, flush=True)
+    if args.param_sedov:
+        out["param_sedov"] = param_sedov(lib, pipeline)
     if args.sedov3d:
         out["sedov3d_batch"] = sedov3d_batch(lib, pipeline)
     if not args.no_cpu_baseline:
