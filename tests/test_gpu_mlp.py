@@ -248,3 +248,27 @@ def test_trained_network_gains_over_untrained_and_over_deim_work(gpu_lib):
     # normalisation fitted, predicts the mean force): measured 2.9x (v) and 1.4x (e)
     assert e_tr[1] < 0.5 * e_un[1] and e_tr[2] < e_un[2]
     assert ev_tr <= 0.15 * ev_deim
+
+
+@pytest.mark.parametrize("sizes,batch", [([7, 16, 16, 16, 16, 16, 16, 16, 5], 1), ([3, 9, 2], 1), ([5, 33, 4], 65)],
+                         ids=["8-layers-batch-1", "one-hidden-batch-1", "ragged-batch-65"])
+def test_network_limits_layer_by_layer(gpu_lib, sizes, batch):
+    """The most layers the library takes (8), a batch of one sample and ragged tiles: every layer
+    from the GPU's own input to it, and the gradients of a one-sample batch."""
+    from paper_2104_11404_amd import lib
+    print(f"[case] mlp limits {sizes} batch {batch}", flush=True)
+    assert len(sizes) - 1 <= lib.LH_MLP_MAX_LAYERS
+    net = make_net(sizes, 31, scale=0.5)
+    X = W.rng(32).normal(0, 1, (batch, sizes[0]))
+    m = gpu_net(net, max(batch, 2))
+    Y, tr = m.forward(_t(X), trace=True)
+    tr = [t.cpu().numpy().astype(np.float64) for t in tr]
+    for l in range(len(net.W)):
+        z = M.bf16(tr[l]) @ M.bf16(net.W[l]) + net.b[l]
+        ref = np.tanh(z) if l < len(net.W) - 1 else z
+        assert nrel(tr[l + 1], ref) < 1e-5, l
+    T = W.rng(33).normal(0, 1, (batch, sizes[-1]))
+    gW, gb, loss = m.gradients(_t(X), _t(T))
+    oW, ob = M.backward(net, X, T)
+    assert nrel(gW[-1].cpu().numpy(), oW[-1]) < 2e-2
+    assert nrel(gb[-1].cpu().numpy(), ob[-1]) < 2e-2

@@ -158,3 +158,46 @@ def test_rom3d_sedov_full_run_ten_windows(gpu_lib):
         assert st.n_steps == len(run.dt) and st.n_rejected == run.rejections and st.w == run.w
         for a, b in zip(Gr.coords(0), run.yhat):
             assert rel(a, b) < 1e-9
+
+
+def test_rom3d_batch_of_uneven_instances(gpu_lib, tg3):
+    """Hexahedral instances with different dimensions and window counts in one launch, each against
+    its own oracle run (fixed steps)."""
+    from paper_2104_11404_amd import lib
+    wl, op, tr, y0, _ = tg3
+    specs = [((5, 5, 5), 1), ((3, 6, 4), 2), ((6, 4, 2), 3)]
+    roms, runs = [], []
+    for dims, nw in specs:
+        T = windows_by_samples([tr.t], 2 * int(np.ceil(len(tr.dt) / nw)))
+        rom = R.build_rom(op, [tr], [y0], T, n_fixed=dims, lam=(2, 2))
+        roms.append(rom)
+        runs.append(R.run_rom(op, rom, y0, wl.t_final, fixed_dt=2e-4))
+    print(f"[case] rom 3d batch, windows {[len(r.windows) for r in roms]}", flush=True)
+    P, G = _gpu_rom(wl, [(r, wl.t_final) for r in roms], [y0] * len(roms), dt0=2e-4)
+    G.step(flags=lib.LH_FIXED_DT)
+    for i, run in enumerate(runs):
+        st = G.states()[i]
+        assert st.status == 0 and st.done == 1 and st.n_steps == len(run.dt) and st.w == run.w
+        for a, b in zip(G.coords(i), run.yhat):
+            assert rel(a, b) < 1e-10, i
+
+
+def test_surrogate_with_fp32_lift_keeps_its_audits(gpu_lib, tg3):
+    """LH_SURROGATE with LH_FP32_LIFT on hexahedra: the same audits and surrogate steps as the oracle's
+    FP64 surrogate run, reduced state within the bfloat16 bound."""
+    from paper_2104_11404_amd import lib
+    from tests.test_gpu_mlp import gpu_net
+    wl, op, tr, y0, rom = tg3
+    X, T = M.training_set(op, rom, 0, [tr], [[0] * len(tr.snaps)])
+    net = _net3d(rom, X, T, 63)
+    run = M.run_surrogate(op, rom, {0: net}, y0, wl.t_final, audit_every=5, tol=10.0, fixed_dt=2e-4)
+    print(f"[case] surrogate 3d with fp32 lift: {run.audits} audits", flush=True)
+    P = lib.Problem.from_workload(wl)
+    G = lib.Rom(P, [gpu_instance(rom, wl.t_final)])
+    G.attach_surrogate(0, 0, gpu_net(net, 16), audit_every=5, tol=10.0)
+    G.init_state(_t(y0[0]), _t(y0[1]), _t(y0[2]), 2e-4)
+    G.step(flags=lib.LH_SURROGATE | lib.LH_FIXED_DT | lib.LH_FP32_LIFT)
+    st = G.states()[0]
+    assert st.status == 0 and st.n_audits == run.audits and st.n_surrogate_steps == run.surrogate_steps
+    for a, b in zip(G.coords(0), run.yhat):
+        assert rel(a, b) < 1e-3
