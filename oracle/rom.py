@@ -24,7 +24,7 @@ The relative error at the final time is the Euclidean one of eq. relerrors.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -229,6 +229,7 @@ class ROMRun:
     yhat: tuple
     rejections: int = 0
     window_of_step: list = field(default_factory=list)
+    os: tuple = None  # offsets in use at the end (offsets="previous" changes them at every switch)
 
 
 def initial_coords(rom: ROM, y0: tuple):
@@ -255,13 +256,27 @@ def reached(t: float, T_end: float) -> bool:
     return t >= T_end * (1.0 - SWITCH_RTOL)
 
 
+def with_offsets(win: WindowROM, os: tuple) -> WindowROM:
+    """The window with other offsets: its offset-dependent operator b_x = Phi_x^T v_os follows."""
+    return replace(win, os=[np.asarray(o) for o in os], bx=win.Phi[0].T @ np.asarray(os[1]))
+
+
 def run_rom(op: F.Operator, rom: ROM, y0: tuple, t_final: float, dt_replay=None, fixed_dt=None,
-            max_steps=10**7) -> ROMRun:
-    """Online phase from t = 0 to t_final (same step control as the FOM)."""
+            max_steps=10**7, offsets="given") -> ROMRun:
+    """Online phase from t = 0 to t_final (same step control as the FOM).
+
+    offsets="given": every window uses the offsets it was built with and the reduced state moves to
+    the next window by eq. ic-tw (or ic2-tw).  offsets="previous" (eq. previous_os): the first window
+    uses its own offsets; at each switch the ROM's state lifted with the closing window becomes the
+    next window's offset, so the reduced state restarts at zero.  run.os holds the offsets in use at
+    the end."""
+    if offsets not in ("given", "previous"):
+        raise ValueError(offsets)
     w = 0
     yhat = initial_coords(rom, y0)
     t = 0.0
     run = ROMRun([0.0], [], 0, yhat)
+    cur = rom.windows[0]
     if fixed_dt is not None:
         dt = fixed_dt
     elif dt_replay is None:
@@ -273,7 +288,7 @@ def run_rom(op: F.Operator, rom: ROM, y0: tuple, t_final: float, dt_replay=None,
     n = 0
     while (F.not_done(t, t_final) if dt_replay is None else n < len(dt_replay)) and n < max_steps:
         h = dt_replay[n] if dt_replay is not None else F.final_step_clip(t, t_final, dt)
-        new, _, tau = rom_step(op, rom.windows[w], *yhat, h)
+        new, _, tau = rom_step(op, cur, *yhat, h)
         if fixed_dt is None and dt_replay is None:
             if h >= tau:
                 dt = F.BETA1 * h
@@ -288,14 +303,24 @@ def run_rom(op: F.Operator, rom: ROM, y0: tuple, t_final: float, dt_replay=None,
         run.window_of_step.append(w)
         while w + 1 < len(rom.windows) and reached(t, rom.windows[w].T_end):
             w += 1
-            yhat = switch_window(rom, w, yhat)
+            if offsets == "previous":
+                lifted = tuple(lift_full(cur, f, yhat[f]) for f in range(3))
+                cur = with_offsets(rom.windows[w], lifted)
+                yhat = tuple(np.zeros(n) for n in cur.dims)
+            else:
+                yhat = switch_window(rom, w, yhat)
+                cur = rom.windows[w]
     run.w = w
     run.yhat = yhat
+    run.os = tuple(np.asarray(o) for o in cur.os)
     return run
 
 
 def final_lift(rom: ROM, run: ROMRun):
     win = rom.windows[run.w]
+    os = getattr(run, "os", None)
+    if os is not None:
+        win = replace(win, os=list(os))
     return tuple(lift_full(win, f, run.yhat[f]) for f in range(3))
 
 

@@ -375,3 +375,26 @@ def test_window_start_offsets_are_the_trajectory_states_at_window_starts():
     for w in range(3):
         for f in range(3):
             np.testing.assert_array_equal(rom.windows[w].os[f], starts[w][f])
+
+
+def test_previous_window_offsets_retrace_the_fom_with_full_bases(tg_fom):
+    """eq. previous_os: with window-start training offsets, bases of full rank in every window and
+    full sampling, the ROM whose next offset is its own lifted state at each switch retraces the FOM
+    through several windows (the lifted state at a switch is the FOM state, which is the training
+    offset the next window was built around); the reduced state restarts at zero at every switch."""
+    wl, op, tr, y0 = tg_fom
+    T = windows_by_samples([tr.t], 2 * int(np.ceil(len(tr.dt) / 3)))
+    assert len(T) == 3
+    starts = window_start_states(tr, y0, T)
+    mats = snapshot_matrices([tr], [y0], T, offsets_by_window=[[s] for s in starts])
+    ranks = [max(int(np.sum(np.linalg.svd(S, compute_uv=False) > 1e-11 * np.linalg.norm(S, 2))), 1)
+             for S in mats[0]]
+    rom = R.build_rom(op, [tr], [y0], T, n_fixed=ranks, lam=(1e9, 1e9), window_offsets="window_start",
+                      online_offsets=starts)
+    run = R.run_rom(op, rom, y0, wl.t_final, dt_replay=tr.dt, offsets="previous")
+    assert run.w == 2
+    err = R.relative_errors((tr.x, tr.v, tr.e), R.final_lift(rom, run))
+    assert max(err) < 1e-9, err
+    # the offsets in use at the end are the ROM's own lifted state at the last switch, i.e. the FOM's
+    for f in range(3):
+        np.testing.assert_allclose(run.os[f], starts[2][f], rtol=1e-9, atol=1e-12)
