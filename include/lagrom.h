@@ -238,6 +238,7 @@ typedef struct {
 } lh_window_desc;
 
 enum { LH_WINDOW_IC_ORTHOGONAL = 0, LH_WINDOW_IC_OBLIQUE = 1 };
+enum { LH_OFFSETS_GIVEN = 0, LH_OFFSETS_PREVIOUS = 1 };
 
 typedef struct {
     int32_t n_windows;
@@ -247,7 +248,10 @@ typedef struct {
                                       LH_WINDOW_IC_ORTHOGONAL, eq. ic-tw; LH_WINDOW_IC_OBLIQUE,
                                       eq. ic2-tw (velocity and energy projected in the M_V and M_E
                                       inner products, position as in eq. ic-tw) */
-    int32_t reserved_;
+    int32_t offsets;               /* LH_OFFSETS_GIVEN: every window uses the offsets of its
+                                      description; LH_OFFSETS_PREVIOUS (eq. previous_os): the
+                                      first window's offsets, then at each switch the lifted state
+                                      (rom_switch_window_previous) */
 } lh_instance_desc;
 
 #define LH_NMAX 64
@@ -311,7 +315,10 @@ int rom_init_state(const lh_rom* r, const lh_instance_desc* inst, const double* 
  * does not arrive within a bounded wait sets LH_FLAG_TIMEOUT.  flags: LH_REPLAY_DT uses dt_replay (dev, n_replay steps,
  * shared by all instances), LH_FIXED_DT keeps state.dt fixed,
  * LH_FP32_LIFT lifts and projects in FP32 (FP64 accumulation of the
- * reduced state).  Asynchronous. */
+ * reduced state).  An instance created with LH_OFFSETS_PREVIOUS stops when
+ * it reaches the end of a window that has a successor (done stays 0, the
+ * state keeps the closing window) and waits for
+ * rom_switch_window_previous.  Asynchronous. */
 int rom_step(const lh_rom* r, lh_rom_state* state, int32_t max_steps, uint32_t flags, const double* dt_replay,
              int32_t n_replay, hipStream_t stream);
 
@@ -319,9 +326,22 @@ int rom_step(const lh_rom* r, lh_rom_state* state, int32_t max_steps, uint32_t f
  * device state, so the call synchronises): y = os_w + Phi_w y^
  * (eq. solrepresentation-tw).  inst_desc (host) is the description that was
  * passed to rom_create for this instance; its bases and offsets must still
- * be alive.  Outputs x, v (N_V, dev) and e (N_E, dev). */
+ * be alive.  With LH_OFFSETS_PREVIOUS the offsets are the instance's current
+ * ones.  Outputs x, v (N_V, dev) and e (N_E, dev). */
 int rom_lift(const lh_rom* r, const lh_rom_state* state, int32_t inst, const lh_instance_desc* inst_desc,
              double* x, double* v, double* e, hipStream_t stream);
+
+/* Window switch with the previous-window offsets (Sec. 4.5,
+ * eq. previous_os) for an instance created with LH_OFFSETS_PREVIOUS that
+ * rom_step has stopped at the end of window w: its offsets
+ * become its lifted state os_w + Phi_w y^_w (a full-size lift, kept in the
+ * instance's own buffers), window w + 1's offset rows and b_x = Phi_x^T v_os
+ * are rebuilt from them, and the state moves to window w + 1 with
+ * y^ = 0.  inst_desc (host) is the description passed to rom_create; its
+ * bases must still be alive.  LH_EINVAL if the instance does not use
+ * previous-window offsets or is not stopped at a window end.  Synchronises. */
+int rom_switch_window_previous(lh_rom* r, lh_rom_state* state, int32_t inst, const lh_instance_desc* inst_desc,
+                               hipStream_t stream);
 
 /* Number of sampled elements of (instance, window) (host query). */
 int rom_sampled_elements(const lh_rom* r, int32_t inst, int32_t window, int32_t* n_elems);

@@ -88,6 +88,7 @@ struct InstDev {
     double* part;  // [2][G][PSTRIDE] shares exchanged after every pass
     int* flag;     // [G] sequence number of the last share each workgroup published
     double* sig;   // [max n_el][NQ][D*D] kept stress when it is not resident
+    int prev_os;   // offsets of the previous window (eq. previous_os): stop at a window end, the host switches
 };
 
 struct RomArgs {
@@ -715,6 +716,9 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
     }
     int accepted = 0;
     while (!done && accepted < A.max_steps) {
+        // with previous-window offsets the next window's offsets are the lifted state, which the
+        // host forms between launches: stop here (t and w agree in every workgroup of the instance)
+        if (I.prev_os && w + 1 < I.n_windows && t >= I.win[w].t_end * (1.0 - 1e-12)) break;
         const WinDev& W = I.win[w];
         const WgView& V = W.views[g];
         double h;
@@ -833,7 +837,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         bool moved = false;
         // a window ends at T_w; a time within 1e-12 relative below T_w has reached it (window
         // ends chosen by snapshot count are FOM step times, met by the ROM up to rounding)
-        while (w + 1 < I.n_windows && t >= I.win[w].t_end * (1.0 - 1e-12)) {
+        while (!I.prev_os && w + 1 < I.n_windows && t >= I.win[w].t_end * (1.0 - 1e-12)) {
             const WinDev& Wn = I.win[w + 1];
             const WinDev& Wo = I.win[w];
             for (int f = 0; f < 3; ++f) {
@@ -1080,6 +1084,15 @@ struct HostWin {
     std::vector<std::vector<std::pair<int, int>>> contrib;  // per sampled kinematic row: (slot, dof)
     std::vector<int> own_slot;                              // owner index -> closure slot
     std::vector<std::pair<int, int>> th;                    // per sampled energy row: (owner index, local dof)
+    const int64_t* growk = nullptr;  // (dev) global row of every element-local kinematic / energy entry
+    const int64_t* growt = nullptr;
+};
+
+// Offsets of an instance that takes them from the previous window (eq. previous_os).
+struct PrevOs {
+    double* os = nullptr;                         // [2 N_V + N_E] x, v, e offsets in use
+    double* os_loc[3] = {nullptr, nullptr, nullptr};  // [max n_el][rows_f] element-local rows of the current window
+    double* bx = nullptr;                         // [LH_NMAX] Phi_x^T v_os of the current window
 };
 
 }  // namespace rom
@@ -1101,6 +1114,7 @@ struct lh_rom {
     std::vector<lh::rom::InstDev> h_inst;
     std::vector<std::vector<lh::rom::WinDev>> h_win;
     std::vector<std::vector<lh::rom::HostWin>> h_struct;
+    std::vector<lh::rom::PrevOs> prev;  // per instance; os == nullptr: offsets as given
 };
 
 namespace lh {
@@ -1232,6 +1246,8 @@ static int build_window(lh_rom* R, const lh_problem* p, const lh_window_desc& wd
     const int64_t* d_growt;
     if ((rc = upload(R, growk, &d_growk))) return rc;
     if ((rc = upload(R, growt, &d_growt))) return rc;
+    H.growk = d_growk;
+    H.growt = d_growt;
     for (int f = 0; f < 3; ++f) {
         const int rows = f == 2 ? NT : NKD;
         const int64_t* grow = f == 2 ? d_growt : d_growk;
@@ -1504,6 +1520,7 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
     R->h_inst.resize(n_inst);
     R->h_win.resize(n_inst);
     R->h_struct.resize(n_inst);
+    R->prev.resize(n_inst);
     const int dim = p->dim;
     const int NQ = dim == 3 ? 64 : 16;
     auto fail = [&](int rc) {
@@ -1520,6 +1537,10 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
         }
         if (d.window_ic != LH_WINDOW_IC_ORTHOGONAL && d.window_ic != LH_WINDOW_IC_OBLIQUE) {
             set_error("rom_create: window_ic must be LH_WINDOW_IC_ORTHOGONAL or LH_WINDOW_IC_OBLIQUE");
+            return fail(LH_EINVAL);
+        }
+        if (d.offsets != LH_OFFSETS_GIVEN && d.offsets != LH_OFFSETS_PREVIOUS) {
+            set_error("rom_create: offsets must be LH_OFFSETS_GIVEN or LH_OFFSETS_PREVIOUS");
             return fail(LH_EINVAL);
         }
         for (int j = 0; j < i && R->alias[i] < 0; ++j)
@@ -1573,6 +1594,15 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
             (rc = dev_alloc(R, &I.part, (int64_t)2 * MAX_G * PSTRIDE)) || (rc = dev_alloc(R, &I.flag, MAX_G)))
             return fail(rc);
         hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, I.flag, (int64_t)MAX_G);
+        I.prev_os = inst[i].offsets == LH_OFFSETS_PREVIOUS;
+        if (I.prev_os) {
+            PrevOs& P = R->prev[i];
+            const int NKD = dim * (dim == 2 ? 9 : 27), NT = dim == 2 ? 4 : 8;
+            if ((rc = dev_alloc(R, &P.os, 2 * p->NV + p->NE)) || (rc = dev_alloc(R, &P.bx, LH_NMAX)))
+                return fail(rc);
+            for (int f = 0; f < 3; ++f)
+                if ((rc = dev_alloc(R, &P.os_loc[f], (int64_t)ie * (f == 2 ? NT : NKD)))) return fail(rc);
+        }
         const WinDev* dw;
         if ((rc = upload(R, R->h_win[i], &dw))) return fail(rc);
         I.win = dw;
@@ -1614,6 +1644,9 @@ int rom_init_state(const lh_rom* R, const lh_instance_desc* inst, const double* 
             double* dst = reinterpret_cast<double*>(reinterpret_cast<char*>(state + i) + offsetof(lh_rom_state, yhat)) +
                           f * LH_NMAX;
             hipLaunchKernelGGL(init_coords_kernel, dim3(w0.n[f]), dim3(256), 0, s, w0.phi[f], N, y0[f], w0.os[f], dst);
+            if (R->prev[i].os)  // previous-window offsets start from the first window's
+                hipLaunchKernelGGL(copy_kernel, dim3(nb(N)), dim3(256), 0, s, w0.os[f],
+                                   R->prev[i].os + (f > 0 ? p->NV : 0) + (f > 1 ? p->NV : 0), N);
         }
     }
     return launch_check("rom_init_state");
@@ -1760,9 +1793,67 @@ int rom_lift(const lh_rom* R, const lh_rom_state* state, int32_t inst, const lh_
         const int64_t N = f == 2 ? p->NE : p->NV;
         const double* yh = reinterpret_cast<const double*>(reinterpret_cast<const char*>(state + inst) +
                                                            offsetof(lh_rom_state, yhat)) + f * LH_NMAX;
-        hipLaunchKernelGGL(lift_full_kernel, dim3(nb(N)), dim3(256), 0, s, W.phi[f], N, W.n[f], yh, W.os[f], out[f]);
+        const double* os = R->prev[inst].os ? R->prev[inst].os + (f > 0 ? p->NV : 0) + (f > 1 ? p->NV : 0) : W.os[f];
+        hipLaunchKernelGGL(lift_full_kernel, dim3(nb(N)), dim3(256), 0, s, W.phi[f], N, W.n[f], yh, os, out[f]);
     }
     return launch_check("rom_lift");
+}
+
+int rom_switch_window_previous(lh_rom* R, lh_rom_state* state, int32_t inst, const lh_instance_desc* d,
+                               hipStream_t s) {
+    using namespace lh;
+    using namespace lh::rom;
+    LH_REQUIRE(R && state && d, "rom_switch_window_previous: null argument");
+    LH_REQUIRE(inst >= 0 && inst < R->n_inst, "rom_switch_window_previous: instance out of range");
+    PrevOs& P = R->prev[inst];
+    LH_REQUIRE(P.os != nullptr, "rom_switch_window_previous: the instance was not created with LH_OFFSETS_PREVIOUS");
+    LH_REQUIRE(d->n_windows == (int)R->h_win[inst].size(), "rom_switch_window_previous: description differs from rom_create");
+    const lh_problem* p = R->p;
+    lh_rom_state h;
+    LH_HIP_CHECK(hipMemcpyAsync(&h, state + inst, sizeof(h), hipMemcpyDeviceToHost, s));
+    LH_HIP_CHECK(hipStreamSynchronize(s));
+    const int w = h.w;
+    LH_REQUIRE(w >= 0 && w + 1 < d->n_windows && h.t >= R->h_win[inst][w].t_end * (1.0 - 1e-12),
+               "rom_switch_window_previous: the instance is not stopped at the end of a window with a successor");
+    // os <- os + Phi_w y^_w, every row reading and writing only itself
+    const lh_window_desc& Wo = d->windows[w];
+    const lh_window_desc& Wn = d->windows[w + 1];
+    double* os[3] = {P.os, P.os + p->NV, P.os + 2 * p->NV};
+    for (int f = 0; f < 3; ++f) {
+        const int64_t N = f == 2 ? p->NE : p->NV;
+        LH_REQUIRE(Wo.n[f] == R->h_win[inst][w].n[f] && Wn.n[f] == R->h_win[inst][w + 1].n[f],
+                   "rom_switch_window_previous: description differs from rom_create");
+        const double* yh = reinterpret_cast<const double*>(reinterpret_cast<const char*>(state + inst) +
+                                                           offsetof(lh_rom_state, yhat)) + f * LH_NMAX;
+        hipLaunchKernelGGL(lift_full_kernel, dim3(nb(N)), dim3(256), 0, s, Wo.phi[f], N, Wo.n[f], yh, os[f], os[f]);
+    }
+    // window w + 1: element-local offset rows and b_x = Phi_x^T v_os from the new offsets
+    const HostWin& H = R->h_struct[R->alias[inst] >= 0 ? R->alias[inst] : inst][w + 1];
+    const int dim = p->dim;
+    const int NKD = dim * (dim == 2 ? 9 : 27), NT = dim == 2 ? 4 : 8;
+    for (int f = 0; f < 3; ++f) {
+        const int64_t cnt = (int64_t)H.n_el * (f == 2 ? NT : NKD);
+        if (cnt > 0)
+            hipLaunchKernelGGL(gather_vec_kernel, dim3(nb(cnt)), dim3(256), 0, s, os[f], f == 2 ? H.growt : H.growk,
+                               cnt, P.os_loc[f]);
+    }
+    hipLaunchKernelGGL(gemm_tn_kernel, dim3(Wn.n[0], 1), dim3(256), 0, s, Wn.phi[0], os[1], p->NV, p->NV, p->NV,
+                       Wn.n[0], P.bx);
+    WinDev& D = R->h_win[inst][w + 1];
+    for (int f = 0; f < 3; ++f) D.os_loc[f] = P.os_loc[f];
+    D.bx = P.bx;
+    // the reduced state restarts at zero in window w + 1 (surrogate bookkeeping as at any window change)
+    h.w = w + 1;
+    for (int f = 0; f < 3; ++f)
+        for (int k = 0; k < LH_NMAX; ++k) h.yhat[f][k] = 0.0;
+    h.since = 0;
+    h.fallen = 0;
+    h.tau_est = INFINITY;
+    LH_HIP_CHECK(hipStreamSynchronize(s));  // the lift has read y^ before the state is overwritten
+    LH_HIP_CHECK(hipMemcpy(const_cast<WinDev*>(R->h_inst[inst].win) + w + 1, &D, sizeof(WinDev), hipMemcpyHostToDevice));
+    LH_HIP_CHECK(hipMemcpyAsync(state + inst, &h, sizeof(h), hipMemcpyHostToDevice, s));
+    LH_HIP_CHECK(hipStreamSynchronize(s));
+    return launch_check("rom_switch_window_previous");
 }
 
 int rom_sampled_elements(const lh_rom* R, int32_t inst, int32_t window, int32_t* n_elems) {

@@ -55,7 +55,7 @@ class WindowDesc(C.Structure):
 
 class InstanceDesc(C.Structure):
     _fields_ = [("n_windows", C.c_int32), ("windows", C.POINTER(WindowDesc)), ("t_final", C.c_double),
-                ("window_ic", C.c_int32), ("reserved_", C.c_int32)]
+                ("window_ic", C.c_int32), ("offsets", C.c_int32)]
 
 
 class MlpDesc(C.Structure):
@@ -102,6 +102,7 @@ _SIGNATURES = {
     "rom_workgroups_per_instance": (_I32, [_VP, C.POINTER(_I32)]),
     "rom_set_workgroups": (_I32, [_VP, _I32, _U32, _VP]),
     "rom_device_bytes": (_I32, [_VP, C.POINTER(_I64)]),
+    "rom_switch_window_previous": (_I32, [_VP, _VP, _I32, C.POINTER(InstanceDesc), _VP]),
     "rom_autotune": (_I32, [_VP, _VP, _I32, _U32, _VP, _I32, C.POINTER(_I32), C.POINTER(C.c_float), _VP]),
     "mlp_create": (_I32, [C.POINTER(MlpDesc), _I32, C.POINTER(_VP)]),
     "mlp_destroy": (None, [_VP]),
@@ -348,7 +349,8 @@ class Rom:
     """Online ROM of one or more instances sharing a problem (rom_create / rom_step)."""
 
     def __init__(self, problem: Problem, instances: list):
-        """instances: list of dicts {t_final, windows: [window dicts]}.
+        """instances: list of dicts {t_final, windows: [window dicts]} with optional window_ic
+        ("orthogonal" | "oblique") and offsets ("given" | "previous": run with run_to_end).
 
         A window dict holds t_end, n (n_x, n_v, n_e), phi (3 tensors (n_f, N) = column-major N x n_f),
         os (3 tensors of length N), z1, z2 (int32 tensors), a1 ((n_s1, n_v) = column-major n_v x n_s1), a2.
@@ -376,6 +378,7 @@ class Rom:
             descs[i].windows = C.cast(ws, C.POINTER(WindowDesc))
             descs[i].t_final = float(inst["t_final"])
             descs[i].window_ic = {"orthogonal": 0, "oblique": 1}[inst.get("window_ic", "orthogonal")]
+            descs[i].offsets = {"given": 0, "previous": 1}[inst.get("offsets", "given")]
         self.descs = descs
         h = C.c_void_p()
         _check(lib.rom_create(problem.h, len(instances), descs, C.byref(h), stream_handle()))
@@ -430,6 +433,24 @@ class Rom:
         g = _I32()
         _check(load().rom_workgroups_per_instance(self.h, C.byref(g)))
         return g.value
+
+    def run_to_end(self, flags=0, dt_replay=None, max_launches=100000):
+        """rom_step until every instance has finished.  An instance with offsets="previous" stops at
+        each window end; it moves on through rom_switch_window_previous (eq. previous_os)."""
+        lib = load()
+        for _ in range(max_launches):
+            self.step(flags=flags, dt_replay=dt_replay)
+            moved = False
+            for i, st in enumerate(self.states()):
+                wins = self.instances[i]["windows"]
+                if (self.descs[i].offsets == 1 and st.status == 0 and st.w + 1 < len(wins)
+                        and st.t >= wins[st.w]["t_end"] * (1 - 1e-12)):
+                    _check(lib.rom_switch_window_previous(self.h, ptr(self.state), i, C.byref(self.descs[i]),
+                                                          stream_handle()))
+                    moved = True
+            if not moved:
+                return
+        raise LagromError(-1, "run_to_end: too many launches")
 
     def device_bytes(self):
         b = _I64()
