@@ -89,6 +89,7 @@ struct InstDev {
     int* flag;     // [G] sequence number of the last share each workgroup published
     double* sig;   // [max n_el][NQ][D*D] kept stress when it is not resident
     int prev_os;   // offsets of the previous window (eq. previous_os): stop at a window end, the host switches
+    int* xcc;      // [G] XCD of each workgroup in the current launch
 };
 
 struct RomArgs {
@@ -104,6 +105,7 @@ struct RomArgs {
     int n_replay;
     int nkin_max, nth_max;  // sizes of the entry-value arrays in LDS
     int mlp_floats;         // LDS scratch of the surrogate (0: no surrogate this launch)
+    int xcd_map;            // blocks placed so that an instance's workgroups share one XCD (see rom_block)
 };
 
 template <int DIM>
@@ -161,6 +163,18 @@ __device__ double block_min(double v, double* wred) {
     return r;
 }
 
+// Exchange within one XCD.  Workgroups are dispatched to the 8 XCDs
+// round-robin (block b runs on XCD b % 8), and each XCD has its own L2, which
+// is not kept coherent with the others; the device-scope release therefore
+// writes the L2 back and invalidates it.  When every workgroup of an instance
+// runs on one XCD, that L2 is where their accesses meet: a share is published
+// by waiting until its stores are acknowledged (they pass the write-through L1
+// into the L2) and then storing the sequence number.  The reads stay
+// device-scope loads, which miss the reader's L1 (a workgroup-scope load may
+// hit it: outside thread-group-split mode a workgroup's waves share one CU).
+// XCD (accelerator complex die) the calling wave runs on.
+__device__ __forceinline__ int xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15; }
+
 // Publish this workgroup's share of the current pass and wait for the other
 // G - 1 workgroups of the instance.  The share is released (device-scope
 // fence) before the workgroup's sequence number is stored; thread t < G then
@@ -170,11 +184,19 @@ __device__ double block_min(double v, double* wred) {
 // copy, so no cache invalidation is needed on the reading side.  A wait that
 // does not end within a bounded spin reports LH_FLAG_TIMEOUT, so every wave
 // exits.
-__device__ void sync_shares(int* flag, int G, int g, int target, int* status) {
+__device__ void sync_shares(int* flag, int G, int g, int target, int* status, bool local) {
+    if (local && G > 1) {
+        // this thread's share stores are in the L2 before the barrier
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_s_waitcnt(0);
+    }
     __syncthreads();
     if (G == 1) return;
     if (threadIdx.x == 0) {
-        __threadfence();
+        if (!local)
+            __threadfence();
+        else
+            asm volatile("" ::: "memory");  // compiler barrier only: keeps the schedule of the fenced path
         __hip_atomic_store(&flag[g], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if ((int)threadIdx.x < G) {
@@ -660,16 +682,31 @@ __device__ double rel_disc(const double* a, const double* b, const double* sc, i
     return v;
 }
 
+// Instance and workgroup of a block.  With xcd_map, the G workgroups of
+// instance i are the blocks 8 ((i / 8) G + g) + i % 8, g < G, which the
+// round-robin dispatch puts on one XCD; the grid then has 8 ceil(n_inst / 8) G
+// blocks and those past the last instance exit at once.
+__device__ __forceinline__ void rom_block(const RomArgs& A, int b, int* ii, int* g) {
+    if (A.xcd_map) {
+        const int s = b >> 3;
+        *ii = (s / A.G) * 8 + (b & 7);
+        *g = s % A.G;
+    } else {
+        *ii = b / A.G;
+        *g = b % A.G;
+    }
+}
+
 template <int DIM, class TT, bool RES>
 __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
     extern __shared__ double dyn_raw[];
     __shared__ NodeBuf<DIM> B;
     __shared__ Shared S;
     __shared__ lh_rom_state st;
-    __shared__ int s_status, s_base;
+    __shared__ int s_status, s_base, s_local;
     const int tid = threadIdx.x;
-    const int ii = blockIdx.x / A.G;
-    const int g = blockIdx.x % A.G;
+    int ii, g;
+    rom_block(A, blockIdx.x, &ii, &g);
     if (ii >= A.n_inst) return;
     const InstDev& I = A.inst[ii];
     double* fe = dyn_raw;
@@ -697,6 +734,23 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         n_fallbacks = st.n_fallbacks;
     const bool surrogate = (A.flags & LH_SURROGATE) != 0 && A.mlp_floats > 0;
     int phase = 0;
+    // whether every workgroup of the instance runs on one XCD; the exchanges then stay in its L2
+    bool local = false;
+    if (A.G > 1) {
+        typedef const __attribute__((address_space(1))) int gi32;
+        if (tid == 0) __hip_atomic_store(&I.xcc[g], xcc_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, false);
+        ++phase;
+        if (tid == 0) {
+            const int x0 = __hip_atomic_load((gi32*)&I.xcc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int same = (s_status & LH_FLAG_TIMEOUT) == 0;
+            for (int j = 1; j < A.G; ++j)
+                same &= __hip_atomic_load((gi32*)&I.xcc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == x0;
+            s_local = same;
+        }
+        __syncthreads();
+        local = s_local != 0;
+    }
     Local<TT> L;
     load_local<DIM, TT>(I.win[w], I.win[w].views[g], I, RES, dyn, L);
     double* const part0 = I.part + (int64_t)g * PSTRIDE;                     // my share, even phases
@@ -708,7 +762,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         const WinDev& W = I.win[w];
         pass_a<DIM, TT>(A, W, W.views[g], L, B, S, fe, S.y[0], S.y[1], S.y[2], (phase & 1) ? part1 : part0,
                         &s_status);
-        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status);
+        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
         const double tau0 = combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage);
         ++phase;
         evals += W.n_el;
@@ -767,13 +821,13 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         } else {
         // ---- stage 1 at y_n
         pass_a<DIM, TT>(A, W, V, L, B, S, fe, S.y[0], S.y[1], S.y[2], (phase & 1) ? part1 : part0, &s_status);
-        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status);
+        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
         const double tau1 = combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage);
         ++phase;
         for (int i = tid; i < W.n[1]; i += BLK) S.yh[1][i] = S.y[1][i] - 0.5 * h * S.f1h[i];
         __syncthreads();
         pass_b<DIM, TT>(A, W, V, L, B, te, S.yh[1], (phase & 1) ? part1 : part0, &s_status, S.red);
-        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status);
+        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
         combine((phase & 1) ? all1 : all0, A.G, W.n[2], S.ftvh, &s_status, S, stage);
         ++phase;
         if (audit_now) {
@@ -795,7 +849,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         __syncthreads();
         // ---- stage 2 at y_{n+1/2}
         pass_a<DIM, TT>(A, W, V, L, B, S, fe, S.yh[0], S.yh[1], S.yh[2], (phase & 1) ? part1 : part0, &s_status);
-        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status);
+        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
         const double tau2 = combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage);
         ++phase;
         for (int i = tid; i < W.n[1]; i += BLK) {
@@ -805,7 +859,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         }
         __syncthreads();
         pass_b<DIM, TT>(A, W, V, L, B, te, S.vc, (phase & 1) ? part1 : part0, &s_status, S.red);
-        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status);
+        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
         combine((phase & 1) ? all1 : all0, A.G, W.n[2], S.ftvh, &s_status, S, stage);
         ++phase;
         for (int i = tid; i < W.n[2]; i += BLK) S.yn[2][i] = S.y[2][i] + h * S.ftvh[i];
@@ -1591,7 +1645,8 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
         int ie = 0;
         for (auto& W : R->h_win[i]) ie = std::max(ie, W.n_el);
         if ((rc = dev_alloc(R, &I.sig, (int64_t)ie * NQ * dim * dim)) ||
-            (rc = dev_alloc(R, &I.part, (int64_t)2 * MAX_G * PSTRIDE)) || (rc = dev_alloc(R, &I.flag, MAX_G)))
+            (rc = dev_alloc(R, &I.part, (int64_t)2 * MAX_G * PSTRIDE)) || (rc = dev_alloc(R, &I.flag, MAX_G)) ||
+            (rc = dev_alloc(R, &I.xcc, MAX_G)))
             return fail(rc);
         hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, I.flag, (int64_t)MAX_G);
         I.prev_os = inst[i].offsets == LH_OFFSETS_PREVIOUS;
@@ -1658,12 +1713,29 @@ namespace lh {
 namespace rom {
 
 template <int DIM, class TT, bool RES>
+static int blocks_per_cu(size_t dyn, int* nb);
+
+// LAGROM_XCD_MAP=0 turns the XCD-aware placement off (the exchange then always
+// takes the device-scope path); results are bit-identical either way.
+static bool xcd_map_enabled() {
+    const char* e = std::getenv("LAGROM_XCD_MAP");
+    return !(e && e[0] == '0');
+}
+
+template <int DIM, class TT, bool RES>
 static int launch_rom(const lh_rom* R, const RomArgs& A, size_t dyn, hipStream_t s) {
     auto kern = rom_step_kernel<DIM, TT, RES>;
     if (dyn > 0) LH_HIP_CHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
     dim3 grid(R->n_inst * R->G), block(BLK);
     if (R->G > 1) {
         RomArgs a = A;
+        // keep each instance's workgroups on one XCD when the padded grid is still co-resident
+        int nb = 0;
+        const int rc = blocks_per_cu<DIM, TT, RES>(dyn, &nb);
+        if (rc) return rc;
+        const int64_t padded = 8LL * ((R->n_inst + 7) / 8) * R->G;
+        a.xcd_map = xcd_map_enabled() && padded <= (int64_t)nb * cu_count();
+        if (a.xcd_map) grid = dim3((unsigned)padded);
         void* args[] = {&a};
         LH_HIP_CHECK(hipLaunchCooperativeKernel((const void*)kern, grid, block, args, (unsigned)dyn, s));
     } else {
@@ -1772,6 +1844,7 @@ int rom_step(const lh_rom* R, lh_rom_state* state, int32_t max_steps, uint32_t f
     A.nkin_max = R->nkin_max;
     A.nth_max = R->nth_max;
     A.mlp_floats = (flags & LH_SURROGATE) ? R->mlp_floats : 0;
+    A.xcd_map = 0;  // set per launch in launch_rom
     const bool f32 = (flags & LH_FP32_LIFT) != 0;
     return p->dim == 2 ? dispatch<2>(R, A, f32, s) : dispatch<3>(R, A, f32, s);
 }

@@ -94,3 +94,32 @@ def test_set_workgroups_rejects_bad_shapes(gpu_lib, sedov3):
     st = G.states()
     for i in range(16):
         assert st[i].status == 0 and st[i].n_steps == len(run.dt)
+
+
+def test_xcd_local_exchange_is_bit_identical(gpu_lib, sedov3, monkeypatch):
+    """The exchange through one XCD's L2 (workgroups placed on one XCD) and the device-scope exchange
+    (LAGROM_XCD_MAP=0) give bit-identical runs at every shape; both match the oracle."""
+    wl, rom, y0, run = sedov3
+    P, G = _gpu_rom(wl, [(rom, wl.t_final)] * 3, [y0] * 3)
+    n_el = max(len(w.elems) for w in rom.windows)
+    for g in sorted({2, 5, n_el}):
+        print(f"[case] xcd-local exchange against device scope, 3 sedov instances, G={g}", flush=True)
+        G.set_workgroups(g)
+        monkeypatch.delenv("LAGROM_XCD_MAP", raising=False)
+        _restart3(G, y0)
+        G.step()
+        local = G.state.clone()
+        monkeypatch.setenv("LAGROM_XCD_MAP", "0")
+        _restart3(G, y0)
+        G.step()
+        assert torch.equal(G.state, local)
+        monkeypatch.delenv("LAGROM_XCD_MAP", raising=False)
+        for i in range(3):
+            st = G.states()[i]
+            assert st.status == 0 and st.done == 1 and st.n_steps == len(run.dt)
+            for a, b in zip(G.coords(i), run.yhat):
+                assert rel(a, b) < 1e-9
+
+
+def _restart3(G, y0):
+    G.init_state(torch.cat([_t(y0[0])] * 3), torch.cat([_t(y0[1])] * 3), torch.cat([_t(y0[2])] * 3))
