@@ -682,6 +682,26 @@ __device__ double rel_disc(const double* a, const double* b, const double* sc, i
     return v;
 }
 
+// Whether every workgroup of the instance runs on one XCD: each publishes its
+// XCD and they agree after one device-scope exchange; the exchanges of the
+// launch then stay in that XCD's L2.  The 2D kernels carry the same steps
+// inline; called out of line by the 3D kernels, whose register allocation
+// otherwise tips into spilling inside the step loop.
+__device__ __noinline__ bool same_xcd(const InstDev& I, int G, int g, int target, int* s_status, int* s_local) {
+    typedef const __attribute__((address_space(1))) int gi32;
+    if (threadIdx.x == 0) __hip_atomic_store(&I.xcc[g], xcc_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    sync_shares(I.flag, G, g, target, s_status, false);
+    if (threadIdx.x == 0) {
+        const int x0 = __hip_atomic_load((gi32*)&I.xcc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int same = (*s_status & LH_FLAG_TIMEOUT) == 0;
+        for (int j = 1; j < G; ++j)
+            same &= __hip_atomic_load((gi32*)&I.xcc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == x0;
+        *s_local = same;
+    }
+    __syncthreads();
+    return *s_local != 0;
+}
+
 // Instance and workgroup of a block.  With xcd_map, the G workgroups of
 // instance i are the blocks 8 ((i / 8) G + g) + i % 8, g < G, which the
 // round-robin dispatch puts on one XCD; the grid then has 8 ceil(n_inst / 8) G
@@ -737,19 +757,23 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
     // whether every workgroup of the instance runs on one XCD; the exchanges then stay in its L2
     bool local = false;
     if (A.G > 1) {
-        typedef const __attribute__((address_space(1))) int gi32;
-        if (tid == 0) __hip_atomic_store(&I.xcc[g], xcc_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, false);
-        ++phase;
-        if (tid == 0) {
-            const int x0 = __hip_atomic_load((gi32*)&I.xcc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            int same = (s_status & LH_FLAG_TIMEOUT) == 0;
-            for (int j = 1; j < A.G; ++j)
-                same &= __hip_atomic_load((gi32*)&I.xcc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == x0;
-            s_local = same;
+        if constexpr (DIM == 3) {
+            local = same_xcd(I, A.G, g, s_base + phase + 1, &s_status, &s_local);
+        } else {
+            typedef const __attribute__((address_space(1))) int gi32;
+            if (tid == 0) __hip_atomic_store(&I.xcc[g], xcc_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, false);
+            if (tid == 0) {
+                const int x0 = __hip_atomic_load((gi32*)&I.xcc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                int same = (s_status & LH_FLAG_TIMEOUT) == 0;
+                for (int j = 1; j < A.G; ++j)
+                    same &= __hip_atomic_load((gi32*)&I.xcc[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == x0;
+                s_local = same;
+            }
+            __syncthreads();
+            local = s_local != 0;
         }
-        __syncthreads();
-        local = s_local != 0;
+        ++phase;
     }
     Local<TT> L;
     load_local<DIM, TT>(I.win[w], I.win[w].views[g], I, RES, dyn, L);
