@@ -18,6 +18,7 @@
 // three kernels.  Columns are finally signed so that their largest-magnitude
 // entry (first such row) is positive.
 #include <algorithm>
+#include <cstdlib>
 #include <numeric>
 #include <vector>
 
@@ -306,6 +307,90 @@ __global__ void __launch_bounds__(256) jacobi_round_kernel(double* W, int m, int
     if (threadIdx.x == 0) atomicAdd(rotated, 1);
 }
 
+// Block form of the same sweep.  The columns are grouped in blocks of BJ; one
+// outer round pairs the blocks round-robin, and each workgroup loads its two
+// blocks (2 BJ columns of m rows) into LDS and runs one whole round-robin sweep
+// over those 2 BJ columns there: BJ column pairs at a time, 32 lanes per pair
+// (dot products reduced with lane shuffles), the same rotation and the same
+// skip test as the one-pair rounds.  A sweep then takes (number of blocks - 1)
+// launches instead of m - 1.  Columns at or past m (the padding block) read as
+// zero and are never rotated or written.
+constexpr int BJ = 8;
+constexpr int JL = 256 / BJ;  // lanes per column pair
+
+__device__ __forceinline__ double lane_sum32(double v) {
+#pragma unroll
+    for (int o = JL / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, JL);
+    return v;
+}
+
+__global__ void __launch_bounds__(256) jacobi_block_round_kernel(double* W, int m, int NBK, int round, double tol,
+                                                                double negl, int* rotated) {
+    extern __shared__ double colbuf[];  // [2 BJ][m]
+    __shared__ int s_rot;
+    const int i = blockIdx.x;
+    int P, Q;
+    if (i == 0) {
+        P = 0;
+        Q = 1 + round % (NBK - 1);
+    } else {
+        P = 1 + (round + i) % (NBK - 1);
+        Q = 1 + (round - i + (NBK - 1)) % (NBK - 1);
+    }
+    auto gcol = [&](int l) { return l < BJ ? P * BJ + l : Q * BJ + (l - BJ); };
+    if (threadIdx.x == 0) s_rot = 0;
+    for (int l = 0; l < 2 * BJ; ++l) {
+        const int c = gcol(l);
+        for (int r = threadIdx.x; r < m; r += 256) colbuf[(int64_t)l * m + r] = c < m ? W[(int64_t)c * m + r] : 0.0;
+    }
+    __syncthreads();
+    const int pr = threadIdx.x / JL, lane = threadIdx.x % JL;
+    constexpr int L = 2 * BJ;
+    for (int ir = 0; ir < L - 1; ++ir) {
+        int p, q;
+        if (pr == 0) {
+            p = 0;
+            q = 1 + ir % (L - 1);
+        } else {
+            p = 1 + (ir + pr) % (L - 1);
+            q = 1 + (ir - pr + (L - 1)) % (L - 1);
+        }
+        double* wp = colbuf + (int64_t)p * m;
+        double* wq = colbuf + (int64_t)q * m;
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int r = lane; r < m; r += JL) {
+            const double x = wp[r], y = wq[r];
+            a += x * x;
+            b += y * y;
+            g += x * y;
+        }
+        a = lane_sum32(a);
+        b = lane_sum32(b);
+        g = lane_sum32(g);
+        const bool skip = gcol(p) >= m || gcol(q) >= m || g == 0.0 || a <= negl || b <= negl ||
+                          fabs(g) <= tol * sqrt(a) * sqrt(b);
+        if (!skip) {
+            const double zeta = (b - a) / (2.0 * g);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double c = 1.0 / sqrt(1.0 + t * t);
+            const double s = c * t;
+            for (int r = lane; r < m; r += JL) {
+                const double x = wp[r], y = wq[r];
+                wp[r] = c * x - s * y;
+                wq[r] = s * x + c * y;
+            }
+            if (lane == 0) s_rot = 1;
+        }
+        __syncthreads();
+    }
+    for (int l = 0; l < 2 * BJ; ++l) {
+        const int c = gcol(l);
+        if (c < m)
+            for (int r = threadIdx.x; r < m; r += 256) W[(int64_t)c * m + r] = colbuf[(int64_t)l * m + r];
+    }
+    if (threadIdx.x == 0 && s_rot) atomicAdd(rotated, 1);
+}
+
 __global__ void __launch_bounds__(256) col_norm_kernel(const double* W, int m, double* sig) {
     __shared__ double sh[256];
     const double* col = W + (int64_t)blockIdx.x * m;
@@ -484,11 +569,25 @@ int rom_build_basis(const double* S, int64_t N, int32_t m, int64_t ldS, double e
         negl = 1e-30 * fro2;  // column norm below 1e-15 ||R||_F
     }
     bool converged = m == 1;
+    // block sweeps when 2 BJ columns fit in LDS, one-pair rounds otherwise
+    const int nbk = (m + BJ - 1) / BJ, NBK = nbk + (nbk & 1);
+    const size_t jlds = sizeof(double) * 2 * BJ * (size_t)m;
+    const char* jenv = std::getenv("LAGROM_POD_JACOBI");  // "pairs": one-pair rounds throughout
+    const bool blocked = jlds <= 150 * 1024 && !(jenv && std::string(jenv) == "pairs");
+    if (blocked)
+        LH_HIP_CHECK(hipFuncSetAttribute((const void*)jacobi_block_round_kernel,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)jlds));
     for (int sweep = 0; sweep < 80 && !converged; ++sweep) {
         LH_HIP_CHECK(hipMemsetAsync(w.rotated, 0, sizeof(int), s));
-        for (int r = 0; r < M - 1; ++r)
-            hipLaunchKernelGGL(jacobi_round_kernel, dim3(M / 2), dim3(256), 0, s, w.W, m, M, r, tol, negl,
-                               w.rotated);
+        if (blocked) {
+            for (int r = 0; r < NBK - 1; ++r)
+                hipLaunchKernelGGL(jacobi_block_round_kernel, dim3(NBK / 2), dim3(256), jlds, s, w.W, m, NBK, r, tol,
+                                   negl, w.rotated);
+        } else {
+            for (int r = 0; r < M - 1; ++r)
+                hipLaunchKernelGGL(jacobi_round_kernel, dim3(M / 2), dim3(256), 0, s, w.W, m, M, r, tol, negl,
+                                   w.rotated);
+        }
         int hrot = 0;
         LH_HIP_CHECK(hipMemcpyAsync(&hrot, w.rotated, sizeof(int), hipMemcpyDeviceToHost, s));
         LH_HIP_CHECK(hipStreamSynchronize(s));

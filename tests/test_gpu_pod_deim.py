@@ -44,7 +44,7 @@ def tg_snapshots():
 
 
 @pytest.mark.parametrize("N,m,seed", [(700, 60, 0), (1031, 33, 1), (257, 257, 2), (300, 1, 3), (9000, 150, 4),
-                                      (4099, 97, 5)])
+                                      (4099, 97, 5), (64, 5, 6), (500, 8, 7), (500, 9, 8)])
 def test_pod_matches_oracle_random(gpu_lib, N, m, seed):
     from paper_2104_11404_amd import lib
     print(f"[case] pod random N={N} m={m}", flush=True)
@@ -59,6 +59,23 @@ def test_pod_matches_oracle_random(gpu_lib, N, m, seed):
     for k in range(n):
         assert np.linalg.norm(Pg[:, k] - Phi_o[:, k]) < 1e-10, k
     np.testing.assert_allclose(Pg.T @ Pg, np.eye(n), atol=1e-13)
+
+
+def test_pod_block_and_pair_jacobi_agree(gpu_lib, monkeypatch):
+    """The block Jacobi sweep (2 x 8 columns in LDS) and the one-pair rounds reach the same singular
+    values and leading vectors."""
+    from paper_2104_11404_amd import lib
+    S, _ = _decaying(6000, 211, 9, rate=0.8)
+    print("[case] pod block against pair Jacobi N=6000 m=211", flush=True)
+    Pb, sb, _ = lib.rom_build_basis(_rows(S), n_fixed=12)
+    monkeypatch.setenv("LAGROM_POD_JACOBI", "pairs")
+    Pp, sp, _ = lib.rom_build_basis(_rows(S), n_fixed=12)
+    monkeypatch.delenv("LAGROM_POD_JACOBI")
+    sb, sp = sb.cpu().numpy(), sp.cpu().numpy()
+    assert np.max(np.abs(sb - sp)) <= 1e-13 * sp[0]
+    Pb, Pp = Pb.cpu().numpy(), Pp.cpu().numpy()
+    for k in range(12):
+        assert min(np.linalg.norm(Pb[k] - Pp[k]), np.linalg.norm(Pb[k] + Pp[k])) < 1e-10, k
 
 
 def test_pod_energy_criterion_and_eckart_young_on_snapshots(gpu_lib, tg_snapshots):
