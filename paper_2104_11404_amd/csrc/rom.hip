@@ -237,6 +237,29 @@ __device__ __forceinline__ double lift_row(const TT* tp, const double* os, int n
     return *os + (double)((a0 + a1) + (a2 + a3));
 }
 
+// The same sum with the tile in global memory: eight loads in flight per
+// round trip instead of four.
+template <class TT>
+__device__ __forceinline__ double lift_row_g(const TT* tp, const double* os, int n, int rows, const double* y) {
+    TT a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int k = 0;
+    for (; k + 7 < n; k += 8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] += tp[(k + j) * rows] * (TT)y[k + j];
+    }
+    for (; k < n; ++k) a[0] += tp[k * rows] * (TT)y[k];
+    return *os + (double)(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
+}
+
+// lift_row_g when GL (tiles in global memory), lift_row otherwise
+template <bool GL, class TT>
+__device__ __forceinline__ double lift_at(const TT* tp, const double* os, int n, int rows, const double* y) {
+    if constexpr (GL)
+        return lift_row_g(tp, os, n, rows, y);
+    else
+        return lift_row(tp, os, n, rows, y);
+}
+
 // share[i] = sum_e a(e, i) val[e] for i < n over the workgroup's ne entries (a: resident rows
 // [e][n], or the global DEIM operator indexed by the entry's column, ent[3 e + 2]): thread (i, c)
 // sums chunk c of the entries, the chunks are added in order (red: BLK doubles).
@@ -266,7 +289,7 @@ __device__ void project_share(const TT* a, bool res, const int* ent, int ne, int
 
 // Pass A for one workgroup: kept stress, entries of F.1 at the sampled rows,
 // the share of F^1 and the minimum step estimate (written to `share`).
-template <int DIM, class TT>
+template <int DIM, class TT, bool GL = false>
 __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const Local<TT>& L, NodeBuf<DIM>& B,
                        Shared& S, double* fe, const double* yx, const double* yv, const double* ye, double* share,
                        int* status) {
@@ -280,13 +303,13 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
             const int r = t % (2 * NKD + NT);
             const int slot = c0 + sl;
             if (r < NKD)
-                B.x[sl][r] = lift_row(L.tile[0] + (int64_t)slot * W.n[0] * NKD + r, L.os[0] + slot * NKD + r, W.n[0],
+                B.x[sl][r] = lift_at<GL>(L.tile[0] + (int64_t)slot * W.n[0] * NKD + r, L.os[0] + slot * NKD + r, W.n[0],
                                       NKD, yx);
             else if (r < 2 * NKD)
-                B.v[sl][r - NKD] = lift_row(L.tile[1] + (int64_t)slot * W.n[1] * NKD + (r - NKD),
+                B.v[sl][r - NKD] = lift_at<GL>(L.tile[1] + (int64_t)slot * W.n[1] * NKD + (r - NKD),
                                             L.os[1] + slot * NKD + (r - NKD), W.n[1], NKD, yv);
             else
-                B.e[sl][r - 2 * NKD] = lift_row(L.tile[2] + (int64_t)slot * W.n[2] * NT + (r - 2 * NKD),
+                B.e[sl][r - 2 * NKD] = lift_at<GL>(L.tile[2] + (int64_t)slot * W.n[2] * NT + (r - 2 * NKD),
                                                 L.os[2] + slot * NT + (r - 2 * NKD), W.n[2], NT, ye);
         }
         __syncthreads();
@@ -333,7 +356,7 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
 }
 
 // Pass B for one workgroup: F^T.v_c at its sampled energy dofs and its share of F^tv.
-template <int DIM, class TT>
+template <int DIM, class TT, bool GL = false>
 __device__ void pass_b(const RomArgs& A, const WinDev& W, const WgView& V, const Local<TT>& L, NodeBuf<DIM>& B,
                        double* te, const double* yvc, double* share, const int* status, double* red) {
     constexpr int EC = Cfg<DIM>::EC, NKD = Cfg<DIM>::NKD, NK = Cfg<DIM>::NK, NQ = Cfg<DIM>::NQ, DD = Cfg<DIM>::DD;
@@ -343,7 +366,7 @@ __device__ void pass_b(const RomArgs& A, const WinDev& W, const WgView& V, const
         for (int t = tid; t < ne * NKD; t += BLK) {
             const int o = t / NKD, r = t % NKD;
             const int slot = V.own[c0 + o];
-            B.v[o][r] = lift_row(L.tile[1] + (int64_t)slot * W.n[1] * NKD + r, L.os[1] + slot * NKD + r, W.n[1], NKD,
+            B.v[o][r] = lift_at<GL>(L.tile[1] + (int64_t)slot * W.n[1] * NKD + r, L.os[1] + slot * NKD + r, W.n[1], NKD,
                                  yvc);
         }
         __syncthreads();
@@ -784,7 +807,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
     bool done = false;
     if (adaptive && !(dt > 0.0)) {
         const WinDev& W = I.win[w];
-        pass_a<DIM, TT>(A, W, W.views[g], L, B, S, fe, S.y[0], S.y[1], S.y[2], (phase & 1) ? part1 : part0,
+        pass_a<DIM, TT, !RES>(A, W, W.views[g], L, B, S, fe, S.y[0], S.y[1], S.y[2], (phase & 1) ? part1 : part0,
                         &s_status);
         sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
         const double tau0 = combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage);
@@ -844,13 +867,13 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             tau = tau_est;
         } else {
         // ---- stage 1 at y_n
-        pass_a<DIM, TT>(A, W, V, L, B, S, fe, S.y[0], S.y[1], S.y[2], (phase & 1) ? part1 : part0, &s_status);
+        pass_a<DIM, TT, !RES>(A, W, V, L, B, S, fe, S.y[0], S.y[1], S.y[2], (phase & 1) ? part1 : part0, &s_status);
         sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
         const double tau1 = combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage);
         ++phase;
         for (int i = tid; i < W.n[1]; i += BLK) S.yh[1][i] = S.y[1][i] - 0.5 * h * S.f1h[i];
         __syncthreads();
-        pass_b<DIM, TT>(A, W, V, L, B, te, S.yh[1], (phase & 1) ? part1 : part0, &s_status, S.red);
+        pass_b<DIM, TT, !RES>(A, W, V, L, B, te, S.yh[1], (phase & 1) ? part1 : part0, &s_status, S.red);
         sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
         combine((phase & 1) ? all1 : all0, A.G, W.n[2], S.ftvh, &s_status, S, stage);
         ++phase;
@@ -872,7 +895,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         x_update(W, L, S.y[0], 0.5 * h, S.yh[1], S.yh[0], S.red);
         __syncthreads();
         // ---- stage 2 at y_{n+1/2}
-        pass_a<DIM, TT>(A, W, V, L, B, S, fe, S.yh[0], S.yh[1], S.yh[2], (phase & 1) ? part1 : part0, &s_status);
+        pass_a<DIM, TT, !RES>(A, W, V, L, B, S, fe, S.yh[0], S.yh[1], S.yh[2], (phase & 1) ? part1 : part0, &s_status);
         sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
         const double tau2 = combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage);
         ++phase;
@@ -882,7 +905,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             S.vc[i] = 0.5 * (S.y[1][i] + vn);
         }
         __syncthreads();
-        pass_b<DIM, TT>(A, W, V, L, B, te, S.vc, (phase & 1) ? part1 : part0, &s_status, S.red);
+        pass_b<DIM, TT, !RES>(A, W, V, L, B, te, S.vc, (phase & 1) ? part1 : part0, &s_status, S.red);
         sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
         combine((phase & 1) ? all1 : all0, A.G, W.n[2], S.ftvh, &s_status, S, stage);
         ++phase;
