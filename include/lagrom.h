@@ -181,7 +181,10 @@ size_t rom_build_basis_workspace_size(int64_t N, int32_t m);
  * value sum reaches energy_frac of the total (or n_fixed when > 0), capped
  * by n_max.  Computed as a Householder QR of S (FP64), a one-sided Jacobi
  * SVD of the m x m triangular factor and Phi = Q U_R.  Columns are signed
- * so that their largest-magnitude entry (first such row) is positive.
+ * so that their largest-magnitude entry (first such row) is positive.  The
+ * Jacobi sweep works on pairs of 8-column blocks held in LDS while 16 columns
+ * of m rows fit there (m up to 1228), on single column pairs otherwise or
+ * when the environment sets LAGROM_POD_JACOBI=pairs.
  * S (dev, N x m, ldS >= N) is not modified.  Phi (dev, N x n_max, ldPhi).
  * sigma (dev, m) receives all singular values in descending order.
  * *n_out (host) receives n.  Synchronises (reads the singular values). */
@@ -318,7 +321,12 @@ int rom_init_state(const lh_rom* r, const lh_instance_desc* inst, const double* 
  * reduced state).  An instance created with LH_OFFSETS_PREVIOUS stops when
  * it reaches the end of a window that has a successor (done stays 0, the
  * state keeps the closing window) and waits for
- * rom_switch_window_previous.  Asynchronous. */
+ * rom_switch_window_previous.  With G > 1 the workgroups of instance i are
+ * placed on one XCD (blocks 8 ((i / 8) G + g) + i % 8, the grid padded to
+ * 8 ceil(n_inst / 8) G blocks) when that grid is still co-resident, and the
+ * share exchange then stays in that XCD's L2 (checked in the kernel; the
+ * device-scope exchange otherwise).  LAGROM_XCD_MAP=0 in the environment turns
+ * the placement off; results are bit-identical either way.  Asynchronous. */
 int rom_step(const lh_rom* r, lh_rom_state* state, int32_t max_steps, uint32_t flags, const double* dt_replay,
              int32_t n_replay, hipStream_t stream);
 
