@@ -59,6 +59,7 @@ class WindowROM:
 @dataclass
 class ROM:
     windows: list
+    init_mass: list = field(default_factory=lambda: [None, None, None])  # per field: M of the initial projection
     train_offsets: list = field(default_factory=list)  # [window][trajectory] (x, v, e) snapshot offsets
 
 
@@ -78,13 +79,17 @@ def sampled_rows(op: F.Operator, elems: np.ndarray):
 SAMPLERS = {"deim": D.greedy_deim, "qdeim": D.qdeim}
 
 
-def build_window(op, S_list, os_list, T_end, energy_frac, n_fixed, lam, n_max=0, sampler="deim") -> WindowROM:
+def build_window(op, S_list, os_list, T_end, energy_frac, n_fixed, lam, n_max=0, sampler="deim",
+                 basis="euclidean") -> WindowROM:
     Phis, sigmas = [], []
     for f in range(3):
         nf = n_fixed[f] if n_fixed else 0
         Phi, sigma, _ = pod_basis(S_list[f], energy_frac, nf, n_max)
         Phis.append(Phi)
         sigmas.append(sigma)
+    if basis == "mass":  # velocity and energy bases orthonormal in M_V and M_E
+        Phis[1] = mass_orthonormal(Phis[1], op.Mv_eff)
+        Phis[2] = mass_orthonormal(Phis[2], op.Me)
     PF1, PFtv = sns_bases(op, Phis[1], Phis[2])
     nv, ne = Phis[1].shape[1], Phis[2].shape[1]
     pick = SAMPLERS[sampler]
@@ -112,6 +117,13 @@ def window_transition(Phi_new, os_new, Phi_old, os_old, M=None):
     return np.linalg.solve(Mhat, MP.T @ Phi_old), np.linalg.solve(Mhat, MP.T @ (os_old - os_new))
 
 
+def mass_orthonormal(Phi: np.ndarray, M) -> np.ndarray:
+    """The same subspace in a basis orthonormal in the M inner product (Sec. 3.2, eq. rmass: the alternative
+    with reduced mass matrix Phi^T M Phi = I): Phi L^{-T}, L the Cholesky factor of Phi^T M Phi."""
+    L = np.linalg.cholesky(Phi.T @ (M @ Phi))
+    return np.linalg.solve(L, Phi.T).T
+
+
 def idw_weights(params, mu, r: float = 2.0) -> np.ndarray:
     """Inverse distance weights of eq. interpolate_os: w_k = d(mu, mu_k)^-r / sum_j d(mu, mu_j)^-r with
     the Euclidean distance, or the unit weight of the first training parameter at distance 0."""
@@ -135,7 +147,7 @@ def interpolated_offsets(train_offsets: list, params, mu, r: float = 2.0) -> lis
 
 def build_rom(op, trajs, offsets, T_ends, energy_frac=0.9999, n_fixed=None, lam=(2.0, 2.0),
               n_max=0, online_offsets=None, sampler="deim", window_ic="orthogonal",
-              window_offsets="initial") -> ROM:
+              window_offsets="initial", basis="euclidean") -> ROM:
     """Offline phase: per-window POD, SNS, DEIM (greedy, or Q-DEIM with sampler="qdeim") and
     reduced operators.  window_ic: "orthogonal" (eq. ic-tw) or "oblique" (eq. ic2-tw: velocity and
     energy projected in the M_V and M_E inner products, position as in eq. ic-tw).
@@ -144,9 +156,15 @@ def build_rom(op, trajs, offsets, T_ends, energy_frac=0.9999, n_fixed=None, lam=
     state per trajectory); "window_start", window w's snapshots of trajectory k relative to that
     trajectory's state at the window's start.  online_offsets: one (x, v, e) for every window, or a
     list with one per window (for instance the interpolated offsets of eq. interpolate_os).
-    The training offsets per window and trajectory are kept in ROM.train_offsets."""
+    The training offsets per window and trajectory are kept in ROM.train_offsets.
+
+    basis="mass": the velocity and energy bases of every window are made orthonormal in M_V and M_E
+    (same subspaces, reduced mass matrices I); the projections of the initial state and of the
+    window changes are then taken in those inner products (so window_ic must be "oblique")."""
     if window_ic not in ("orthogonal", "oblique"):
         raise ValueError(window_ic)
+    if basis not in ("euclidean", "mass") or (basis == "mass" and window_ic != "oblique"):
+        raise ValueError("basis must be 'euclidean', or 'mass' with window_ic='oblique'")
     if window_offsets == "initial":
         by_window = [list(offsets)] * len(T_ends)
     elif window_offsets == "window_start":
@@ -160,7 +178,7 @@ def build_rom(op, trajs, offsets, T_ends, energy_frac=0.9999, n_fixed=None, lam=
     wins = []
     for w, Tw in enumerate(T_ends):
         win = build_window(op, mats[w], os_on[w] if per_window_os else os_on, Tw, energy_frac, n_fixed, lam, n_max,
-                           sampler)
+                           sampler, basis)
         if w > 0:
             prev = wins[-1]
             mass = [None, op.Mv_eff, op.Me] if window_ic == "oblique" else [None, None, None]
@@ -168,6 +186,8 @@ def build_rom(op, trajs, offsets, T_ends, energy_frac=0.9999, n_fixed=None, lam=
         wins.append(win)
     rom = ROM(wins)
     rom.train_offsets = by_window
+    if basis == "mass":
+        rom.init_mass = [None, op.Mv_eff, op.Me]
     return rom
 
 
@@ -233,8 +253,19 @@ class ROMRun:
 
 
 def initial_coords(rom: ROM, y0: tuple):
+    """Coordinates of the initial state in the first window: its orthogonal projection, or with a
+    mass inner product the M-orthogonal one, (Phi^T M Phi)^{-1} Phi^T M (y0 - os)."""
     win = rom.windows[0]
-    return tuple(win.Phi[f].T @ (y0[f] - win.os[f]) for f in range(3))
+    out = []
+    for f in range(3):
+        d = y0[f] - win.os[f]
+        M = rom.init_mass[f]
+        if M is None:
+            out.append(win.Phi[f].T @ d)
+        else:
+            MP = M @ win.Phi[f]
+            out.append(np.linalg.solve(win.Phi[f].T @ MP, MP.T @ d))
+    return tuple(out)
 
 
 def switch_window(rom: ROM, w: int, yhat: tuple) -> tuple:

@@ -398,3 +398,59 @@ def test_previous_window_offsets_retrace_the_fom_with_full_bases(tg_fom):
     # the offsets in use at the end are the ROM's own lifted state at the last switch, i.e. the FOM's
     for f in range(3):
         np.testing.assert_allclose(run.os[f], starts[2][f], rtol=1e-9, atol=1e-12)
+
+
+def test_mass_orthonormal_basis_is_gram_schmidt_in_the_mass_inner_product():
+    """Sec. 3.2 (eq. rmass, reduced mass I): Phi^T M Phi = I, the same subspace, and column k equals
+    the M-normalised part of phi_k M-orthogonal to phi_1..phi_{k-1} (modified Gram-Schmidt in the M
+    inner product, written out here); M = I leaves an orthonormal basis unchanged."""
+    rng = np.random.default_rng(23)
+    N, n = 50, 6
+    Phi = np.linalg.qr(rng.normal(size=(N, n)))[0]
+    B = rng.normal(size=(N, N))
+    M = B @ B.T + N * np.eye(N)
+    Q = R.mass_orthonormal(Phi, M)
+    np.testing.assert_allclose(Q.T @ M @ Q, np.eye(n), atol=1e-12)
+    np.testing.assert_allclose(Phi @ (Phi.T @ Q), Q, atol=1e-12)  # inside span(Phi)
+    G = Phi.copy()
+    for k in range(n):
+        for j in range(k):
+            G[:, k] -= (G[:, j] @ M @ G[:, k]) * G[:, j]
+        G[:, k] /= np.sqrt(G[:, k] @ M @ G[:, k])
+    np.testing.assert_allclose(Q, G, atol=1e-11)
+    np.testing.assert_allclose(R.mass_orthonormal(Phi, np.eye(N)), Phi, atol=1e-14)
+
+
+def test_mass_orthonormal_rom_equals_the_euclidean_basis_rom_with_full_sampling(tg_fom):
+    """Same subspaces, projections in the mass inner product (eq. ic2-tw for the window changes): with
+    every element sampled the reduced dynamics do not depend on the basis of each subspace, so the
+    lifted states of the two ROMs agree through three windows at reduced rank."""
+    wl, op, tr, y0 = tg_fom
+    T = windows_by_samples([tr.t], 2 * int(np.ceil(len(tr.dt) / 3)))
+    kw = dict(n_fixed=(5, 6, 4), lam=(1e9, 1e9), window_ic="oblique")
+    rom_e = R.build_rom(op, [tr], [y0], T, **kw)
+    rom_m = R.build_rom(op, [tr], [y0], T, basis="mass", **kw)
+    for w in rom_m.windows:
+        np.testing.assert_allclose(w.Phi[1].T @ op.Mv_eff @ w.Phi[1], np.eye(6), atol=1e-10)
+        np.testing.assert_allclose(w.Phi[2].T @ op.Me @ w.Phi[2], np.eye(4), atol=1e-10)
+    run_e = R.run_rom(op, rom_e, y0, wl.t_final, dt_replay=tr.dt)
+    run_m = R.run_rom(op, rom_m, y0, wl.t_final, dt_replay=tr.dt)
+    assert run_m.w == len(T) - 1
+    for a, b in zip(R.final_lift(rom_m, run_m), R.final_lift(rom_e, run_e)):
+        assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b)
+
+
+def test_mass_basis_initial_coordinates_are_the_mass_projection(tg_fom):
+    """With an offset other than the initial state the first coordinates are the M-orthogonal
+    projection: the residual y0 - os - Phi yhat is M-orthogonal to the window's basis."""
+    wl, op, tr, y0 = tg_fom
+    shifted = (y0[0], y0[1] * 0.9, y0[2] * 1.1)
+    rom = R.build_rom(op, [tr], [y0], [wl.t_final], n_fixed=(4, 5, 3), window_ic="oblique", basis="mass",
+                      online_offsets=shifted)
+    yh = R.initial_coords(rom, y0)
+    win = rom.windows[0]
+    for f, M in ((1, op.Mv_eff), (2, op.Me)):
+        r = y0[f] - win.os[f] - win.Phi[f] @ yh[f]
+        assert np.max(np.abs(win.Phi[f].T @ (M @ r))) <= 1e-10 * max(1.0, np.linalg.norm(M @ r))
+    with pytest.raises(ValueError):
+        R.build_rom(op, [tr], [y0], [wl.t_final], n_fixed=(4, 5, 3), basis="mass")
