@@ -193,13 +193,14 @@ def autotune(rom, flags, trial_steps):
     return {"G": g, "trial_steps": trial_steps, "trial_ms": ms, "tuning_s": time.perf_counter() - t0}
 
 
-OFFLINE_VARIANTS = {"deim": {}, "qdeim": {"sampler": "qdeim"}, "deim_oblique_window_ic": {"window_ic": "oblique"}}
+OFFLINE_VARIANTS = {"deim": {}, "qdeim": {"sampler": "qdeim"}, "deim_oblique_window_ic": {"window_ic": "oblique"},
+                    "deim_mass_orthonormal": {"window_ic": "oblique", "basis": "mass"}}
 
 
 def offline_variants(lib, pipeline, torch, P, traj, T, wl, reps=3):
     """The headline workload rebuilt with each offline variant (same snapshots, windows and lambda):
-    greedy DEIM rows, Q-DEIM rows, and greedy DEIM rows with the oblique window initial condition
-    (eq. ic2-tw).  Sampled elements, errors against the FOM and ROM steps/s at the tuned shape."""
+    greedy DEIM rows, Q-DEIM rows, greedy DEIM rows with the oblique window initial condition
+    (eq. ic2-tw), and the same with velocity and energy bases orthonormal in the mass inner products.  Sampled elements, errors against the FOM and ROM steps/s at the tuned shape."""
     out = {}
     for name, kw in OFFLINE_VARIANTS.items():
         t0 = time.perf_counter()

@@ -242,6 +242,7 @@ typedef struct {
 
 enum { LH_WINDOW_IC_ORTHOGONAL = 0, LH_WINDOW_IC_OBLIQUE = 1 };
 enum { LH_OFFSETS_GIVEN = 0, LH_OFFSETS_PREVIOUS = 1 };
+enum { LH_BASIS_EUCLIDEAN = 0, LH_BASIS_MASS = 1 };
 
 typedef struct {
     int32_t n_windows;
@@ -255,6 +256,11 @@ typedef struct {
                                       description; LH_OFFSETS_PREVIOUS (eq. previous_os): the
                                       first window's offsets, then at each switch the lifted state
                                       (rom_switch_window_previous) */
+    int32_t basis;                 /* LH_BASIS_EUCLIDEAN: orthonormal bases; LH_BASIS_MASS: velocity and
+                                      energy bases orthonormal in M_V and M_E (lh_mass_orthonormalize),
+                                      the initial coordinates then the M-projection of y0 - os;
+                                      needs window_ic = LH_WINDOW_IC_OBLIQUE */
+    int32_t reserved_;             /* 0 */
 } lh_instance_desc;
 
 #define LH_NMAX 64
@@ -432,6 +438,16 @@ int lh_project_snapshots(const double* Phi, int32_t n, int64_t N, int64_t ldp, c
  * dev); in and out must differ for the kinematic apply. */
 int lh_mass_apply_v(const lh_problem* p, const double* in, double* out, hipStream_t stream);
 int lh_mass_apply_e(const lh_problem* p, const double* in, double* out, hipStream_t stream);
+
+/* Basis orthonormal in the mass inner product (Sec. 3.2, eq. rmass: the
+ * alternative with reduced mass matrix Phi^T M Phi = I).  field 1: M_V in the
+ * form lh_mass_apply_v applies (N = N_V); field 2: M_E (N = N_E).  Phi (dev,
+ * n columns of length N, column stride ld >= N, n <= LH_NMAX) is replaced in
+ * place by Phi L^{-T}, L the Cholesky factor of Phi^T M Phi: the same
+ * subspace, column k the M-normalised part of column k M-orthogonal to the
+ * earlier ones.  LH_ERANK, Phi unchanged, if Phi^T M Phi is not positive
+ * definite.  Allocates its scratch; synchronises. */
+int lh_mass_orthonormalize(const lh_problem* p, int32_t field, double* Phi, int32_t n, int64_t ld, hipStream_t stream);
 
 /* Window end points by number of samples (eq. sample_window), host only.
  * t_lists[k] (host, n_steps[k] + 1 accepted times from 0) per parameter k;

@@ -119,6 +119,83 @@ __global__ void weighted_sum_kernel(WsumArgs a, int64_t N, double* out) {
     out[i] = acc;
 }
 
+namespace lh {
+namespace off {
+
+// out[i + j n] = sum_r P[r + i ldp] Q[r + j ldq] over N rows (P^T Q), one workgroup per entry
+__global__ void __launch_bounds__(256) gram_kernel(const double* P, int64_t ldp, const double* Q, int64_t ldq,
+                                                   int64_t N, int n, double* out) {
+    __shared__ double sh[256];
+    const int i = blockIdx.x, j = blockIdx.y;
+    double acc = 0.0;
+    for (int64_t r = threadIdx.x; r < N; r += 256) acc += P[(int64_t)i * ldp + r] * Q[(int64_t)j * ldq + r];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(int64_t)j * n + i] = sh[0];
+}
+
+// One workgroup, n <= 64: the Cholesky factor L of the symmetric G (n x n) in LDS,
+// then Linv = L^{-1} (row-major, lower triangular), one thread per column.
+// *bad = 1 when a pivot is not positive.
+__global__ void __launch_bounds__(256) chol_inv_kernel(const double* G, int n, double* Linv, int* bad) {
+    __shared__ double A[LH_NMAX * LH_NMAX];
+    __shared__ int s_bad;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < n * n; t += 256) A[t] = G[t];  // symmetric: row or column order alike
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        if (tid == 0) {
+            const double d = A[k * n + k];
+            if (!(d > 0.0)) s_bad = 1;
+            A[k * n + k] = d > 0.0 ? sqrt(d) : 1.0;
+        }
+        __syncthreads();
+        for (int i = k + 1 + tid; i < n; i += 256) A[i * n + k] /= A[k * n + k];
+        __syncthreads();
+        for (int t = tid; t < (n - k - 1) * (n - k - 1); t += 256) {
+            const int i = k + 1 + t / (n - k - 1), j = k + 1 + t % (n - k - 1);
+            if (j <= i) A[i * n + j] -= A[i * n + k] * A[j * n + k];
+        }
+        __syncthreads();
+    }
+    if (tid < n) {
+        const int c = tid;
+        for (int i = 0; i < c; ++i) Linv[i * n + c] = 0.0;
+        Linv[c * n + c] = 1.0 / A[c * n + c];
+        for (int i = c + 1; i < n; ++i) {
+            double acc = 0.0;
+            for (int k = c; k < i; ++k) acc += A[i * n + k] * Linv[k * n + c];
+            Linv[i * n + c] = -acc / A[i * n + i];
+        }
+    }
+    if (tid == 0) *bad = s_bad;
+}
+
+// Y[r + j N] = sum_{k <= j} X[r + k ldx] Linv[j n + k]: the rows of X times L^{-T}
+__global__ void rows_linvT_kernel(const double* X, int64_t ldx, int64_t N, int n, const double* Linv, double* Y) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    for (int j = 0; j < n; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k <= j; ++k) acc += X[(int64_t)k * ldx + r] * Linv[j * n + k];
+        Y[(int64_t)j * N + r] = acc;
+    }
+}
+
+__global__ void copy_cols_kernel(const double* Y, int64_t N, int n, double* X, int64_t ldx) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    for (int j = 0; j < n; ++j) X[(int64_t)j * ldx + r] = Y[(int64_t)j * N + r];
+}
+
+}  // namespace off
+}  // namespace lh
+
 extern "C" {
 
 int lh_snapshot_deviation(const double* snaps, int64_t N, int32_t m, int64_t ld, const double* os, double* out,
@@ -269,6 +346,59 @@ int lh_weighted_sum(const double* const* x, const double* w, int32_t K, int64_t 
     }
     hipLaunchKernelGGL(weighted_sum_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, a, N, out);
     return launch_check("lh_weighted_sum");
+}
+
+int lh_mass_orthonormalize(const lh_problem* p, int32_t field, double* Phi, int32_t n, int64_t ld, hipStream_t s) {
+    using namespace lh;
+    LH_REQUIRE(p && Phi && (field == 1 || field == 2), "lh_mass_orthonormalize: bad arguments");
+    LH_REQUIRE(n >= 1 && n <= LH_NMAX, "lh_mass_orthonormalize: n outside [1, 64]");
+    const int64_t N = field == 1 ? (int64_t)p->NV : (int64_t)p->NE;
+    LH_REQUIRE(ld >= N, "lh_mass_orthonormalize: ld < N");
+    double *MP = nullptr, *G = nullptr, *Linv = nullptr;
+    int* bad = nullptr;
+    auto cleanup = [&]() {
+        if (MP) (void)hipFree(MP);
+        if (G) (void)hipFree(G);
+        if (Linv) (void)hipFree(Linv);
+        if (bad) (void)hipFree(bad);
+    };
+    if (hipMalloc(&MP, sizeof(double) * N * n) != hipSuccess || hipMalloc(&G, sizeof(double) * n * n) != hipSuccess ||
+        hipMalloc(&Linv, sizeof(double) * n * n) != hipSuccess || hipMalloc(&bad, sizeof(int)) != hipSuccess) {
+        cleanup();
+        set_error("lh_mass_orthonormalize: device allocation failed");
+        return LH_EDEVICE;
+    }
+    int rc = LH_OK;
+    for (int k = 0; k < n && rc == LH_OK; ++k)
+        rc = field == 1 ? lh_mass_apply_v(p, Phi + (int64_t)k * ld, MP + (int64_t)k * N, s)
+                        : lh_mass_apply_e(p, Phi + (int64_t)k * ld, MP + (int64_t)k * N, s);
+    int hbad = 0;
+    if (rc == LH_OK) {
+        const unsigned nb = (unsigned)((N + 255) / 256);
+        hipLaunchKernelGGL(off::gram_kernel, dim3(n, n), dim3(256), 0, s, Phi, ld, MP, N, N, n, G);
+        hipLaunchKernelGGL(off::chol_inv_kernel, dim3(1), dim3(256), 0, s, G, n, Linv, bad);
+        rc = launch_check("lh_mass_orthonormalize");
+        if (rc == LH_OK && (hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                            hipStreamSynchronize(s) != hipSuccess)) {
+            set_error("lh_mass_orthonormalize: synchronisation failed");
+            rc = LH_EDEVICE;
+        }
+        if (rc == LH_OK && !hbad) {
+            hipLaunchKernelGGL(off::rows_linvT_kernel, dim3(nb), dim3(256), 0, s, Phi, ld, N, n, Linv, MP);
+            hipLaunchKernelGGL(off::copy_cols_kernel, dim3(nb), dim3(256), 0, s, MP, N, n, Phi, ld);
+            rc = launch_check("lh_mass_orthonormalize");
+            if (rc == LH_OK && hipStreamSynchronize(s) != hipSuccess) {
+                set_error("lh_mass_orthonormalize: synchronisation failed");
+                rc = LH_EDEVICE;
+            }
+        }
+    }
+    cleanup();
+    if (rc == LH_OK && hbad) {
+        set_error("lh_mass_orthonormalize: the basis is rank deficient in the mass inner product");
+        rc = LH_ERANK;
+    }
+    return rc;
 }
 
 }  // extern "C"

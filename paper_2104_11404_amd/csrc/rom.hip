@@ -1216,6 +1216,8 @@ struct lh_rom {
     std::vector<std::vector<lh::rom::WinDev>> h_win;
     std::vector<std::vector<lh::rom::HostWin>> h_struct;
     std::vector<lh::rom::PrevOs> prev;  // per instance; os == nullptr: offsets as given
+    std::vector<char> mass_basis;       // per instance: bases orthonormal in the mass inner products
+    double* init_tmp = nullptr;         // [2 max(N_V, N_E)] scratch of their initial projection
 };
 
 namespace lh {
@@ -1622,6 +1624,7 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
     R->h_win.resize(n_inst);
     R->h_struct.resize(n_inst);
     R->prev.resize(n_inst);
+    R->mass_basis.assign(n_inst, 0);
     const int dim = p->dim;
     const int NQ = dim == 3 ? 64 : 16;
     auto fail = [&](int rc) {
@@ -1642,6 +1645,15 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
         }
         if (d.offsets != LH_OFFSETS_GIVEN && d.offsets != LH_OFFSETS_PREVIOUS) {
             set_error("rom_create: offsets must be LH_OFFSETS_GIVEN or LH_OFFSETS_PREVIOUS");
+            return fail(LH_EINVAL);
+        }
+        if (d.basis != LH_BASIS_EUCLIDEAN && d.basis != LH_BASIS_MASS) {
+            set_error("rom_create: basis must be LH_BASIS_EUCLIDEAN or LH_BASIS_MASS");
+            return fail(LH_EINVAL);
+        }
+        if (d.basis == LH_BASIS_MASS && d.window_ic != LH_WINDOW_IC_OBLIQUE) {
+            set_error("rom_create: mass-orthonormal bases need LH_WINDOW_IC_OBLIQUE (window changes in the mass inner "
+                      "products)");
             return fail(LH_EINVAL);
         }
         for (int j = 0; j < i && R->alias[i] < 0; ++j)
@@ -1709,6 +1721,12 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
         if ((rc = upload(R, R->h_win[i], &dw))) return fail(rc);
         I.win = dw;
     }
+    bool any_mass = false;
+    for (int i = 0; i < n_inst; ++i) any_mass = any_mass || (R->mass_basis[i] = inst[i].basis == LH_BASIS_MASS);
+    if (any_mass) {
+        const int rc = dev_alloc(R, &R->init_tmp, 2 * (int64_t)std::max(p->NV, p->NE));
+        if (rc) return fail(rc);
+    }
     const InstDev* di;
     int rc = upload(R, R->h_inst, &di);
     if (rc) return fail(rc);
@@ -1746,6 +1764,16 @@ int rom_init_state(const lh_rom* R, const lh_instance_desc* inst, const double* 
             double* dst = reinterpret_cast<double*>(reinterpret_cast<char*>(state + i) + offsetof(lh_rom_state, yhat)) +
                           f * LH_NMAX;
             hipLaunchKernelGGL(init_coords_kernel, dim3(w0.n[f]), dim3(256), 0, s, w0.phi[f], N, y0[f], w0.os[f], dst);
+            if (R->mass_basis[i] && f > 0) {
+                // mass-orthonormal basis: y^ = Phi^T M (y0 - os), the M-orthogonal projection
+                double* d = R->init_tmp;
+                double* Md = R->init_tmp + std::max(p->NV, p->NE);
+                hipLaunchKernelGGL(sub_kernel, dim3(nb(N)), dim3(256), 0, s, y0[f], w0.os[f], d, N);
+                const int rc = f == 1 ? lh_mass_apply_v(p, d, Md, s) : lh_mass_apply_e(p, d, Md, s);
+                if (rc) return rc;
+                hipLaunchKernelGGL(gemm_tn_kernel, dim3(w0.n[f], 1), dim3(256), 0, s, w0.phi[f], Md, N, N, N, w0.n[f],
+                                   dst);
+            }
             if (R->prev[i].os)  // previous-window offsets start from the first window's
                 hipLaunchKernelGGL(copy_kernel, dim3(nb(N)), dim3(256), 0, s, w0.os[f],
                                    R->prev[i].os + (f > 0 ? p->NV : 0) + (f > 1 ? p->NV : 0), N);

@@ -55,7 +55,7 @@ class WindowDesc(C.Structure):
 
 class InstanceDesc(C.Structure):
     _fields_ = [("n_windows", C.c_int32), ("windows", C.POINTER(WindowDesc)), ("t_final", C.c_double),
-                ("window_ic", C.c_int32), ("offsets", C.c_int32)]
+                ("window_ic", C.c_int32), ("offsets", C.c_int32), ("basis", C.c_int32), ("reserved_", C.c_int32)]
 
 
 class MlpDesc(C.Structure):
@@ -120,6 +120,7 @@ _SIGNATURES = {
     "lh_weighted_sum": (_I32, [C.POINTER(_VP), C.POINTER(_D), _I32, _I64, _VP, _VP]),
     "lh_mass_apply_v": (_I32, [_VP, _VP, _VP, _VP]),
     "lh_mass_apply_e": (_I32, [_VP, _VP, _VP, _VP]),
+    "lh_mass_orthonormalize": (_I32, [_VP, _I32, _VP, _I32, _I64, _VP]),
     "lh_windows_by_samples": (_I32, [_I32, C.POINTER(C.POINTER(_D)), C.POINTER(_I32), _I32, C.POINTER(_D), _I32,
                                      C.POINTER(_I32)]),
     "lh_window_columns": (_I32, [C.POINTER(_D), _I32, C.POINTER(_D), _I32, C.POINTER(_I32), C.POINTER(_I32)]),
@@ -301,6 +302,16 @@ def rom_build_basis(S, energy_frac=0.9999, n_fixed=0, n_max=0):
     return Phi[: n_out.value], sigma, n_out.value
 
 
+def mass_orthonormalize(problem, field, Phi):
+    """lh_mass_orthonormalize in place on Phi, a (n, N) float64 CUDA tensor (n basis columns of length N
+    stored one after another); field 1: M_V, 2: M_E."""
+    if Phi.dtype != torch.float64 or not Phi.is_cuda or not Phi.is_contiguous() or Phi.dim() != 2:
+        raise ValueError("Phi must be a contiguous (n, N) float64 CUDA tensor")
+    n, N = Phi.shape
+    _check(load().lh_mass_orthonormalize(problem.h, int(field), ptr(Phi), int(n), int(N), stream_handle()))
+    return Phi
+
+
 def idw_weights(params, mu, r=2.0):
     """Weights of eq. interpolate_os (lh_idw_weights); params: K training parameters (scalars or
     d-vectors), mu: the parameter to interpolate at."""
@@ -379,6 +390,7 @@ class Rom:
             descs[i].t_final = float(inst["t_final"])
             descs[i].window_ic = {"orthogonal": 0, "oblique": 1}[inst.get("window_ic", "orthogonal")]
             descs[i].offsets = {"given": 0, "previous": 1}[inst.get("offsets", "given")]
+            descs[i].basis = {"euclidean": 0, "mass": 1}[inst.get("basis", "euclidean")]
         self.descs = descs
         h = C.c_void_p()
         _check(lib.rom_create(problem.h, len(instances), descs, C.byref(h), stream_handle()))

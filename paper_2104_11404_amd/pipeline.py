@@ -56,7 +56,7 @@ def fom_trajectory(P: lib.Problem, t_final: float, fixed_dt: float = 0.0, max_st
 
 def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_frac=0.9999, n_fixed=(), n_max=64,
                   lam=(2.0, 2.0), t_final=None, verbose=False, snapshot_offsets=None, sampler="deim",
-                  window_ic="orthogonal", window_offsets="initial"):
+                  window_ic="orthogonal", window_offsets="initial", basis="euclidean"):
     """Per-window POD, SNS and DEIM (greedy, or Q-DEIM with sampler="qdeim") on the GPU; returns a lib.Rom
     instance description.
 
@@ -66,9 +66,14 @@ def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_f
     trajectory's state at the window's start (the step state that closed window w - 1).  The offsets
     used are returned as train_offsets[w][k].  online_offsets: one (x, v, e) for every window, or one
     per window (see interpolated_instance).
+
+    basis="mass": the velocity and energy bases are made orthonormal in M_V and M_E
+    (lh_mass_orthonormalize; Sec. 3.2, reduced mass I) before SNS and DEIM; needs window_ic="oblique".
     """
     if window_offsets not in ("initial", "window_start"):
         raise ValueError(window_offsets)
+    if basis not in ("euclidean", "mass") or (basis == "mass" and window_ic != "oblique"):
+        raise ValueError("basis must be 'euclidean', or 'mass' with window_ic='oblique'")
     so = lib.load()
     stream = lib.stream_handle()
     sizes = (P.NV, P.NV, P.NE)
@@ -103,6 +108,9 @@ def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_f
             phis.append(Phi.contiguous())
             dims.append(n)
             del S
+        if basis == "mass":
+            lib.mass_orthonormalize(P, 1, phis[1])
+            lib.mass_orthonormalize(P, 2, phis[2])
         PF1 = torch.empty_like(phis[1])
         PFtv = torch.empty_like(phis[2])
         for k in range(dims[1]):
@@ -114,7 +122,7 @@ def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_f
         os_on = online_offsets[w] if isinstance(online_offsets, list) else online_offsets
         windows.append(dict(t_end=Tw, phi=phis, os=list(os_on), z1=z1, z2=z2, a1=a1, a2=a2))
     return dict(t_final=t_final if t_final is not None else T[-1], windows=windows, window_ic=window_ic,
-                train_offsets=train_offsets)
+                basis=basis, train_offsets=train_offsets)
 
 
 def interpolated_instance(inst: dict, params, mu, r: float = 2.0) -> dict:
