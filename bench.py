@@ -626,8 +626,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, help="also run a plain device copy of this many MiB")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (instances and elements would "
-              "shard across GPUs with no communication; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (instances, or the sampled elements "
+              "of one instance, would be split across GPUs; only the small reduced shares would be exchanged).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
