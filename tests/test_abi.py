@@ -121,3 +121,41 @@ def test_idw_weights_of_the_library_match_the_oracle():
                        ([[0.0, 0.0], [2.0, 0.0], [0.5, 1.5]], [1.0, 3.0])):
         for r in (1.0, 2.0, 3.5):
             np.testing.assert_allclose(lib.idw_weights(params, mu, r), R.idw_weights(params, mu, r), rtol=1e-14)
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes mirror of a header struct has the C size and the C offset of each field (a host
+    program built from include/lagrom.h with g++ prints them)."""
+    import shutil
+    import subprocess
+
+    from paper_2104_11404_amd import lib
+
+    gxx = shutil.which("g++")
+    if gxx is None or not os.path.exists("/opt/rocm/include/hip/hip_runtime_api.h"):
+        pytest.skip("needs g++ and the HIP headers")
+    pairs = {"lh_problem_desc": lib.ProblemDesc, "lh_fom_run_desc": lib.FomRunDesc,
+             "lh_fom_run_stats": lib.FomRunStats, "lh_window_desc": lib.WindowDesc,
+             "lh_instance_desc": lib.InstanceDesc, "lh_mlp_desc": lib.MlpDesc, "lh_rom_state": lib.RomState}
+    lines = ["#include <cstdio>", "#include <cstddef>", '#include "lagrom.h"', "int main() {"]
+    for cname, cls in pairs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'    printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.cpp"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run([gxx, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", inc, str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            c, f, v = ln.split()
+            got[(c, f)] = int(v)
+    for cname, cls in pairs.items():
+        assert got[(cname, "size")] == C.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
