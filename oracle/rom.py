@@ -250,6 +250,40 @@ class ROMRun:
     rejections: int = 0
     window_of_step: list = field(default_factory=list)
     os: tuple = None  # offsets in use at the end (offsets="previous" changes them at every switch)
+    energy: list = field(default_factory=list)  # total energy of the lifted state at t_0 and every accepted step
+
+
+@dataclass
+class EnergyOps:
+    """Reduced form of the discrete total energy of a window's lifted state.
+
+    RK2-average conserves E = 1/2 v^T M_V v + 1^T M_E e of the semi-discrete system (Sec. 2.2.1).
+    For v = v_os + Phi_v v^ and e = e_os + Phi_e e^ it is a quadratic in the reduced coordinates,
+    with the reduced mass matrix Mhat_V = Phi_v^T M_V Phi_v of eq. rmass (Sec. 3.2):
+
+        E = c + m_v^T v^ + 1/2 v^T Mhat_V v^ + m_e^T e^,
+        m_v = Phi_v^T M_V v_os,  m_e = Phi_e^T M_E 1,  c = 1/2 v_os^T M_V v_os + 1^T M_E e_os.
+
+    M_V is the kinematic mass matrix without boundary elimination, the one of the FOM's total energy."""
+
+    Mv_hat: np.ndarray
+    mv: np.ndarray
+    me: np.ndarray
+    c: float
+
+
+def energy_ops(op: F.Operator, win: WindowROM) -> EnergyOps:
+    Pv, Pe = win.Phi[1], win.Phi[2]
+    vos, eos = np.asarray(win.os[1]), np.asarray(win.os[2])
+    MPv = op.Mv @ Pv
+    Mvos = op.Mv @ vos
+    Me1 = op.Me.T @ np.ones(op.mesh.NE)
+    c = 0.5 * float(vos @ Mvos) + float(Me1 @ eos)
+    return EnergyOps(Pv.T @ MPv, Pv.T @ Mvos, Pe.T @ Me1, c)
+
+
+def reduced_energy(ops: EnergyOps, vh: np.ndarray, eh: np.ndarray) -> float:
+    return ops.c + float(ops.mv @ vh) + 0.5 * float(vh @ (ops.Mv_hat @ vh)) + float(ops.me @ eh)
 
 
 def initial_coords(rom: ROM, y0: tuple):
@@ -308,6 +342,14 @@ def run_rom(op: F.Operator, rom: ROM, y0: tuple, t_final: float, dt_replay=None,
     t = 0.0
     run = ROMRun([0.0], [], 0, yhat)
     cur = rom.windows[0]
+    eops = {}
+
+    def energy_of(win, y):
+        if id(win) not in eops:
+            eops[id(win)] = (win, energy_ops(op, win))  # keep win alive so its id stays unique
+        return reduced_energy(eops[id(win)][1], y[1], y[2])
+
+    run.energy.append(energy_of(cur, yhat))
     if fixed_dt is not None:
         dt = fixed_dt
     elif dt_replay is None:
@@ -341,6 +383,7 @@ def run_rom(op: F.Operator, rom: ROM, y0: tuple, t_final: float, dt_replay=None,
             else:
                 yhat = switch_window(rom, w, yhat)
                 cur = rom.windows[w]
+        run.energy.append(energy_of(cur, yhat))
     run.w = w
     run.yhat = yhat
     run.os = tuple(np.asarray(o) for o in cur.os)
