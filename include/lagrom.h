@@ -284,6 +284,14 @@ typedef struct {
     int32_t n_surrogate_steps;
     int32_t n_fallbacks;     /* windows that fell back                                */
     int32_t pad_;
+    /* Total energy 1/2 v~^T M_V v~ + 1^T M_E e~ of the lifted state, which RK2-average
+     * conserves for the semi-discrete system (Sec. 2.2.1), formed in FP64 from the reduced
+     * coordinates with the reduced mass matrix Phi_v^T M_V Phi_v (Sec. 3.2, eq. rmass),
+     * Phi_v^T M_V v_os and Phi_e^T M_E 1 precomputed per window (M_V without wall
+     * elimination).  Written by rom_init_state and after every accepted step of rom_step. */
+    double energy;           /* at the current state                                  */
+    double energy0;          /* at the initial state                                  */
+    double energy_dev;       /* max over accepted steps of |energy - energy0|         */
 } lh_rom_state;
 
 typedef struct lh_rom lh_rom;

@@ -141,6 +141,10 @@ void set_error(const std::string& msg);
         }                                  \
     } while (0)
 
+// out = M_V in with the kinematic mass matrix of the total energy (no wall elimination), one
+// kinematic vector (N_V, dev; in and out must differ).  Uses the problem's scratch under its mutex.
+int mass_apply_v_full(const lh_problem* p, const double* in, double* out, hipStream_t stream);
+
 inline int launch_check(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {

@@ -403,6 +403,23 @@ static int tensor_apply(const lh_problem* p, double* const* mats, const double* 
     return lh::launch_check("apply_axis_kernel");
 }
 
+}  // extern "C"
+
+namespace lh {
+int mass_apply_v_full(const lh_problem* p, const double* in, double* out, hipStream_t stream) {
+    LH_REQUIRE(p && in && out && in != out, "mass_apply_v_full: bad arguments");
+    ProblemExtra* ex = extra_of(p);
+    std::lock_guard<std::mutex> lock(ex->mtx);
+    for (int c = 0; c < p->dim; ++c) {
+        const int rc = tensor_apply(p, ex->d_m, in + c * p->n_nodes, out + c * p->n_nodes, ex->d_tmp, stream);
+        if (rc) return rc;
+    }
+    return LH_OK;
+}
+}  // namespace lh
+
+extern "C" {
+
 int lh_mass_solve_v(const lh_problem* p, const double* rhs, double* out, hipStream_t stream) {
     using namespace lh;
     LH_REQUIRE(p && rhs && out, "lh_mass_solve_v: null argument");

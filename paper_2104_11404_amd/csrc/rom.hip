@@ -76,6 +76,11 @@ struct WinDev {
     const double* T[3];  // from the previous window: n_f^w x n_f^{w-1}
     const double* c[3];
     const WgView* views;  // [G]
+    // total energy of the lifted state in reduced form: Ec[0] + Emv.v^ + 1/2 v^T EMv v^ + Eme.e^
+    const double* EMv;  // Phi_v^T M_V Phi_v, n_v x n_v (the reduced mass matrix of eq. rmass)
+    const double* Emv;  // Phi_v^T M_V v_os
+    const double* Eme;  // Phi_e^T M_E 1
+    const double* Ec;   // [0] = 1/2 v_os^T M_V v_os + 1^T M_E e_os ([1], [2]: its two dot products)
     MlpDev net;           // surrogate of this window (net.L == 0: none)
     int audit_every;
     double tol;
@@ -725,6 +730,29 @@ __device__ __noinline__ bool same_xcd(const InstDev& I, int G, int g, int target
     return *s_local != 0;
 }
 
+// Total energy 1/2 v~^T M_V v~ + 1^T M_E e~ of the state lifted from window W (conserved by the
+// semi-discrete RK2-average step, Sec. 2.2.1), in FP64 from the reduced coordinates yv, ye (LDS):
+// Ec + Emv.v^ + 1/2 v^T EMv v^ + Eme.e^.  Lane i < 64 of the first wave forms coordinate i's terms,
+// the lanes are summed by a fixed butterfly and lane 0's value is broadcast through red[0].
+__device__ __noinline__ double reduced_energy(const WinDev& W, const double* yv, const double* ye, double* red) {
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        double acc = 0.0;
+        if (tid < W.n[1]) {
+            double r = 0.0;
+            for (int j = 0; j < W.n[1]; ++j) r += W.EMv[(int64_t)j * W.n[1] + tid] * yv[j];
+            acc = yv[tid] * (W.Emv[tid] + 0.5 * r);
+        }
+        if (tid < W.n[2]) acc += W.Eme[tid] * ye[tid];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (tid == 0) red[0] = W.Ec[0] + acc;
+    }
+    __syncthreads();
+    const double E = red[0];
+    __syncthreads();
+    return E;
+}
+
 // Instance and workgroup of a block.  With xcd_map, the G workgroups of
 // instance i are the blocks 8 ((i / 8) G + g) + i % 8, g < G, which the
 // round-robin dispatch puts on one XCD; the grid then has 8 ceil(n_inst / 8) G
@@ -960,6 +988,13 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             fallen = 0;
             tau_est = INFINITY;
         }
+        if (g == 0) {  // energy diagnostic of the accepted state, kept by the workgroup that writes the state
+            const double E = reduced_energy(I.win[w], S.y[1], S.y[2], S.red);
+            if (tid == 0) {
+                st.energy = E;
+                st.energy_dev = fmax(st.energy_dev, fabs(E - st.energy0));
+            }
+        }
         if (replay)
             done = n_steps >= A.n_replay;
         else
@@ -1164,7 +1199,34 @@ __global__ void reset_state_kernel(lh_rom_state* st, int n, double dt) {
         for (int k = 0; k < LH_NMAX; ++k) z.yhat[f][k] = 0.0;
     z.tau_est = INFINITY;
     z.since = z.fallen = z.n_audits = z.n_surrogate_steps = z.n_fallbacks = z.pad_ = 0;
+    z.energy = z.energy0 = z.energy_dev = 0.0;
     st[i] = z;
+}
+
+// energy, energy0 of instance blockIdx.x at its initial coordinates in window 0; energy_dev = 0
+__global__ void __launch_bounds__(256) init_energy_kernel(const InstDev* inst, lh_rom_state* st) {
+    __shared__ double y[2][LH_NMAX];
+    __shared__ double red[1];
+    const int i = blockIdx.x;
+    for (int k = threadIdx.x; k < LH_NMAX; k += blockDim.x) {
+        y[0][k] = st[i].yhat[1][k];
+        y[1][k] = st[i].yhat[2][k];
+    }
+    __syncthreads();
+    const double E = reduced_energy(inst[i].win[0], y[0], y[1], red);
+    if (threadIdx.x == 0) {
+        st[i].energy = E;
+        st[i].energy0 = E;
+        st[i].energy_dev = 0.0;
+    }
+}
+
+// c[0] = 1/2 c[1] + c[2]
+__global__ void energy_const_kernel(double* c) { c[0] = 0.5 * c[1] + c[2]; }
+
+__global__ void fill_kernel(double* p, double v, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
 }
 
 // y = os + Phi y^
@@ -1194,6 +1256,8 @@ struct PrevOs {
     double* os = nullptr;                         // [2 N_V + N_E] x, v, e offsets in use
     double* os_loc[3] = {nullptr, nullptr, nullptr};  // [max n_el][rows_f] element-local rows of the current window
     double* bx = nullptr;                         // [LH_NMAX] Phi_x^T v_os of the current window
+    double* Emv = nullptr;                        // [LH_NMAX] Phi_v^T M_V v_os of the current window
+    double* Ec = nullptr;                         // [3] energy constant of the current window
 };
 
 }  // namespace rom
@@ -1250,12 +1314,43 @@ static int upload(lh_rom* R, const std::vector<T>& h, const T** out, std::vector
 
 static unsigned nb(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// Energy terms of a window in reduced form (the total energy of Sec. 2.2.1 with the reduced mass
+// matrix of eq. rmass, Sec. 3.2): EMv = Phi_v^T M_V Phi_v (column-major n_v x n_v), Emv = Phi_v^T M_V
+// v_os, Eme = Phi_e^T M_E 1 and Ec[0] = 1/2 v_os^T M_V v_os + 1^T M_E e_os, with M_V the kinematic mass
+// matrix without wall elimination.  EMv and Eme may be null (only the offset-dependent terms are
+// formed).  scratch: 2 N_V + N_E doubles.
+static int energy_terms(const lh_problem* p, const double* phi_v, int nv, const double* v_os, const double* phi_e,
+                        int ne, const double* e_os, double* EMv, double* Emv, double* Eme, double* Ec,
+                        double* scratch, hipStream_t s) {
+    const int64_t NV = p->NV, NE = p->NE;
+    double* MP = scratch;
+    double* Mos = scratch + NV;
+    double* Me1 = scratch + 2 * NV;
+    int rc;
+    if ((rc = mass_apply_v_full(p, v_os, Mos, s))) return rc;
+    hipLaunchKernelGGL(gemm_tn_kernel, dim3(nv, 1), dim3(256), 0, s, phi_v, Mos, NV, NV, NV, nv, Emv);
+    if (EMv) {
+        for (int k = 0; k < nv; ++k) {
+            if ((rc = mass_apply_v_full(p, phi_v + (int64_t)k * NV, MP, s))) return rc;
+            hipLaunchKernelGGL(gemm_tn_kernel, dim3(nv, 1), dim3(256), 0, s, phi_v, MP, NV, NV, NV, nv,
+                               EMv + (int64_t)k * nv);
+        }
+    }
+    hipLaunchKernelGGL(fill_kernel, dim3(nb(NE)), dim3(256), 0, s, MP, 1.0, NE);
+    if ((rc = lh_mass_apply_e(p, MP, Me1, s))) return rc;
+    if (Eme) hipLaunchKernelGGL(gemm_tn_kernel, dim3(ne, 1), dim3(256), 0, s, phi_e, Me1, NE, NE, NE, ne, Eme);
+    hipLaunchKernelGGL(gemm_tn_kernel, dim3(1, 1), dim3(256), 0, s, v_os, Mos, NV, NV, NV, 1, Ec + 1);
+    hipLaunchKernelGGL(gemm_tn_kernel, dim3(1, 1), dim3(256), 0, s, Me1, e_os, NE, NE, NE, 1, Ec + 2);
+    hipLaunchKernelGGL(energy_const_kernel, dim3(1), dim3(1), 0, s, Ec);
+    return launch_check("rom_create energy terms");
+}
+
 // Build the device tables of one window and its host structure.
 static int oblique_transition(lh_rom* R, const lh_problem* p, int f, const lh_window_desc& wd,
                               const lh_window_desc* prev, double* T, double* c, hipStream_t s);
 
 static int build_window(lh_rom* R, const lh_problem* p, const lh_window_desc& wd, const lh_window_desc* prev,
-                        int window_ic, WinDev& W, HostWin& H, hipStream_t s) {
+                        int window_ic, WinDev& W, HostWin& H, double* escratch, hipStream_t s) {
     const int dim = p->dim;
     const int NK = dim == 3 ? 27 : 9, NT = dim == 3 ? 8 : 4, NKD = NK * dim;
     const int64_t NV = p->NV, NE = p->NE, nn = p->n_nodes;
@@ -1393,6 +1488,17 @@ static int build_window(lh_rom* R, const lh_problem* p, const lh_window_desc& wd
     hipLaunchKernelGGL(gemm_tn_kernel, dim3(W.n[0], 1), dim3(256), 0, s, wd.phi[0], wd.os[1], NV, NV, NV, W.n[0], bx);
     W.Bxv = bxv;
     W.bx = bx;
+    double *EMv, *Emv, *Eme, *Ec;
+    if ((rc = dev_alloc(R, &EMv, (int64_t)W.n[1] * W.n[1])) || (rc = dev_alloc(R, &Emv, W.n[1])) ||
+        (rc = dev_alloc(R, &Eme, W.n[2])) || (rc = dev_alloc(R, &Ec, 3)))
+        return rc;
+    if ((rc = energy_terms(p, wd.phi[1], W.n[1], wd.os[1], wd.phi[2], W.n[2], wd.os[2], EMv, Emv, Eme, Ec, escratch,
+                           s)))
+        return rc;
+    W.EMv = EMv;
+    W.Emv = Emv;
+    W.Eme = Eme;
+    W.Ec = Ec;
     for (int f = 0; f < 3; ++f) {
         W.T[f] = nullptr;
         W.c[f] = nullptr;
@@ -1633,6 +1739,16 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
     };
     int max_el = 0;
     R->alias.assign(n_inst, -1);
+    // scratch of the per-window energy terms, freed before returning
+    double* escratch = nullptr;
+    if (hipMalloc(&escratch, sizeof(double) * (2 * p->NV + p->NE)) != hipSuccess) {
+        set_error("rom_create: hipMalloc failed");
+        return fail(LH_EDEVICE);
+    }
+    struct FreeOnExit {
+        double* q;
+        ~FreeOnExit() { (void)hipFree(q); }
+    } free_escratch{escratch};
     for (int i = 0; i < n_inst; ++i) {
         const lh_instance_desc& d = inst[i];
         if (d.n_windows < 1 || !d.windows || !(d.t_final > 0.0)) {
@@ -1666,7 +1782,7 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
         R->h_struct[i].resize(d.n_windows);
         for (int w = 0; w < d.n_windows; ++w) {
             int rc = build_window(R, p, d.windows[w], w > 0 ? &d.windows[w - 1] : nullptr, d.window_ic,
-                                  R->h_win[i][w], R->h_struct[i][w], s);
+                                  R->h_win[i][w], R->h_struct[i][w], escratch, s);
             if (rc) return fail(rc);
             max_el = std::max(max_el, R->h_win[i][w].n_el);
         }
@@ -1712,7 +1828,8 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
         if (I.prev_os) {
             PrevOs& P = R->prev[i];
             const int NKD = dim * (dim == 2 ? 9 : 27), NT = dim == 2 ? 4 : 8;
-            if ((rc = dev_alloc(R, &P.os, 2 * p->NV + p->NE)) || (rc = dev_alloc(R, &P.bx, LH_NMAX)))
+            if ((rc = dev_alloc(R, &P.os, 2 * p->NV + p->NE)) || (rc = dev_alloc(R, &P.bx, LH_NMAX)) ||
+                (rc = dev_alloc(R, &P.Emv, LH_NMAX)) || (rc = dev_alloc(R, &P.Ec, 3)))
                 return fail(rc);
             for (int f = 0; f < 3; ++f)
                 if ((rc = dev_alloc(R, &P.os_loc[f], (int64_t)ie * (f == 2 ? NT : NKD)))) return fail(rc);
@@ -1779,6 +1896,7 @@ int rom_init_state(const lh_rom* R, const lh_instance_desc* inst, const double* 
                                    R->prev[i].os + (f > 0 ? p->NV : 0) + (f > 1 ? p->NV : 0), N);
         }
     }
+    hipLaunchKernelGGL(init_energy_kernel, dim3(R->n_inst), dim3(256), 0, s, R->d_inst, state);
     return launch_check("rom_init_state");
 }
 
@@ -1987,9 +2105,24 @@ int rom_switch_window_previous(lh_rom* R, lh_rom_state* state, int32_t inst, con
     }
     hipLaunchKernelGGL(gemm_tn_kernel, dim3(Wn.n[0], 1), dim3(256), 0, s, Wn.phi[0], os[1], p->NV, p->NV, p->NV,
                        Wn.n[0], P.bx);
+    {  // offset-dependent energy terms of window w + 1 (the lifted state's energy is unchanged by the switch)
+        double* scratch = nullptr;
+        if (hipMalloc(&scratch, sizeof(double) * (2 * p->NV + p->NE)) != hipSuccess) {
+            set_error("rom_switch_window_previous: hipMalloc failed");
+            return LH_EDEVICE;
+        }
+        const int rc = energy_terms(p, Wn.phi[1], Wn.n[1], os[1], Wn.phi[2], Wn.n[2], os[2], nullptr, P.Emv, nullptr,
+                                    P.Ec, scratch, s);
+        const hipError_t se = hipStreamSynchronize(s);
+        (void)hipFree(scratch);
+        if (rc) return rc;
+        LH_HIP_CHECK(se);
+    }
     WinDev& D = R->h_win[inst][w + 1];
     for (int f = 0; f < 3; ++f) D.os_loc[f] = P.os_loc[f];
     D.bx = P.bx;
+    D.Emv = P.Emv;
+    D.Ec = P.Ec;
     // the reduced state restarts at zero in window w + 1 (surrogate bookkeeping as at any window change)
     h.w = w + 1;
     for (int f = 0; f < 3; ++f)

@@ -7,8 +7,10 @@ fallback: if the library is missing or no GPU is visible, loading raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import torch
 
@@ -67,7 +69,8 @@ class RomState(C.Structure):
                 ("n_steps", C.c_int32), ("n_rejected", C.c_int32), ("n_force_evals", C.c_int32),
                 ("done", C.c_int32), ("yhat", (C.c_double * LH_NMAX) * 3), ("tau_est", C.c_double),
                 ("since", C.c_int32), ("fallen", C.c_int32), ("n_audits", C.c_int32),
-                ("n_surrogate_steps", C.c_int32), ("n_fallbacks", C.c_int32), ("pad_", C.c_int32)]
+                ("n_surrogate_steps", C.c_int32), ("n_fallbacks", C.c_int32), ("pad_", C.c_int32),
+                ("energy", C.c_double), ("energy0", C.c_double), ("energy_dev", C.c_double)]
 
 
 ROM_STATE_BYTES = C.sizeof(RomState)
@@ -129,6 +132,28 @@ _SIGNATURES = {
 }
 
 _LIB = None
+# Live handles by kind, destroyed in this order at interpreter exit (networks and ROMs before the
+# problems they use), while the HIP runtime is still up; afterwards __del__ does nothing.
+_LIVE = {"rom": weakref.WeakSet(), "mlp": weakref.WeakSet(), "problem": weakref.WeakSet()}
+
+
+def _register(kind, obj):
+    _LIVE[kind].add(obj)
+
+
+def _shutdown():
+    global _LIB
+    if _LIB is None:
+        return
+    try:
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except RuntimeError:
+        pass
+    for kind in ("rom", "mlp", "problem"):
+        for obj in list(_LIVE[kind]):
+            obj.close()
+    _LIB = None
 
 
 def load(path: str = LIB_PATH):
@@ -146,6 +171,7 @@ def load(path: str = LIB_PATH):
         fn.restype = res
         fn.argtypes = args
     _LIB = so
+    atexit.register(_shutdown)  # runs before torch's own exit handlers, which were registered earlier
     return so
 
 
@@ -196,6 +222,7 @@ class Problem:
         h = C.c_void_p()
         _check(lib.lh_problem_create(C.byref(d), C.byref(h)))
         self.h = h
+        _register("problem", self)
         nv, ne, nel_, nn = _I64(), _I64(), _I64(), _I64()
         _check(lib.lh_problem_sizes(h, C.byref(nv), C.byref(ne), C.byref(nel_), C.byref(nn)))
         self.NV, self.NE, self.n_elem, self.n_nodes = nv.value, ne.value, nel_.value, nn.value
@@ -208,10 +235,12 @@ class Problem:
         kw.update(over)
         return cls(wl.dim, wl.nel, wl.lo, wl.hi, wl.problem, wl.gamma, wl.use_av, wl.cfl, **kw)
 
-    def __del__(self):
+    def close(self):
         if getattr(self, "h", None) is not None and _LIB is not None:
             _LIB.lh_problem_destroy(self.h)
-            self.h = None
+        self.h = None
+
+    __del__ = close
 
     def initial_state(self):
         x, v, e = _f64(self.NV), _f64(self.NV), _f64(self.NE)
@@ -395,13 +424,16 @@ class Rom:
         h = C.c_void_p()
         _check(lib.rom_create(problem.h, len(instances), descs, C.byref(h), stream_handle()))
         self.h = h
+        _register("rom", self)
         self.n_inst = len(instances)
         self.state = torch.zeros((self.n_inst, ROM_STATE_BYTES), dtype=torch.uint8, device="cuda")
 
-    def __del__(self):
+    def close(self):
         if getattr(self, "h", None) is not None and _LIB is not None:
             _LIB.rom_destroy(self.h)
-            self.h = None
+        self.h = None
+
+    __del__ = close
 
     def init_state(self, x0, v0, e0, dt0=0.0):
         _check(load().rom_init_state(self.h, self.descs, ptr(x0), ptr(v0), ptr(e0), float(dt0), ptr(self.state),
@@ -504,14 +536,17 @@ class Mlp:
         h = C.c_void_p()
         _check(lib.mlp_create(C.byref(d), int(max_batch), C.byref(h)))
         self.h = h
+        _register("mlp", self)
         self.sizes = [int(n) for n in sizes]
         self.L = len(sizes) - 1
         self.max_batch = int(max_batch)
 
-    def __del__(self):
+    def close(self):
         if getattr(self, "h", None) is not None and _LIB is not None:
             _LIB.mlp_destroy(self.h)
-            self.h = None
+        self.h = None
+
+    __del__ = close
 
     def set_params(self, W=None, b=None, mu_in=None, s_in=None, mu_out=None, s_out=None):
         """W, b: lists of FP64 device tensors (W[l] of shape (sizes[l], sizes[l+1]))."""
