@@ -126,6 +126,24 @@ int fom_force(const lh_problem* p, const double* x, const double* v, const doubl
               const int32_t* elems, int32_t n_elems, uint32_t ops, double* F1, double* Ftv, double* tau_min,
               void* work, size_t work_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): fom_force
+ * with the same arguments, results and errors, minus the workspace.  Its
+ * scratch (element-local F.1 rows, and the stored stress of LH_KEEP_STRESS /
+ * LH_USE_STRESS) is a static device array of fom_force_noalloc_max_bytes()
+ * bytes (64 MiB) that each GPU holds until the process ends; a problem whose
+ * element-local F.1 (n_elem * (2^d ... 3^d nodes) * d doubles), plus the
+ * stored stress (n_elem * 4^d * d^2 doubles) when one of the stress flags is
+ * set, exceeds it is rejected with LH_EINVAL before anything is launched.
+ * The call allocates nothing.  Every call on a GPU shares that GPU's array
+ * and leaves its contents there (LH_USE_STRESS reads the stress of the last
+ * LH_KEEP_STRESS call on the device), so calls that overlap on one GPU, on
+ * any streams, race; order them on one stream. */
+size_t fom_force_noalloc_max_bytes(void);
+int fom_force_noalloc(const lh_problem* p, const double* x, const double* v, const double* e, const double* v_c,
+                      const int32_t* elems, int32_t n_elems, uint32_t ops, double* F1, double* Ftv,
+                      double* tau_min, hipStream_t stream);
+
 /* Kinematic mass solve out = M_V^{-1} rhs with the wall-constrained rows
  * eliminated (constrained entries of out are zero), and thermodynamic mass
  * solve out = M_E^{-1} rhs (eq. fom).  rhs and out (dev) may alias. */

@@ -12,6 +12,8 @@
 // contributions in a fixed order, so results are bitwise reproducible.
 #include "internal.hpp"
 
+#include <string>
+
 namespace lh {
 
 struct ForceArgs {
@@ -246,21 +248,43 @@ static size_t stress_bytes(const lh_problem* p) {
     return sizeof(double) * (size_t)p->n_elem * nq * p->dim * p->dim;
 }
 
-}  // namespace lh
+// Scratch of fom_force_noalloc: the element-local F.1 rows (and, with
+// LH_KEEP_STRESS / LH_USE_STRESS, the stored stress) of the last call on the
+// device.  Each device holds its own copy of the array; host code reaches it
+// only through the address hipGetSymbolAddress returns on that device.
+constexpr size_t FORCE_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[FORCE_SCRATCH_BYTES];
 
-extern "C" {
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mtx;
+static void* g_scratch_addr[MAX_DEVICES];
 
-size_t lh_fom_force_workspace_size(const lh_problem* p) {
-    if (!p) return 0;
-    return lh::f1_loc_bytes(p) + lh::stress_bytes(p) + 256;
+// Device address of the current device's scratch, looked up once per device
+// with that device current.
+static int force_scratch(void** out) {
+    int dev = 0;
+    LH_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        set_error("fom_force_noalloc: device ordinal out of range");
+        return LH_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mtx);
+    if (!g_scratch_addr[dev]) {
+        void* ptr = nullptr;
+        LH_HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) {
+            set_error("fom_force_noalloc: no device address for the scratch array");
+            return LH_EDEVICE;
+        }
+        g_scratch_addr[dev] = ptr;
+    }
+    *out = g_scratch_addr[dev];
+    return LH_OK;
 }
 
-int fom_force(const lh_problem* p, const double* x, const double* v, const double* e, const double* v_c,
-              const int32_t* elems, int32_t n_elems, uint32_t ops, double* F1, double* Ftv, double* tau_min,
-              void* work, size_t work_bytes, hipStream_t stream) {
-    using namespace lh;
-    LH_REQUIRE(p, "fom_force: null problem");
-    LH_REQUIRE(work_bytes >= lh_fom_force_workspace_size(p) && work, "fom_force: workspace too small");
+static int force_launch(const lh_problem* p, const double* x, const double* v, const double* e, const double* v_c,
+                        const int32_t* elems, int32_t n_elems, uint32_t ops, double* F1, double* Ftv,
+                        double* tau_min, void* work, hipStream_t stream) {
     const bool use_stress = (ops & LH_USE_STRESS) != 0;
     LH_REQUIRE(!use_stress || (ops & ~(uint32_t)(LH_USE_STRESS | LH_FTV | LH_NO_BC)) == 0,
                "fom_force: LH_USE_STRESS allows only LH_FTV");
@@ -330,6 +354,45 @@ int fom_force(const lh_problem* p, const double* x, const double* v, const doubl
         return launch_check("gather_f1_kernel");
     }
     return LH_OK;
+}
+
+}  // namespace lh
+
+extern "C" {
+
+size_t lh_fom_force_workspace_size(const lh_problem* p) {
+    if (!p) return 0;
+    return lh::f1_loc_bytes(p) + lh::stress_bytes(p) + 256;
+}
+
+int fom_force(const lh_problem* p, const double* x, const double* v, const double* e, const double* v_c,
+              const int32_t* elems, int32_t n_elems, uint32_t ops, double* F1, double* Ftv, double* tau_min,
+              void* work, size_t work_bytes, hipStream_t stream) {
+    using namespace lh;
+    LH_REQUIRE(p, "fom_force: null problem");
+    LH_REQUIRE(work_bytes >= lh_fom_force_workspace_size(p) && work, "fom_force: workspace too small");
+    return force_launch(p, x, v, e, v_c, elems, n_elems, ops, F1, Ftv, tau_min, work, stream);
+}
+
+size_t fom_force_noalloc_max_bytes(void) { return lh::FORCE_SCRATCH_BYTES; }
+
+int fom_force_noalloc(const lh_problem* p, const double* x, const double* v, const double* e, const double* v_c,
+                      const int32_t* elems, int32_t n_elems, uint32_t ops, double* F1, double* Ftv, double* tau_min,
+                      hipStream_t stream) {
+    using namespace lh;
+    LH_REQUIRE(p, "fom_force_noalloc: null problem");
+    const bool stress = (ops & (LH_KEEP_STRESS | LH_USE_STRESS)) != 0;
+    const size_t need = f1_loc_bytes(p) + (stress ? stress_bytes(p) : 0);
+    if (need > FORCE_SCRATCH_BYTES) {
+        set_error("fom_force_noalloc: the problem needs " + std::to_string(need) +
+                  " bytes of scratch (element-local F.1" + std::string(stress ? " and stored stress" : "") +
+                  "), more than the static " + std::to_string(FORCE_SCRATCH_BYTES) + "; use fom_force");
+        return LH_EINVAL;
+    }
+    void* w = nullptr;
+    const int rc = force_scratch(&w);
+    if (rc) return rc;
+    return force_launch(p, x, v, e, v_c, elems, n_elems, ops, F1, Ftv, tau_min, w, stream);
 }
 
 }  // extern "C"

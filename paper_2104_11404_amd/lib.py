@@ -84,6 +84,8 @@ _SIGNATURES = {
     "lh_initial_state": (_I32, [_VP, _VP, _VP, _VP, _VP]),
     "lh_fom_force_workspace_size": (_SZ, [_VP]),
     "fom_force": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _I32, _U32, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "fom_force_noalloc_max_bytes": (_SZ, []),
+    "fom_force_noalloc": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _I32, _U32, _VP, _VP, _VP, _VP]),
     "lh_mass_solve_v": (_I32, [_VP, _VP, _VP, _VP]),
     "lh_mass_solve_e": (_I32, [_VP, _VP, _VP, _VP]),
     "lh_total_energy": (_I32, [_VP, _VP, _VP, C.POINTER(_D), _VP]),
@@ -256,6 +258,14 @@ class Problem:
         el = None if elems is None or n_el == 0 else ptr(elems)
         _check(load().fom_force(self.h, ptr(x), ptr(v), ptr(e), ptr(vc), el, n_el, ops, ptr(F1), ptr(Ftv),
                                 ptr(tau), ptr(ws), ws.numel(), stream_handle()))
+        return F1, Ftv, tau
+
+    def fom_force_noalloc(self, x, v, e, F1, Ftv, tau, vc=None, elems=None, ops=LH_F1 | LH_FTV | LH_TAU):
+        """fom_force on the library's static scratch: outputs are the caller's, nothing is allocated."""
+        n_el = -1 if elems is None else int(elems.numel())
+        el = None if elems is None or n_el == 0 else ptr(elems)
+        _check(load().fom_force_noalloc(self.h, ptr(x), ptr(v), ptr(e), ptr(vc), el, n_el, ops, ptr(F1), ptr(Ftv),
+                                        ptr(tau), stream_handle()))
         return F1, Ftv, tau
 
     def mass_solve_v(self, rhs, out=None):
