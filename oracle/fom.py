@@ -14,7 +14,9 @@ stress  sigma~_q = w_q det J_q sigma_q J_q^{-T}  at quadrature point q,
     (F^T.u)_j     = sum_q phi_j(q) sum_{c,i} sigma~_q[c, i] (sum_a u_{a,c} dN_a/dxi_i(q)).
 
 Stress: sigma = -p I + mu eps(v), p = (gamma-1) rho e (eq. EOS),
-eps = sym grad v, rho_q = rho0 det J0 / det J (Lagrangian mass conservation).
+eps = sym grad v, rho_q = rho0 det J0 / det J (Lagrangian mass conservation);
+rho0 and gamma are the element's (piecewise constant in the triple-point
+problem, uniform otherwise).
 Artificial viscosity (reading; the paper refers to Dobrev Sec. 6):
 
     mu = rho l^2 q2 max(0, -lambda_min(eps)) + rho l q1 c_s psi0,
@@ -37,7 +39,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .fe import ORDER, Mesh, ref_tables
-from .problems import Problem, initial_state
+from .problems import Problem, element_material, initial_state
 
 ALPHA_MU = 2.5
 BETA1 = 0.85
@@ -61,6 +63,7 @@ class Operator:
     en: np.ndarray  # (E, nk) element -> global node
     et: np.ndarray  # (E, nt) element -> thermo dof
     cq: np.ndarray  # (E, nq) rho0 det J0 w_q
+    gamma_e: np.ndarray  # (E,) adiabatic index of each element
     Mv_scalar: sp.csr_matrix  # scalar Q2 mass matrix
     Mv: sp.csr_matrix  # d copies (component-major), no elimination
     Mv_eff: sp.csc_matrix  # eliminated
@@ -95,8 +98,8 @@ def build_operator(prob: Problem) -> Operator:
     x0, _, _ = initial_state(prob)
     J0 = _element_geometry(ref, en, x0, mesh.n_nodes, d)
     det0 = np.linalg.det(J0)
-    rho0 = 1.0
-    cq = rho0 * det0 * ref.w[None, :]
+    rho0, gamma_e = element_material(prob)
+    cq = rho0[:, None] * det0 * ref.w[None, :]
     # scalar kinematic mass: sum_q cq N_a N_b
     Mloc = np.einsum("eq,qa,qb->eab", cq, ref.B, ref.B)
     nk = en.shape[1]
@@ -110,7 +113,7 @@ def build_operator(prob: Problem) -> Operator:
     # thermodynamic mass: block diagonal, sum_q cq phi_i phi_j
     Meloc = np.einsum("eq,qi,qj->eij", cq, ref.Bt, ref.Bt)
     Me = sp.block_diag(list(Meloc), format="csr")
-    op = Operator(prob, mesh, ref, en, et, cq, Ms, Mv, Mv_eff, Me, constrained)
+    op = Operator(prob, mesh, ref, en, et, cq, gamma_e, Ms, Mv, Mv_eff, Me, constrained)
     op._me_inv = np.linalg.inv(Meloc)
     return op
 
@@ -143,7 +146,7 @@ def stress(op: Operator, x, v, e, elems=None) -> Stress:
     w = ref.w[None, :]
     rho = cq / (w * det)
     eq = np.einsum("ej,qj->eq", e[et], ref.Bt)
-    g = prob.gamma
+    g = (op.gamma_e if elems is None else op.gamma_e[elems])[:, None]
     p = (g - 1.0) * rho * eq
     cs = np.sqrt(np.maximum(g * (g - 1.0) * eq, 0.0))
     hmin = np.linalg.svd(J, compute_uv=False)[..., -1] / ORDER
@@ -210,6 +213,7 @@ class StepResult:
     vh: np.ndarray
     eh: np.ndarray
     tau: float
+    stages: list = field(default_factory=list)  # every stage state the force was evaluated at, after y_n
 
 
 def rk2avg_step(op: Operator, x, v, e, dt) -> StepResult:
@@ -225,6 +229,31 @@ def rk2avg_step(op: Operator, x, v, e, dt) -> StepResult:
     xn = x + dt * vbar
     tau = min(float(np.min(s1.tau)), float(np.min(s2.tau)))
     return StepResult(xn, vn, en_, xh, vh, eh, tau)
+
+
+def rhs(op: Operator, x, v, e):
+    """Right-hand side of eq. fom at one state, (dx/dt, dv/dt, de/dt) = (v, -M_V^{-1} F.1, M_E^{-1} F^T.v),
+    the force contracted with the state's own velocity; and the state's step estimate."""
+    st = stress(op, x, v, e)
+    return (v, -op.solve_v(force_one(op, st)), op.solve_e(force_tv(op, st, v))), float(np.min(st.tau))
+
+
+def rk4_step(op: Operator, x, v, e, dt) -> StepResult:
+    """One classical RK4 step (eq. RK4, eq. RK4coeff) of the whole state y = (x, v, e):
+    k1 = f(y), k2 = f(y + dt/2 k1), k3 = f(y + dt/2 k2), k4 = f(y + dt k3),
+    y_{n+1} = y + dt/6 (k1 + 2 k2 + 2 k3 + k4).  tau is the minimum over the four stages.  The
+    returned stage state (xh, vh, eh) is y + dt/2 k1, the half-step state of the first stage, and
+    ``stages`` holds the three stage states y + dt/2 k1, y + dt/2 k2, y + dt k3."""
+    y = (x, v, e)
+    k1, t1 = rhs(op, *y)
+    y2 = tuple(a + 0.5 * dt * k for a, k in zip(y, k1))
+    k2, t2 = rhs(op, *y2)
+    y3 = tuple(a + 0.5 * dt * k for a, k in zip(y, k2))
+    k3, t3 = rhs(op, *y3)
+    y4 = tuple(a + dt * k for a, k in zip(y, k3))
+    k4, t4 = rhs(op, *y4)
+    yn = tuple(a + dt / 6.0 * (p + 2.0 * q + 2.0 * r + s) for a, p, q, r, s in zip(y, k1, k2, k3, k4))
+    return StepResult(yn[0], yn[1], yn[2], y2[0], y2[1], y2[2], min(t1, t2, t3, t4), [y2, y3, y4])
 
 
 def final_step_clip(t, t_final, dt):
@@ -248,23 +277,31 @@ class Trajectory:
     snaps: list = field(default_factory=list)  # (x, v, e) at stage and step states
     snap_kind: list = field(default_factory=list)  # 0 = stage n+1/2, 1 = step n+1
     snap_step: list = field(default_factory=list)  # step index n+1 the snapshot belongs to
+    r: int = 2  # snapshots per accepted step: its stage states, then its step state
     rejections: int = 0
     energy: list = field(default_factory=list)
 
 
 def run_fom(op: Operator, t_final: float, fixed_dt=None, dt_replay=None, record=True,
-            max_steps=10**7) -> Trajectory:
-    """Integrate the FOM from t = 0 to t_final with RK2-average.
+            max_steps=10**7, scheme="rk2avg") -> Trajectory:
+    """Integrate the FOM from t = 0 to t_final with RK2-average (eq. RK2-avg) or, with scheme="rk4",
+    classical RK4 (eq. RK4).  Snapshots of every accepted step are the stage states its forces were
+    evaluated at after y_n, then the step state: r = 2 per step for RK2-average (y_{n+1/2}, y_{n+1}),
+    r = 4 for RK4 (y_n + h/2 k1, y_n + h/2 k2, y_n + h k3, y_{n+1}), so that every stage increment
+    lies in the snapshots' span.
 
     Step control (Sec. 2.2.3): attempt h = min(dt, t_final - t); if h >= tau
-    (tau = min over the quadrature points of both stages) reject and retry
+    (tau = min over the quadrature points of all stages) reject and retry
     with dt = beta1 h; otherwise accept and, if h <= gamma tau, grow the next
     step to beta2 h.  The first dt is beta1 tau(y_0).  With ``fixed_dt`` no
     step is rejected; with ``dt_replay`` the given step sizes are used.
     """
+    if scheme not in ("rk2avg", "rk4"):
+        raise ValueError(scheme)
+    step = rk4_step if scheme == "rk4" else rk2avg_step
     x, v, e = initial_state(op.prob)
     t = 0.0
-    tr = Trajectory([0.0], [], x, v, e)
+    tr = Trajectory([0.0], [], x, v, e, r=4 if scheme == "rk4" else 2)
     tr.energy.append(total_energy(op, v, e))
     if fixed_dt is not None:
         dt = fixed_dt
@@ -273,7 +310,7 @@ def run_fom(op: Operator, t_final: float, fixed_dt=None, dt_replay=None, record=
     n = 0
     while (not_done(t, t_final) if dt_replay is None else n < len(dt_replay)) and n < max_steps:
         h = dt_replay[n] if dt_replay is not None else final_step_clip(t, t_final, dt)
-        r = rk2avg_step(op, x, v, e, h)
+        r = step(op, x, v, e, h)
         if fixed_dt is None and dt_replay is None:
             if h >= r.tau:
                 dt = BETA1 * h
@@ -281,10 +318,16 @@ def run_fom(op: Operator, t_final: float, fixed_dt=None, dt_replay=None, record=
                 continue
             dt = BETA2 * h if h <= GAMMA_DT * r.tau else h
         if record:
-            tr.snap_t += [t + 0.5 * h, t + h]
-            tr.snaps += [(r.xh, r.vh, r.eh), (r.x, r.v, r.e)]
-            tr.snap_kind += [0, 1]
-            tr.snap_step += [n + 1, n + 1]
+            if scheme == "rk4":
+                tr.snap_t += [t + 0.5 * h, t + 0.5 * h, t + h, t + h]
+                tr.snaps += [*r.stages, (r.x, r.v, r.e)]
+                tr.snap_kind += [0, 0, 0, 1]
+                tr.snap_step += [n + 1] * 4
+            else:
+                tr.snap_t += [t + 0.5 * h, t + h]
+                tr.snaps += [(r.xh, r.vh, r.eh), (r.x, r.v, r.e)]
+                tr.snap_kind += [0, 1]
+                tr.snap_step += [n + 1, n + 1]
         x, v, e = r.x, r.v, r.e
         t = t + h
         n += 1

@@ -4,7 +4,7 @@ Each problem fixes the domain, the adiabatic index, whether artificial
 viscosity is used, and the initial velocity, density and pressure (Sec. 6.1).
 Velocities are interpolated at the Q2 nodes, the specific internal energy
 e = p / ((gamma - 1) rho) (eq. EOS) at the Q1 nodes, positions are the node
-coordinates, and rho0 = 1 everywhere in all problems used here.
+coordinates, and rho0 = 1 everywhere except in the triple-point problem.
 
 Readings where the paper is silent or garbled:
 
@@ -19,6 +19,14 @@ Readings where the paper is silent or garbled:
 * Sedov: the delta source is modelled by giving every thermodynamic dof of
   the element at the origin the value E / (rho0 |K|), so that the total
   internal energy equals E.
+* Triple point (Sec. 6.1.4): density, pressure and adiabatic index are
+  piecewise constant over three regions of [0,7] x [0,3] (x [0,1.5]).  The
+  material of an element (its rho0, gamma and initial pressure) is the one
+  at the element's centre, so rho0 and gamma are constant per element and
+  the thermodynamic dofs of an element share its pressure.  On meshes whose
+  faces contain the interfaces x = 1 and y = 1.5 this is the printed data
+  exactly; the interfaces' own points, which the paper assigns with <= and
+  >, are never evaluated.  Every other problem has rho0 = 1 and one gamma.
 """
 from __future__ import annotations
 
@@ -31,7 +39,7 @@ from .fe import Q1_NODES_1D, Mesh
 
 @dataclass(frozen=True)
 class Problem:
-    name: str  # "taylor_green", "sedov", "gresho"
+    name: str  # "taylor_green", "sedov", "gresho", "triple_point"
     mesh: Mesh
     gamma: float
     use_av: bool
@@ -39,6 +47,33 @@ class Problem:
     amp: float = 1.0  # TG / Gresho amplitude
     p_bg: float = 3.0 + 4.0 * np.log(2.0)  # Gresho background pressure
     energy: float = 0.25  # Sedov deposited energy
+
+
+def triple_point_regions(X: np.ndarray):
+    """(rho0, gamma, p0) of the triple-point problem at positions X (n, d), Sec. 6.1.4:
+    rho0 = 1 where x <= 1 or y <= 1.5, else 1/8; p0 = 1 where x <= 1, else 0.1;
+    gamma = 1.5 where x <= 1 or y > 1.5, else 1.4."""
+    x, y = X[:, 0], X[:, 1]
+    left = x <= 1.0
+    top = y > 1.5
+    rho = np.where(left | ~top, 1.0, 0.125)
+    gamma = np.where(left | top, 1.5, 1.4)
+    p = np.where(left, 1.0, 0.1)
+    return rho, gamma, p
+
+
+def element_centres(mesh: Mesh) -> np.ndarray:
+    E = mesh.elem_coords()
+    return np.array(mesh.lo, float)[None, :] + (E + 0.5) * mesh.h[None, :]
+
+
+def element_material(prob: Problem):
+    """Per-element (rho0, gamma): the triple point's regions at the element centres, else (1, prob.gamma)."""
+    n = prob.mesh.n_elem
+    if prob.name == "triple_point":
+        rho, gamma, _ = triple_point_regions(element_centres(prob.mesh))
+        return rho, gamma
+    return np.ones(n), np.full(n, float(prob.gamma))
 
 
 def thermo_coords(mesh: Mesh) -> np.ndarray:
@@ -72,7 +107,7 @@ def _velocity(prob: Problem, X: np.ndarray) -> np.ndarray:
         vphi = np.where(r < 0.2, 5.0 * r, np.where(r < 0.4, 2.0 - 5.0 * r, 0.0))
         rs = np.where(r > 0, r, 1.0)
         return A * np.stack([-vphi * y / rs, vphi * x / rs], axis=1)
-    if prob.name == "sedov":
+    if prob.name in ("sedov", "triple_point"):
         return np.zeros_like(X)
     raise ValueError(prob.name)
 
@@ -109,7 +144,10 @@ def initial_state(prob: Problem):
     x0 = X.T.reshape(-1).copy()  # component-major
     v0 = _velocity(prob, X).T.reshape(-1).copy()
     rho0 = 1.0
-    if prob.name == "sedov":
+    if prob.name == "triple_point":
+        rho, gamma, p = triple_point_regions(element_centres(mesh))
+        e0 = np.repeat(p / ((gamma - 1.0) * rho), 2 ** d)
+    elif prob.name == "sedov":
         e0 = np.zeros(mesh.NE)
         vol = float(np.prod(mesh.h))
         e0[: 2 ** d] = prob.energy / (rho0 * vol)  # element 0 touches the origin

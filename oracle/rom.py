@@ -241,6 +241,35 @@ def rom_step(op: F.Operator, win: WindowROM, xh, vh, eh, dt):
     return (x_new, v_new, e_new), (x_half, v_half, e_half), tau
 
 
+def rom_step_rk4(op: F.Operator, win: WindowROM, xh, vh, eh, dt):
+    """One classical RK4 step (eq. RK4) of the hyper-reduced SNS system of a window:
+    d x^/dt = b_x + B_xv v^, d v^/dt = -F^1(y~), d e^/dt = F^tv(y~; v~), with y~ the lifted state
+    and the force contracted with the state's own lifted velocity.  Returns new coords, the
+    first stage's half-step coords and tau (the minimum over the four stages)."""
+    mesh = op.mesh
+    NV, NE = mesh.NV, mesh.NE
+    els = win.elems
+
+    def f(xc, vc, ec):
+        lifted = (lift_rows(win, 0, xc, win.rows_k, NV), lift_rows(win, 1, vc, win.rows_k, NV),
+                  lift_rows(win, 2, ec, win.rows_t, NE))
+        st = F.stress(op, *lifted, elems=els)
+        k = (win.bx + win.Bxv @ vc, -(win.A1 @ F.force_one(op, st, elems=els)[win.Z1]),
+             win.A2 @ F.force_tv(op, st, lifted[1], elems=els)[win.Z2])
+        return k, float(np.min(st.tau))
+
+    y = (xh, vh, eh)
+    k1, t1 = f(*y)
+    y2 = tuple(a + 0.5 * dt * k for a, k in zip(y, k1))
+    k2, t2 = f(*y2)
+    y3 = tuple(a + 0.5 * dt * k for a, k in zip(y, k2))
+    k3, t3 = f(*y3)
+    y4 = tuple(a + dt * k for a, k in zip(y, k3))
+    k4, t4 = f(*y4)
+    yn = tuple(a + dt / 6.0 * (p + 2.0 * q + 2.0 * r + s) for a, p, q, r, s in zip(y, k1, k2, k3, k4))
+    return yn, y2, min(t1, t2, t3, t4)
+
+
 @dataclass
 class ROMRun:
     t: list
@@ -327,8 +356,9 @@ def with_offsets(win: WindowROM, os: tuple) -> WindowROM:
 
 
 def run_rom(op: F.Operator, rom: ROM, y0: tuple, t_final: float, dt_replay=None, fixed_dt=None,
-            max_steps=10**7, offsets="given") -> ROMRun:
-    """Online phase from t = 0 to t_final (same step control as the FOM).
+            max_steps=10**7, offsets="given", scheme="rk2avg") -> ROMRun:
+    """Online phase from t = 0 to t_final (same step control as the FOM), with RK2-average
+    (eq. RK2-avg-rom-hr) or, with scheme="rk4", classical RK4 (eq. RK4) of the reduced system.
 
     offsets="given": every window uses the offsets it was built with and the reduced state moves to
     the next window by eq. ic-tw (or ic2-tw).  offsets="previous" (eq. previous_os): the first window
@@ -337,6 +367,9 @@ def run_rom(op: F.Operator, rom: ROM, y0: tuple, t_final: float, dt_replay=None,
     the end."""
     if offsets not in ("given", "previous"):
         raise ValueError(offsets)
+    if scheme not in ("rk2avg", "rk4"):
+        raise ValueError(scheme)
+    step = rom_step_rk4 if scheme == "rk4" else rom_step
     w = 0
     yhat = initial_coords(rom, y0)
     t = 0.0
@@ -361,7 +394,7 @@ def run_rom(op: F.Operator, rom: ROM, y0: tuple, t_final: float, dt_replay=None,
     n = 0
     while (F.not_done(t, t_final) if dt_replay is None else n < len(dt_replay)) and n < max_steps:
         h = dt_replay[n] if dt_replay is not None else F.final_step_clip(t, t_final, dt)
-        new, _, tau = rom_step(op, cur, *yhat, h)
+        new, _, tau = step(op, cur, *yhat, h)
         if fixed_dt is None and dt_replay is None:
             if h >= tau:
                 dt = F.BETA1 * h

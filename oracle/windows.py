@@ -8,7 +8,8 @@ T_w = min_k t_{s_{w-1}(k) + N}(k), times past the last step being t_f.
 
 Reading: the paper's tables count snapshots including the intermediate RK
 stage (N_w = ceil(2 N_t / N_sample) reproduces Table tab:tw), so N = N_sample / r
-steps with r = 2 snapshots per step.
+steps with r = 2 snapshots per step (RK2-average; a trajectory's own r, 4 for
+RK4, sets its column layout).
 
 Per-window snapshot matrix (eq. window_sample; its first column has a typo
 mu_k for mu_1): for each parameter, the step state at the start of the window
@@ -67,6 +68,7 @@ def window_columns(traj, T_ends: list):
     kind 'snap' indexes traj.snaps.
     """
     t = traj.t
+    r = getattr(traj, "r", 2)
     out = []
     s_prev = 0
     for Tw in T_ends:
@@ -75,8 +77,8 @@ def window_columns(traj, T_ends: list):
         if s_prev > 0:
             cols.append(("init", s_prev))
         for m in range(s_prev + 1, s_w + 1):
-            cols.append(("snap", 2 * (m - 1)))  # stage state of step m
-            cols.append(("snap", 2 * (m - 1) + 1))  # step state m
+            for k in range(r):  # stage states of step m, then step state m
+                cols.append(("snap", r * (m - 1) + k))
         out.append(cols)
         s_prev = s_w
     return out
@@ -90,7 +92,8 @@ def window_start_states(traj, y0, T_ends: list) -> list:
     for w, cols in enumerate(window_columns(traj, T_ends)):
         if w > 0 and cols and cols[0][0] == "init":
             s = cols[0][1]
-            out.append(tuple(np.array(a) for a in traj.snaps[2 * (s - 1) + 1]))
+            r = getattr(traj, "r", 2)
+            out.append(tuple(np.array(a) for a in traj.snaps[r * (s - 1) + r - 1]))
         else:
             out.append(tuple(np.array(a) for a in y0))
     return out
@@ -107,7 +110,8 @@ def snapshot_matrices(trajs: list, offsets: list, T_ends: list, offsets_by_windo
         for tr, os_, cols in zip(trajs, offs, cols_per_traj):
             for kind, idx in cols[w]:
                 if kind == "init":
-                    y = tr.snaps[2 * (idx - 1) + 1]
+                    r = getattr(tr, "r", 2)
+                    y = tr.snaps[r * (idx - 1) + r - 1]
                 else:
                     y = tr.snaps[idx]
                 for f in range(3):

@@ -23,7 +23,8 @@ SEED = 210411404
 TAYLOR_GREEN = "taylor_green"
 SEDOV = "sedov"
 GRESHO = "gresho"
-PROBLEM_IDS = {TAYLOR_GREEN: 1, SEDOV: 2, GRESHO: 3}
+TRIPLE_POINT = "triple_point"
+PROBLEM_IDS = {TAYLOR_GREEN: 1, SEDOV: 2, GRESHO: 3, TRIPLE_POINT: 4}
 
 
 @dataclass(frozen=True)
@@ -99,6 +100,19 @@ def tg3d(n: int = 24, t_final: float = 0.05) -> Workload:
 def sedov3d(n: int = 32, t_final: float = 0.8) -> Workload:
     return Workload("sedov3d", SEDOV, 3, (n, n, n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), 1.4, True, 0.5, t_final,
                     n_windows=20, energy=0.25)
+
+
+def triple_point(nel: tuple = (28, 12, 4), t_final: float = 0.8) -> Workload:
+    """Triple point (Sec. 6.1.4) on [0,7] x [0,3] x [0,1.5] (2D: [0,7] x [0,3]), walls everywhere,
+    v = 0, piecewise density, pressure and adiabatic index; artificial viscosity on, CFL 0.5.
+
+    The default mesh, 28 x 12 x 4, is the size of the paper's table of FOM sizes (N_V = 38475,
+    N_E = 10752); nel must put the interfaces x = 1 and y = 1.5 on element faces (nel_x a multiple
+    of 7, nel_y even).  gamma here is unused: each element takes its region's."""
+    dim = len(nel)
+    hi = (7.0, 3.0, 1.5)[:dim]
+    return Workload("triple_point", TRIPLE_POINT, dim, tuple(nel), (0.0,) * dim, hi, 1.5, True,
+                    0.5, t_final)
 
 
 def tg2d_param(n: int = 32, t_final: float = 0.2, n_inst: int = 64, seed: int = SEED) -> Workload:
