@@ -55,11 +55,19 @@ enum lh_status {
 /* Device status word bits (lh_status_read returns them OR-ed). */
 enum { LH_FLAG_TANGLED = 1, LH_FLAG_NONFINITE = 2, LH_FLAG_DTCOLLAPSE = 4, LH_FLAG_TIMEOUT = 8 };
 
-enum lh_problem_kind { LH_TAYLOR_GREEN = 1, LH_SEDOV = 2, LH_GRESHO = 3 };
+enum lh_problem_kind { LH_TAYLOR_GREEN = 1, LH_SEDOV = 2, LH_GRESHO = 3, LH_TRIPLE_POINT = 4 };
 
 /* Problem description (Sec. 2 and Sec. 6.1 of the paper).  Q2-Q1 elements,
- * 4 Gauss-Legendre points per direction, rho0 = 1, wall boundary conditions
- * v.n = 0 on every face of the box. */
+ * 4 Gauss-Legendre points per direction, wall boundary conditions v.n = 0 on
+ * every face of the box.  rho0 = 1 and one gamma, except LH_TRIPLE_POINT
+ * (Sec. 6.1.4, on [0,7] x [0,3] (x [0,1.5])): each element takes the initial
+ * density, pressure and adiabatic index of the region holding its centre
+ * (rho0 = 1 where x <= 1 or y <= 1.5, else 1/8; p0 = 1 where x <= 1, else
+ * 0.1; gamma = 1.5 where x <= 1 or y > 1.5, else 1.4), and the desc's gamma
+ * is ignored.  Piecewise-constant rho0 enters the mass constants
+ * rho0 det J0 w_q of the force, M_V (whose solve is then a preconditioned
+ * conjugate gradient instead of the per-axis inverse of the uniform case) and
+ * M_E. */
 typedef struct {
     int32_t dim;        /* 2 or 3                                           */
     int32_t nel[3];     /* elements per direction (nel[2] ignored in 2D)    */
@@ -89,7 +97,8 @@ int lh_problem_sizes(const lh_problem* p, int64_t* nv, int64_t* ne, int64_t* n_e
  * nodal velocities v (N_V each, dev) and energies e (N_E, dev) interpolated
  * at the Q1 nodes.  Taylor-Green and Gresho fields scale with amp (velocity)
  * and amp^2 (pressure perturbation); Gresho adds p_bg; Sedov puts
- * energy / |K| on every dof of the element at the origin. */
+ * energy / |K| on every dof of the element at the origin; the triple point
+ * is at rest with e = p0 / ((gamma - 1) rho0) of each element's region. */
 int lh_initial_state(const lh_problem* p, double* x, double* v, double* e, hipStream_t stream);
 
 /* ---------------------------------------------------------------- force */
@@ -161,16 +170,21 @@ typedef struct {
     const double* dt_replay; /* (host) step sizes to replay, or NULL               */
     int32_t n_replay;
     int32_t max_steps;       /* hard cap on accepted steps                          */
-    /* snapshot storage (dev, column-major, ld N_V / N_E), stage and step
-     * states of every accepted step in order: column 2n = y_{n+1/2},
-     * column 2n+1 = y_{n+1}.  NULL disables recording. */
+    /* snapshot storage (dev, column-major, ld N_V / N_E): the stage states
+     * of every accepted step, then its step state.  RK2-average: column
+     * 2n = y_{n+1/2}, 2n+1 = y_{n+1}.  RK4: columns 4n .. 4n+3 =
+     * y_n + h/2 k1, y_n + h/2 k2, y_n + h k3, y_{n+1}.  NULL disables
+     * recording. */
     double* snap_x;
     double* snap_v;
     double* snap_e;
     int32_t max_snap;
     double* t_out;           /* (host, max_steps + 1) accepted times t_0 .. t_Nt  */
     double* dt_out;          /* (host, max_steps) accepted step sizes             */
+    int32_t scheme;          /* LH_SCHEME_RK2AVG (0) or LH_SCHEME_RK4 (1)          */
 } lh_fom_run_desc;
+
+enum { LH_SCHEME_RK2AVG = 0, LH_SCHEME_RK4 = 1 };
 
 typedef struct {
     int32_t n_steps;
@@ -182,11 +196,13 @@ typedef struct {
 /* Workspace bytes needed by lh_fom_run. */
 size_t lh_fom_run_workspace_size(const lh_problem* p);
 
-/* Full-order RK2-average integration (eq. RK2-avg) with the step control of
- * Sec. 2.2.3 (reject when h >= tau, retry with 0.85 h; grow the next step to
- * 1.02 h when h <= 0.8 tau; first step 0.85 tau(y_0); last step clipped to
- * t_final).  x, v, e (dev) are advanced in place.  Synchronises once per
- * step to read tau. */
+/* Full-order integration by RK2-average (eq. RK2-avg) or classical RK4
+ * (eq. RK4, Sec. 2.2.2: the force of every stage contracted with the stage's
+ * own velocity) with the step control of Sec. 2.2.3 (tau over all stages;
+ * reject when h >= tau, retry with 0.85 h; grow the next step to 1.02 h when
+ * h <= 0.8 tau; first step 0.85 tau(y_0); last step clipped to t_final).
+ * x, v, e (dev) are advanced in place.  Synchronises once per step to read
+ * tau. */
 int lh_fom_run(const lh_problem* p, double* x, double* v, double* e, const lh_fom_run_desc* desc,
                lh_fom_run_stats* stats, void* work, size_t work_bytes, hipStream_t stream);
 
@@ -314,7 +330,7 @@ typedef struct {
 
 typedef struct lh_rom lh_rom;
 
-enum { LH_FP32_LIFT = 1, LH_REPLAY_DT = 2, LH_FIXED_DT = 4, LH_SURROGATE = 8 };
+enum { LH_FP32_LIFT = 1, LH_REPLAY_DT = 2, LH_FIXED_DT = 4, LH_SURROGATE = 8, LH_RK4 = 16 };
 
 /* Build the online data of n_inst instances sharing one problem: element
  * closure of the sampled rows, element-local tiles of the sampled basis
@@ -350,7 +366,12 @@ int rom_init_state(const lh_rom* r, const lh_instance_desc* inst, const double* 
  * does not arrive within a bounded wait sets LH_FLAG_TIMEOUT.  flags: LH_REPLAY_DT uses dt_replay (dev, n_replay steps,
  * shared by all instances), LH_FIXED_DT keeps state.dt fixed,
  * LH_FP32_LIFT lifts and projects in FP32 (FP64 accumulation of the
- * reduced state).  An instance created with LH_OFFSETS_PREVIOUS stops when
+ * reduced state).  LH_RK4 integrates the reduced system
+ * dx^/dt = b_x + B_xv v^, dv^/dt = -F^1(y~), de^/dt = F^tv(y~; v~) with
+ * classical RK4 (eq. RK4, the force of each stage contracted with the
+ * stage's own lifted velocity; tau over the four stages) instead of
+ * RK2-average; it takes neither LH_FP32_LIFT nor LH_SURROGATE (LH_EINVAL).
+ * An instance created with LH_OFFSETS_PREVIOUS stops when
  * it reaches the end of a window that has a successor (done stays 0, the
  * state keeps the closing window) and waits for
  * rom_switch_window_previous.  With G > 1 the workgroups of instance i are
@@ -485,12 +506,13 @@ int lh_windows_by_samples(int32_t n_params, const double* const* t_lists, const 
                           double* T_out, int32_t max_windows, int32_t* n_windows);
 
 /* Column range of each window's snapshot matrix (eq. window_sample) in the
- * snapshot array written by lh_fom_run (column 2n = stage state of step n+1,
- * column 2n+1 = step state n+1): the step state at the window's start (none
- * for the first window, whose start is the offset), then the stage and step
+ * snapshot array written by lh_fom_run with r snapshots per step (r = 2 for
+ * RK2-average, 4 for RK4; columns r n .. r n + r - 1 belong to step n+1, the
+ * last being its step state): the step state at the window's start (none for
+ * the first window, whose start is the offset), then the stage and step
  * states of every step up to the first one reaching T_w.  Host only. */
-int lh_window_columns(const double* t, int32_t n_steps, const double* T, int32_t n_windows, int32_t* first_col,
-                      int32_t* n_cols);
+int lh_window_columns(const double* t, int32_t n_steps, const double* T, int32_t n_windows, int32_t r,
+                      int32_t* first_col, int32_t* n_cols);
 
 /* -------------------------------------------------------- MLP surrogate */
 

@@ -35,6 +35,7 @@ struct ForceArgs {
     double* stress;  // (n_elem, NQ, DIM, DIM) kept / used stress
     double* tau;
     int32_t* status;
+    const double* mat;  // per element (gamma, rho0 det J0), or null: fc.gamma and fc.detJ0
 };
 
 template <int DIM>
@@ -56,6 +57,7 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
     __shared__ double s_sig[EPB][NQ][DD];
     __shared__ double s_s[EPB][NQ];
     __shared__ int s_elem[EPB];
+    __shared__ double s_m[EPB][2];  // element material: gamma, rho0 det J0
     __shared__ double s_tau[256];
 
     const int tid = threadIdx.x;
@@ -71,6 +73,8 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
             K = -1;
         }
         s_elem[tid] = K;
+        s_m[tid][0] = A.mat && K >= 0 ? A.mat[2 * K] : A.fc.gamma;
+        s_m[tid][1] = A.mat && K >= 0 ? A.mat[2 * K + 1] : A.fc.detJ0;
     }
     __syncthreads();
     // stage node data: component-major, element-slot, local node (x fastest)
@@ -109,7 +113,7 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
 #pragma unroll
                 for (int i = 0; i < DIM; ++i) sig[c][i] = src[c * DIM + i];
         } else {
-            const int fl = qp_stress<DIM>(A.T, A.fc, q, s_x[s], s_v[s], s_e[s], sig, tau);
+            const int fl = qp_stress<DIM>(A.T, A.fc, s_m[s], q, s_x[s], s_v[s], s_e[s], sig, tau);
             if (fl) atomicOr(A.status, fl);
             if (A.ops & LH_KEEP_STRESS) {
                 double* dst = A.stress + ((int64_t)K * NQ + q) * DD;
@@ -323,6 +327,7 @@ static int force_launch(const lh_problem* p, const double* x, const double* v, c
     A.ftv = Ftv;
     A.tau = tau_min;
     A.status = p->d_status;
+    A.mat = p->d_mat_e;
     const bool want_f1 = (ops & LH_F1) && !use_stress;
     if (want_f1 && !all) {
         const int64_t n = (int64_t)(f1_loc_bytes(p) / sizeof(double));

@@ -13,6 +13,7 @@
 #include <cstdint>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/lagrom.h"
 
@@ -35,11 +36,13 @@ struct ElemDims {
     static constexpr int NT = DIM == 2 ? 4 : 8;    // Q1 dofs
 };
 
-// Physical constants of the force evaluation.
+// Physical constants of the force evaluation.  gamma and rho0 = 1 hold for
+// every element unless the problem has per-element materials, which the
+// kernels then read from tables and pass to qp_stress.
 struct ForceConst {
     double gamma;
     double cfl;
-    double detJ0;  // det of the (uniform) initial element map; rho0 = 1
+    double detJ0;  // det of the (uniform) initial element map
     int use_av;
 };
 
@@ -103,6 +106,10 @@ struct lh_problem {
     double* d_minv_bc[3];  // same with the wall rows/columns eliminated
     int32_t* d_status;
     int device;
+    // per-element materials (triple point): rho0 and gamma of each element (dev, n_elem), and
+    // c0 = rho0 det J0 next to gamma as pairs (dev, 2 n_elem); all null for uniform materials
+    double* d_rho_e;
+    double* d_mat_e;
     struct lh_problem_extra* ex;  // mass-solve scratch and reduction buffers
 };
 
@@ -116,6 +123,9 @@ struct lh_problem_extra {
     double* d_medinv;   // 8 entries: inverse thermodynamic mass per local dof
     double* d_mediag;   // 8 entries
     double* d_partial;  // reduction partials
+    double* d_cg;       // 4 N_V conjugate-gradient vectors of the non-uniform kinematic mass solve, 5 scalars
+    double* d_one;      // a device 1.0 (inside d_cg)
+    std::vector<double> h_rho_e, h_gam_e;  // per-element materials on the host (empty when uniform)
     std::mutex mtx;
 };
 
@@ -144,6 +154,13 @@ void set_error(const std::string& msg);
 // out = M_V in with the kinematic mass matrix of the total energy (no wall elimination), one
 // kinematic vector (N_V, dev; in and out must differ).  Uses the problem's scratch under its mutex.
 int mass_apply_v_full(const lh_problem* p, const double* in, double* out, hipStream_t stream);
+
+// out = M_V in (elim: M_V,eff) for a problem with per-element densities (p->d_rho_e set), one kinematic
+// vector (N_V, dev; in and out must differ).  Needs no scratch.
+int mass_apply_v_rho(const lh_problem* p, const double* in, double* out, bool elim, hipStream_t stream);
+
+// out = M_E in with per-element densities (block diagonal, rho_K times the rho0 = 1 block).
+int thermo_mass_rho(const lh_problem* p, const double* in, double* out, hipStream_t stream);
 
 inline int launch_check(const char* what) {
     hipError_t e = hipGetLastError();
@@ -228,10 +245,13 @@ __device__ inline void sym3_eig(double a[3][3], double lam[3]) {
 
 // Pulled-back stress sigma~ = w det J sigma J^{-T} and the step estimate at
 // one quadrature point, from the element-local node positions xe[a*DIM+c],
-// velocities ve[...] and energies ee[j].  Returns status flag bits.
+// velocities ve[...] and energies ee[j], for an element whose adiabatic index
+// and mass constant rho0 det J0 (rho = rho0 det J0 / det J) are mat[0] and
+// mat[1] (element data staged in LDS next to xe, read where they are used).
+// Returns status flag bits.
 template <int DIM>
-__device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, int q, const double* xe, const double* ve,
-                                const double* ee, double sig_t[DIM][DIM], double& tau) {
+__device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, const double* mat, int q, const double* xe,
+                                const double* ve, const double* ee, double sig_t[DIM][DIM], double& tau) {
     constexpr int NK = ElemDims<DIM>::NK;
     constexpr int NT = ElemDims<DIM>::NT;
     int qx, qy, qz;
@@ -287,12 +307,12 @@ __device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, int q, co
     }
     if (!(det > 0.0)) flags |= LH_FLAG_TANGLED;
     const double w = qweight<DIM>(T, qx, qy, qz);
-    const double cq = w * fc.detJ0;
+    const double cq = w * mat[1];
     const double rho = cq / (w * det);
     double eq = 0.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) eq += ee[j] * tshape<DIM>(T, qx, qy, qz, j);
-    const double gm = fc.gamma;
+    const double gm = mat[0];
     const double p = (gm - 1.0) * rho * eq;
     const double cs = sqrt(fmax(gm * (gm - 1.0) * eq, 0.0));
     // smallest singular value of J: |det J| / (product of the larger ones)

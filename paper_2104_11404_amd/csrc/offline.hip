@@ -251,17 +251,18 @@ int lh_windows_by_samples(int32_t n_params, const double* const* t_lists, const 
     return LH_OK;
 }
 
-int lh_window_columns(const double* t, int32_t n_steps, const double* T, int32_t n_windows, int32_t* first_col,
-                      int32_t* n_cols) {
+int lh_window_columns(const double* t, int32_t n_steps, const double* T, int32_t n_windows, int32_t r,
+                      int32_t* first_col, int32_t* n_cols) {
     using namespace lh;
     LH_REQUIRE(t && T && first_col && n_cols && n_steps >= 1 && n_windows >= 1, "lh_window_columns: bad arguments");
+    LH_REQUIRE(r >= 1, "lh_window_columns: r must be positive");
     int s_prev = 0;
     for (int w = 0; w < n_windows; ++w) {
         int s = 0;
         while (s < n_steps && t[s] < T[w]) ++s;
-        // previous step state (column 2 s_prev - 1) unless s_prev = 0, then stage/step pairs
-        first_col[w] = s_prev > 0 ? 2 * s_prev - 1 : 0;
-        n_cols[w] = 2 * (s - s_prev) + (s_prev > 0 ? 1 : 0);
+        // previous step state (column r s_prev - 1) unless s_prev = 0, then r columns per step
+        first_col[w] = s_prev > 0 ? r * s_prev - 1 : 0;
+        n_cols[w] = r * (s - s_prev) + (s_prev > 0 ? 1 : 0);
         s_prev = s;
     }
     return LH_OK;
@@ -270,6 +271,7 @@ int lh_window_columns(const double* t, int32_t n_steps, const double* T, int32_t
 int lh_mass_apply_v(const lh_problem* p, const double* in, double* out, hipStream_t s) {
     using namespace lh;
     LH_REQUIRE(p && in && out && in != out, "lh_mass_apply_v: bad arguments");
+    if (p->d_rho_e) return mass_apply_v_rho(p, in, out, true, s);
     lh_problem_extra* ex = p->ex;
     std::lock_guard<std::mutex> lock(ex->mtx);
     const int64_t n = p->n_nodes;
@@ -303,6 +305,7 @@ int lh_mass_apply_e(const lh_problem* p, const double* in, double* out, hipStrea
     LH_REQUIRE(p && in && out, "lh_mass_apply_e: bad arguments");
     const lh_problem_extra* ex = p->ex;
     const int64_t n = p->NE;
+    if (p->d_rho_e) return thermo_mass_rho(p, in, out, s);
     hipLaunchKernelGGL(off::diag_mul_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out,
                        ex->d_mediag, p->dim == 3 ? 8 : 4, n);
     return launch_check("lh_mass_apply_e");

@@ -142,7 +142,13 @@ __global__ void initial_state_kernel(lh_problem_desc d, int dim, int nnx, int nn
         const double rho0 = 1.0;
         double p = 0.0;
         double ev;
-        if (d.kind == LH_SEDOV) {
+        if (d.kind == LH_TRIPLE_POINT) {  // the region of the element's centre
+            const double cx = d.lo[0] + hx * (ex + 0.5), cy = d.lo[1] + hy * (ey + 0.5);
+            const double rho = (cx <= 1.0 || cy <= 1.5) ? 1.0 : 0.125;
+            const double gm = (cx <= 1.0 || cy > 1.5) ? 1.5 : 1.4;
+            p = cx <= 1.0 ? 1.0 : 0.1;
+            ev = p / ((gm - 1.0) * rho);
+        } else if (d.kind == LH_SEDOV) {
             const double vol = hx * hy * (dim == 3 ? hz : 1.0);
             ev = K == 0 ? d.energy / (rho0 * vol) : 0.0;
         } else {
@@ -217,6 +223,112 @@ __global__ void weighted_sum_partial_kernel(const double* e, int64_t n, const do
     if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
 }
 
+// 1D element mass matrices m[axis][i][j] = h_axis sum_q w_q B_i(q) B_j(q).
+struct Mass1D {
+    double m[3][3][3];
+};
+
+// out = M in for the kinematic mass with a density per element, M_ab = sum_K rho_K int_K N_a N_b:
+// thread (c, node) gathers, in a fixed order, the rows of the (at most 2^d) elements around its
+// node.  elim: the wall-eliminated M_V,eff (constrained columns dropped, identity rows).
+__global__ void mass_rho_kernel(const double* __restrict__ in, double* __restrict__ out, const double* __restrict__ rho,
+                                Mass1D M, int dim, int nex, int ney, int nez, int nnx, int nny, int nnz,
+                                int64_t n_nodes, int elim) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= n_nodes * dim) return;
+    const int c = (int)(tid / n_nodes);
+    const int64_t node = tid % n_nodes;
+    const int g[3] = {(int)(node % nnx), (int)((node / nnx) % nny), dim == 3 ? (int)(node / ((int64_t)nnx * nny)) : 0};
+    const int nn[3] = {nnx, nny, nnz};
+    const int ne[3] = {nex, ney, nez};
+    if (elim && (g[c] == 0 || g[c] == nn[c] - 1)) {
+        out[tid] = in[tid];
+        return;
+    }
+    int lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        if (k >= dim) {
+            lo[k] = hi[k] = 0;
+        } else if (g[k] & 1) {
+            lo[k] = hi[k] = g[k] >> 1;
+        } else {
+            lo[k] = max((g[k] >> 1) - 1, 0);
+            hi[k] = min(g[k] >> 1, ne[k] - 1);
+        }
+    }
+    const double* src = in + (int64_t)c * n_nodes;
+    double acc = 0.0;
+    for (int ez = lo[2]; ez <= hi[2]; ++ez)
+        for (int ey = lo[1]; ey <= hi[1]; ++ey)
+            for (int ex = lo[0]; ex <= hi[0]; ++ex) {
+                const int e3[3] = {ex, ey, ez};
+                int a[3];
+                for (int k = 0; k < 3; ++k) a[k] = k < dim ? g[k] - 2 * e3[k] : 0;
+                double s = 0.0;
+                const int bz_n = dim == 3 ? 3 : 1;
+                for (int bz = 0; bz < bz_n; ++bz)
+                    for (int by = 0; by < 3; ++by)
+                        for (int bx = 0; bx < 3; ++bx) {
+                            const int gb[3] = {2 * ex + bx, 2 * ey + by, 2 * ez + bz};
+                            if (elim && (gb[c] == 0 || gb[c] == nn[c] - 1)) continue;
+                            double m = M.m[0][a[0]][bx] * M.m[1][a[1]][by];
+                            if (dim == 3) m *= M.m[2][a[2]][bz];
+                            const int64_t nb = gb[0] + (int64_t)nnx * (gb[1] + (int64_t)nny * (dim == 3 ? gb[2] : 0));
+                            s += m * src[nb];
+                        }
+                acc += rho[ex + (int64_t)nex * (ey + (int64_t)ney * ez)] * s;
+            }
+    out[tid] = acc;
+}
+
+// out = in * w[j] * f(rho_K) for thermodynamic dof (K, j): f = rho (mult != 0) or 1 / rho
+__global__ void thermo_rho_kernel(const double* in, double* out, const double* __restrict__ w,
+                                  const double* __restrict__ rho, int nt, int64_t n, int mult) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double r = rho[i / nt];
+    out[i] = mult ? in[i] * w[i % nt] * r : in[i] * w[i % nt] / r;
+}
+
+// One block: s[0] = sum of the first n partials (the block sums of a dot product), in order.
+__global__ void finish_dot_kernel(const double* partial, int n, double* s) {
+    __shared__ double r[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += partial[i];
+    r[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) r[threadIdx.x] += r[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) s[0] = r[0];
+}
+
+// Conjugate-gradient updates with the scalars on the device (sc: [0] r.z, [1] p.Ap, [2] new r.z).
+// x += alpha p, r -= alpha Ap with alpha = r.z / p.Ap
+__global__ void cg_xr_kernel(double* x, double* r, const double* p, const double* Ap, const double* sc, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double alpha = sc[1] != 0.0 ? sc[0] / sc[1] : 0.0;
+    x[i] += alpha * p[i];
+    r[i] -= alpha * Ap[i];
+}
+
+// p = z + beta p with beta = new r.z / r.z (cg_roll_kernel then moves new r.z into r.z)
+__global__ void cg_p_kernel(double* p, const double* z, const double* sc, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double beta = sc[0] != 0.0 ? sc[2] / sc[0] : 0.0;
+    p[i] = z[i] + beta * p[i];
+}
+
+__global__ void cg_roll_kernel(double* sc) { sc[0] = sc[2]; }
+
+__global__ void sub_kernel_pb(const double* a, const double* b, double* out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] - b[i];
+}
+
 }  // namespace lh
 
 typedef lh_problem_extra ProblemExtra;
@@ -235,7 +347,7 @@ int lh_problem_create(const lh_problem_desc* desc, lh_problem** out) {
         LH_REQUIRE(desc->nel[c] >= 1 && desc->nel[c] <= 4096, "lh_problem_create: nel out of range");
         LH_REQUIRE(desc->hi[c] > desc->lo[c], "lh_problem_create: empty box");
     }
-    LH_REQUIRE(desc->kind >= LH_TAYLOR_GREEN && desc->kind <= LH_GRESHO, "lh_problem_create: unknown kind");
+    LH_REQUIRE(desc->kind >= LH_TAYLOR_GREEN && desc->kind <= LH_TRIPLE_POINT, "lh_problem_create: unknown kind");
     LH_REQUIRE(desc->gamma > 1.0, "lh_problem_create: gamma must exceed 1");
     LH_REQUIRE(desc->cfl > 0.0, "lh_problem_create: cfl must be positive");
     LH_REQUIRE(!(desc->kind == LH_GRESHO && desc->dim != 2), "lh_problem_create: Gresho is two-dimensional");
@@ -298,8 +410,9 @@ int lh_problem_create(const lh_problem_desc* desc, lh_problem** out) {
         p->d_minv[c] = p->d_minv_bc[c] = nullptr;
         ex->d_m[c] = nullptr;
     }
-    ex->d_tmp = ex->d_medinv = ex->d_mediag = ex->d_partial = nullptr;
+    ex->d_tmp = ex->d_medinv = ex->d_mediag = ex->d_partial = ex->d_cg = ex->d_one = nullptr;
     p->d_status = nullptr;
+    p->d_rho_e = p->d_mat_e = nullptr;
     for (int c = 0; c < p->dim; ++c) {
         const int n = p->nn[c];
         std::vector<double> M(n * n, 0.0);
@@ -343,6 +456,31 @@ int lh_problem_create(const lh_problem_desc* desc, lh_problem** out) {
         hipMemcpy(ex->d_mediag, p->me_diag, sizeof(double) * nt, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(p->d_status, 0, sizeof(int32_t)) != hipSuccess)
         return fail("hipMemcpy");
+    if (desc->kind == LH_TRIPLE_POINT) {
+        // materials of the region holding each element's centre (Sec. 6.1.4)
+        const int64_t ne = p->n_elem;
+        ex->h_rho_e.resize(ne);
+        ex->h_gam_e.resize(ne);
+        std::vector<double> mat(2 * ne);
+        for (int64_t K = 0; K < ne; ++K) {
+            const int exx = (int)(K % p->nel[0]), eyy = (int)((K / p->nel[0]) % p->nel[1]);
+            const double cx = desc->lo[0] + p->h[0] * (exx + 0.5), cy = desc->lo[1] + p->h[1] * (eyy + 0.5);
+            ex->h_rho_e[K] = (cx <= 1.0 || cy <= 1.5) ? 1.0 : 0.125;
+            ex->h_gam_e[K] = (cx <= 1.0 || cy > 1.5) ? 1.5 : 1.4;
+            mat[2 * K] = ex->h_gam_e[K];
+            mat[2 * K + 1] = ex->h_rho_e[K] * detJ0;
+        }
+        if (hipMalloc(&p->d_rho_e, sizeof(double) * ne) != hipSuccess ||
+            hipMalloc(&p->d_mat_e, sizeof(double) * 2 * ne) != hipSuccess ||
+            hipMalloc(&ex->d_cg, sizeof(double) * (4 * p->NV + 8)) != hipSuccess)
+            return fail("hipMalloc");
+        const double one = 1.0;
+        ex->d_one = ex->d_cg + 4 * p->NV + 7;
+        if (hipMemcpy(ex->d_one, &one, sizeof(double), hipMemcpyHostToDevice) != hipSuccess) return fail("hipMemcpy");
+        if (hipMemcpy(p->d_rho_e, ex->h_rho_e.data(), sizeof(double) * ne, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(p->d_mat_e, mat.data(), sizeof(double) * 2 * ne, hipMemcpyHostToDevice) != hipSuccess)
+            return fail("hipMemcpy");
+    }
     *out = p;
     return LH_OK;
 }
@@ -359,6 +497,9 @@ void lh_problem_destroy(lh_problem* p) {
     if (ex->d_medinv) (void)hipFree(ex->d_medinv);
     if (ex->d_mediag) (void)hipFree(ex->d_mediag);
     if (ex->d_partial) (void)hipFree(ex->d_partial);
+    if (ex->d_cg) (void)hipFree(ex->d_cg);
+    if (p->d_rho_e) (void)hipFree(p->d_rho_e);
+    if (p->d_mat_e) (void)hipFree(p->d_mat_e);
     if (p->d_status) (void)hipFree(p->d_status);
     delete ex;
     delete p;
@@ -406,8 +547,36 @@ static int tensor_apply(const lh_problem* p, double* const* mats, const double* 
 }  // extern "C"
 
 namespace lh {
+static Mass1D mass_1d(const lh_problem* p) {
+    Mass1D M;
+    for (int ax = 0; ax < 3; ++ax)
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double s = 0.0;
+                for (int q = 0; q < 4; ++q) s += p->tab.W[q] * p->tab.B[q][i] * p->tab.B[q][j];
+                M.m[ax][i][j] = (ax < p->dim ? p->h[ax] : 1.0) * s;
+            }
+    return M;
+}
+
+int mass_apply_v_rho(const lh_problem* p, const double* in, double* out, bool elim, hipStream_t stream) {
+    const int64_t n = p->n_nodes * p->dim;
+    hipLaunchKernelGGL(mass_rho_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, in, out, p->d_rho_e,
+                       mass_1d(p), p->dim, p->nel[0], p->nel[1], p->nel[2], p->nn[0], p->nn[1], p->nn[2], p->n_nodes,
+                       elim ? 1 : 0);
+    return launch_check("mass_rho_kernel");
+}
+
+int thermo_mass_rho(const lh_problem* p, const double* in, double* out, hipStream_t stream) {
+    const int64_t n = p->NE;
+    hipLaunchKernelGGL(thermo_rho_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, in, out,
+                       p->ex->d_mediag, p->d_rho_e, p->dim == 3 ? 8 : 4, n, 1);
+    return launch_check("thermo_rho_kernel");
+}
+
 int mass_apply_v_full(const lh_problem* p, const double* in, double* out, hipStream_t stream) {
     LH_REQUIRE(p && in && out && in != out, "mass_apply_v_full: bad arguments");
+    if (p->d_rho_e) return mass_apply_v_rho(p, in, out, false, stream);
     ProblemExtra* ex = extra_of(p);
     std::lock_guard<std::mutex> lock(ex->mtx);
     for (int c = 0; c < p->dim; ++c) {
@@ -420,11 +589,9 @@ int mass_apply_v_full(const lh_problem* p, const double* in, double* out, hipStr
 
 extern "C" {
 
-int lh_mass_solve_v(const lh_problem* p, const double* rhs, double* out, hipStream_t stream) {
-    using namespace lh;
-    LH_REQUIRE(p && rhs && out, "lh_mass_solve_v: null argument");
+// out = M_V,eff^{-1} rhs for rho0 = 1 (the per-axis inverses), one kinematic vector; rhs and out may alias.
+static int uniform_solve_v(const lh_problem* p, const double* rhs, double* out, hipStream_t stream) {
     ProblemExtra* ex = extra_of(p);
-    std::lock_guard<std::mutex> lock(ex->mtx);
     for (int c = 0; c < p->dim; ++c) {
         double* mats[3];
         for (int ax = 0; ax < p->dim; ++ax) mats[ax] = ax == c ? p->d_minv_bc[ax] : p->d_minv[ax];
@@ -435,12 +602,78 @@ int lh_mass_solve_v(const lh_problem* p, const double* rhs, double* out, hipStre
     return LH_OK;
 }
 
+// device dot product a.b into *s (block partials summed in order)
+static void dev_dot(const lh_problem* p, const double* a, const double* b, double* s, hipStream_t stream) {
+    ProblemExtra* ex = extra_of(p);
+    hipLaunchKernelGGL(lh::dot_partial_kernel, dim3(256), dim3(256), 0, stream, a, b, p->NV, ex->d_partial);
+    hipLaunchKernelGGL(lh::finish_dot_kernel, dim3(1), dim3(256), 0, stream, ex->d_partial, 256, s);
+}
+
+// M_V,eff x = rhs with a density per element: conjugate gradients preconditioned by the rho0 = 1
+// inverse (eigenvalues of the preconditioned matrix between min and max rho0, so the iteration count
+// is fixed by their ratio), started from the preconditioned right-hand side.  Residual checked every
+// 8 iterations against 1e-15 ||rhs||.  Wall rows stay zero throughout.
+static int cg_solve_v(const lh_problem* p, const double* rhs, double* out, hipStream_t stream) {
+    using namespace lh;
+    ProblemExtra* ex = extra_of(p);
+    const int64_t n = p->NV;
+    double* r = ex->d_cg;
+    double* z = r + n;
+    double* pp = z + n;
+    double* Ap = pp + n;
+    double* sc = Ap + n;  // [0] r.z  [1] p.Ap  [2] new r.z  [3] r.r  [4] rhs.rhs
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    int rc;
+    dev_dot(p, rhs, rhs, sc + 4, stream);
+    if ((rc = uniform_solve_v(p, rhs, out, stream))) return rc;  // x0 = P rhs (rhs is wall-free)
+    if ((rc = mass_apply_v_rho(p, out, Ap, true, stream))) return rc;
+    hipLaunchKernelGGL(sub_kernel_pb, dim3(nb), dim3(256), 0, stream, rhs, Ap, r, n);
+    if ((rc = uniform_solve_v(p, r, z, stream))) return rc;
+    LH_HIP_CHECK(hipMemcpyAsync(pp, z, sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
+    dev_dot(p, r, z, sc, stream);
+    double hs[5];
+    for (int it = 0; it < 400; ++it) {
+        if ((rc = mass_apply_v_rho(p, pp, Ap, true, stream))) return rc;
+        dev_dot(p, pp, Ap, sc + 1, stream);
+        hipLaunchKernelGGL(cg_xr_kernel, dim3(nb), dim3(256), 0, stream, out, r, pp, Ap, sc, n);
+        if ((rc = uniform_solve_v(p, r, z, stream))) return rc;
+        dev_dot(p, r, z, sc + 2, stream);
+        hipLaunchKernelGGL(cg_p_kernel, dim3(nb), dim3(256), 0, stream, pp, z, sc, n);
+        hipLaunchKernelGGL(cg_roll_kernel, dim3(1), dim3(1), 0, stream, sc);
+        if (it % 8 == 7) {
+            dev_dot(p, r, r, sc + 3, stream);
+            LH_HIP_CHECK(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, stream));
+            LH_HIP_CHECK(hipStreamSynchronize(stream));
+            if (!(hs[3] > 1e-30 * hs[4])) return launch_check("cg_solve_v");
+        }
+    }
+    set_error("lh_mass_solve_v: conjugate gradients did not converge in 400 iterations");
+    return LH_EDEVICE;
+}
+
+int lh_mass_solve_v(const lh_problem* p, const double* rhs, double* out, hipStream_t stream) {
+    using namespace lh;
+    LH_REQUIRE(p && rhs && out, "lh_mass_solve_v: null argument");
+    ProblemExtra* ex = extra_of(p);
+    std::lock_guard<std::mutex> lock(ex->mtx);
+    if (p->d_rho_e) {
+        LH_REQUIRE(rhs != out, "lh_mass_solve_v: rhs and out must differ for per-element densities");
+        return cg_solve_v(p, rhs, out, stream);
+    }
+    return uniform_solve_v(p, rhs, out, stream);
+}
+
 int lh_mass_solve_e(const lh_problem* p, const double* rhs, double* out, hipStream_t stream) {
     using namespace lh;
     LH_REQUIRE(p && rhs && out, "lh_mass_solve_e: null argument");
     ProblemExtra* ex = extra_of(p);
     const int64_t n = p->NE;
     const int threads = 256;
+    if (p->d_rho_e) {
+        hipLaunchKernelGGL(thermo_rho_kernel, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, stream,
+                           rhs, out, ex->d_medinv, p->d_rho_e, p->dim == 3 ? 8 : 4, n, 0);
+        return launch_check("thermo_rho_kernel");
+    }
     hipLaunchKernelGGL(diag_scale_kernel, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, stream,
                        rhs, out, ex->d_medinv, p->dim == 3 ? 8 : 4, n);
     return launch_check("diag_scale_kernel");
@@ -451,25 +684,39 @@ int lh_total_energy(const lh_problem* p, const double* v, const double* e, doubl
     LH_REQUIRE(p && v && e && out, "lh_total_energy: null argument");
     ProblemExtra* ex = extra_of(p);
     std::lock_guard<std::mutex> lock(ex->mtx);
-    double* Mv = ex->d_tmp + 2 * p->n_nodes;
-    double kin = 0.0;
     const int nb = 256;
+    const int nt = p->dim == 3 ? 8 : 4;
     std::vector<double> part(nb);
-    for (int c = 0; c < p->dim; ++c) {
-        int rc = tensor_apply(p, ex->d_m, v + c * p->n_nodes, Mv, ex->d_tmp, stream);
-        if (rc) return rc;
-        hipLaunchKernelGGL(dot_partial_kernel, dim3(nb), dim3(256), 0, stream, v + c * p->n_nodes, Mv, p->n_nodes,
-                           ex->d_partial);
+    auto fetch = [&](double* acc) -> int {
         LH_HIP_CHECK(hipMemcpyAsync(part.data(), ex->d_partial, sizeof(double) * nb, hipMemcpyDeviceToHost, stream));
         LH_HIP_CHECK(hipStreamSynchronize(stream));
-        for (int i = 0; i < nb; ++i) kin += part[i];
+        for (int i = 0; i < nb; ++i) *acc += part[i];
+        return LH_OK;
+    };
+    double kin = 0.0, internal = 0.0;
+    int rc;
+    if (p->d_rho_e) {  // per-element densities: M_V v in full (d_tmp holds N_V), rho_K in M_E
+        if ((rc = mass_apply_v_rho(p, v, ex->d_tmp, false, stream))) return rc;
+        hipLaunchKernelGGL(dot_partial_kernel, dim3(nb), dim3(256), 0, stream, v, ex->d_tmp, p->NV, ex->d_partial);
+        if ((rc = fetch(&kin))) return rc;
+        hipLaunchKernelGGL(thermo_rho_kernel, dim3((unsigned)((p->NE + 255) / 256)), dim3(256), 0, stream, e, ex->d_cg,
+                           ex->d_mediag, p->d_rho_e, nt, p->NE, 1);
+        hipLaunchKernelGGL(weighted_sum_partial_kernel, dim3(nb), dim3(256), 0, stream, ex->d_cg, p->NE, ex->d_one, 1,
+                           ex->d_partial);
+        if ((rc = fetch(&internal))) return rc;
+        *out = 0.5 * kin + internal;
+        return launch_check("lh_total_energy");
     }
-    hipLaunchKernelGGL(weighted_sum_partial_kernel, dim3(nb), dim3(256), 0, stream, e, p->NE, ex->d_mediag,
-                       p->dim == 3 ? 8 : 4, ex->d_partial);
-    LH_HIP_CHECK(hipMemcpyAsync(part.data(), ex->d_partial, sizeof(double) * nb, hipMemcpyDeviceToHost, stream));
-    LH_HIP_CHECK(hipStreamSynchronize(stream));
-    double internal = 0.0;
-    for (int i = 0; i < nb; ++i) internal += part[i];
+    double* Mv = ex->d_tmp + 2 * p->n_nodes;
+    for (int c = 0; c < p->dim; ++c) {
+        if ((rc = tensor_apply(p, ex->d_m, v + c * p->n_nodes, Mv, ex->d_tmp, stream))) return rc;
+        hipLaunchKernelGGL(dot_partial_kernel, dim3(nb), dim3(256), 0, stream, v + c * p->n_nodes, Mv, p->n_nodes,
+                           ex->d_partial);
+        if ((rc = fetch(&kin))) return rc;
+    }
+    hipLaunchKernelGGL(weighted_sum_partial_kernel, dim3(nb), dim3(256), 0, stream, e, p->NE, ex->d_mediag, nt,
+                       ex->d_partial);
+    if ((rc = fetch(&internal))) return rc;
     *out = 0.5 * kin + internal;
     return LH_OK;
 }

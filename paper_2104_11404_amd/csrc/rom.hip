@@ -67,6 +67,7 @@ struct WinDev {
     const double* tile[3];  // [n_el][n_f][rows_f]
     const float* tile32[3];
     const double* os_loc[3];  // [n_el][rows_f]
+    const double* mat;        // [n_el][2] (gamma, rho0 det J0) of each slot's element
     const double* A1;         // n_v x ns1
     const double* A2;         // n_e x ns2
     const float* A1f;
@@ -155,6 +156,7 @@ struct NodeBuf {
     double v[Cfg<DIM>::EC][Cfg<DIM>::NKD];
     double e[Cfg<DIM>::EC][Cfg<DIM>::NT];
     double s[Cfg<DIM>::EC][Cfg<DIM>::NQ];
+    double m[Cfg<DIM>::EC][2];  // element material: gamma, rho0 det J0
 };
 
 // Minimum over the workgroup: within each wave by shuffles, then over the waves (wred: BLK / 64).
@@ -303,6 +305,10 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
     double tau = INFINITY;
     for (int c0 = 0; c0 < V.ns; c0 += EC) {
         const int ne = min(EC, V.ns - c0);
+        if (tid < ne) {
+            B.m[tid][0] = W.mat[2 * (V.s0 + c0 + tid)];
+            B.m[tid][1] = W.mat[2 * (V.s0 + c0 + tid) + 1];
+        }
         for (int t = tid; t < ne * (2 * NKD + NT); t += BLK) {
             const int sl = t / (2 * NKD + NT);
             const int r = t % (2 * NKD + NT);
@@ -323,7 +329,7 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
             if (sl < ne) {
                 double sig[DIM][DIM];
                 double tq;
-                const int fl = qp_stress<DIM>(A.T, A.fc, q, B.x[sl], B.v[sl], B.e[sl], sig, tq);
+                const int fl = qp_stress<DIM>(A.T, A.fc, B.m[sl], q, B.x[sl], B.v[sl], B.e[sl], sig, tq);
                 if (fl) atomicOr(status, fl);
                 tau = fmin(tau, tq);
                 double* dst = L.sig + ((int64_t)(c0 + sl) * NQ + q) * DD;
@@ -768,7 +774,7 @@ __device__ __forceinline__ void rom_block(const RomArgs& A, int b, int* ii, int*
     }
 }
 
-template <int DIM, class TT, bool RES>
+template <int DIM, class TT, bool RES, bool RK4 = false>
 __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
     extern __shared__ double dyn_raw[];
     __shared__ NodeBuf<DIM> B;
@@ -869,7 +875,50 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         const bool has_net = surrogate && W.net.L > 0 && !fallen;
         const bool audit_now = has_net && since % W.audit_every == 0;
         double tau;
-        if (has_net && !audit_now) {
+        if constexpr (RK4) {
+            // ---- classical RK4 (eq. RK4) of the reduced system: stage state in S.yh, the slope sums
+            // kv1 + 2 kv2 + 2 kv3 + kv4 (ke likewise) in S.yn[1], S.yn[2], and the same sum of the stage
+            // velocities (the position slopes are b_x + B_xv v) in S.vc
+            for (int f = 0; f < 3; ++f)
+                for (int i = tid; i < W.n[f]; i += BLK) S.yh[f][i] = S.y[f][i];
+            __syncthreads();
+            tau = INFINITY;
+            for (int k = 0; k < 4; ++k) {
+                pass_a<DIM, TT, !RES>(A, W, V, L, B, S, fe, S.yh[0], S.yh[1], S.yh[2], (phase & 1) ? part1 : part0,
+                                      &s_status);
+                sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
+                tau = fmin(tau, combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage));
+                ++phase;
+                pass_b<DIM, TT, !RES>(A, W, V, L, B, te, S.yh[1], (phase & 1) ? part1 : part0, &s_status, S.red);
+                sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
+                combine((phase & 1) ? all1 : all0, A.G, W.n[2], S.ftvh, &s_status, S, stage);
+                ++phase;
+                const double wk = (k == 0 || k == 3) ? 1.0 : 2.0;
+                for (int i = tid; i < W.n[1]; i += BLK) {
+                    S.yn[1][i] = (k == 0 ? 0.0 : S.yn[1][i]) + wk * (-S.f1h[i]);
+                    S.vc[i] = (k == 0 ? 0.0 : S.vc[i]) + wk * S.yh[1][i];
+                }
+                for (int i = tid; i < W.n[2]; i += BLK) S.yn[2][i] = (k == 0 ? 0.0 : S.yn[2][i]) + wk * S.ftvh[i];
+                __syncthreads();
+                if (k < 3) {  // next stage state y_n + c (slope of this stage), c = h/2, h/2, h
+                    const double ck = k < 2 ? 0.5 * h : h;
+                    x_update(W, L, S.y[0], ck, S.yh[1], S.yh[0], S.red);
+                    __syncthreads();
+                    for (int i = tid; i < W.n[1]; i += BLK) S.yh[1][i] = S.y[1][i] + ck * (-S.f1h[i]);
+                    for (int i = tid; i < W.n[2]; i += BLK) S.yh[2][i] = S.y[2][i] + ck * S.ftvh[i];
+                    __syncthreads();
+                }
+            }
+            for (int i = tid; i < W.n[1]; i += BLK) {
+                S.yn[1][i] = S.y[1][i] + h / 6.0 * S.yn[1][i];
+                S.vc[i] = S.vc[i] / 6.0;
+            }
+            for (int i = tid; i < W.n[2]; i += BLK) S.yn[2][i] = S.y[2][i] + h / 6.0 * S.yn[2][i];
+            __syncthreads();
+            x_update(W, L, S.y[0], h, S.vc, S.yn[0], S.red);
+            __syncthreads();
+            evals += 4 * W.n_el;
+        } else if (has_net && !audit_now) {
             // ---- surrogate step: the network's F^1 and F^tv = g + H v^_c in both stages
             float* out;
             mlp_eval(W.net, S.y[0], S.y[1], S.y[2], W.n, t, mscr, out);
@@ -1446,6 +1495,17 @@ static int build_window(lh_rom* R, const lh_problem* p, const lh_window_desc& wd
     if ((rc = upload(R, growt, &d_growt))) return rc;
     H.growk = d_growk;
     H.growt = d_growt;
+    {  // materials of the closure's elements in slot order (the problem's one gamma and rho0 = 1 if uniform)
+        std::vector<double> mat(2 * (size_t)n_el);
+        const bool per_elem = p->d_mat_e != nullptr;
+        for (int sl = 0; sl < n_el; ++sl) {
+            mat[2 * sl] = per_elem ? p->ex->h_gam_e[elem[sl]] : p->fc.gamma;
+            mat[2 * sl + 1] = per_elem ? p->ex->h_rho_e[elem[sl]] * p->fc.detJ0 : p->fc.detJ0;
+        }
+        const double* d_mat;
+        if ((rc = upload(R, mat, &d_mat))) return rc;
+        W.mat = d_mat;
+    }
     for (int f = 0; f < 3; ++f) {
         const int rows = f == 2 ? NT : NKD;
         const int64_t* grow = f == 2 ? d_growt : d_growk;
@@ -1905,7 +1965,7 @@ int rom_init_state(const lh_rom* R, const lh_instance_desc* inst, const double* 
 namespace lh {
 namespace rom {
 
-template <int DIM, class TT, bool RES>
+template <int DIM, class TT, bool RES, bool RK4 = false>
 static int blocks_per_cu(size_t dyn, int* nb);
 
 // LAGROM_XCD_MAP=0 turns the XCD-aware placement off (the exchange then always
@@ -1915,16 +1975,16 @@ static bool xcd_map_enabled() {
     return !(e && e[0] == '0');
 }
 
-template <int DIM, class TT, bool RES>
+template <int DIM, class TT, bool RES, bool RK4 = false>
 static int launch_rom(const lh_rom* R, const RomArgs& A, size_t dyn, hipStream_t s) {
-    auto kern = rom_step_kernel<DIM, TT, RES>;
+    auto kern = rom_step_kernel<DIM, TT, RES, RK4>;
     if (dyn > 0) LH_HIP_CHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
     dim3 grid(R->n_inst * R->G), block(BLK);
     if (R->G > 1) {
         RomArgs a = A;
         // keep each instance's workgroups on one XCD when the padded grid is still co-resident
         int nb = 0;
-        const int rc = blocks_per_cu<DIM, TT, RES>(dyn, &nb);
+        const int rc = blocks_per_cu<DIM, TT, RES, RK4>(dyn, &nb);
         if (rc) return rc;
         const int64_t padded = 8LL * ((R->n_inst + 7) / 8) * R->G;
         a.xcd_map = xcd_map_enabled() && padded <= (int64_t)nb * cu_count();
@@ -1957,14 +2017,17 @@ template <int DIM>
 static int dispatch(const lh_rom* R, const RomArgs& A, bool f32, hipStream_t s) {
     const LaunchShape sh = launch_shape(R, A.G, f32, A.mlp_floats);
     const size_t dyn = sh.dyn;
+    if (A.flags & LH_RK4)
+        return sh.resident ? launch_rom<DIM, double, true, true>(R, A, dyn, s)
+                           : launch_rom<DIM, double, false, true>(R, A, dyn, s);
     if (f32)
         return sh.resident ? launch_rom<DIM, float, true>(R, A, dyn, s) : launch_rom<DIM, float, false>(R, A, dyn, s);
     return sh.resident ? launch_rom<DIM, double, true>(R, A, dyn, s) : launch_rom<DIM, double, false>(R, A, dyn, s);
 }
 
-template <int DIM, class TT, bool RES>
+template <int DIM, class TT, bool RES, bool RK4>
 static int blocks_per_cu(size_t dyn, int* nb) {
-    auto kern = rom_step_kernel<DIM, TT, RES>;
+    auto kern = rom_step_kernel<DIM, TT, RES, RK4>;
     if (dyn > 0) LH_HIP_CHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
     LH_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, (const void*)kern, BLK, dyn));
     return LH_OK;
@@ -1977,7 +2040,12 @@ static int fits_coresident(const lh_rom* R, uint32_t flags, bool* ok) {
     const int mlp = (flags & LH_SURROGATE) ? R->mlp_floats : 0;
     const LaunchShape sh = launch_shape(R, R->G, f32, mlp);
     int nb = 0, rc;
-    if (R->p->dim == 2)
+    if (flags & LH_RK4)
+        rc = R->p->dim == 2 ? (sh.resident ? blocks_per_cu<2, double, true, true>(sh.dyn, &nb)
+                                           : blocks_per_cu<2, double, false, true>(sh.dyn, &nb))
+                            : (sh.resident ? blocks_per_cu<3, double, true, true>(sh.dyn, &nb)
+                                           : blocks_per_cu<3, double, false, true>(sh.dyn, &nb));
+    else if (R->p->dim == 2)
         rc = f32 ? (sh.resident ? blocks_per_cu<2, float, true>(sh.dyn, &nb) : blocks_per_cu<2, float, false>(sh.dyn, &nb))
                  : (sh.resident ? blocks_per_cu<2, double, true>(sh.dyn, &nb) : blocks_per_cu<2, double, false>(sh.dyn, &nb));
     else
@@ -2022,6 +2090,8 @@ int rom_step(const lh_rom* R, lh_rom_state* state, int32_t max_steps, uint32_t f
     using namespace lh::rom;
     LH_REQUIRE(R && state && max_steps >= 0, "rom_step: bad arguments");
     LH_REQUIRE(!(flags & LH_REPLAY_DT) || (dt_replay && n_replay >= 0), "rom_step: replay needs dt_replay");
+    LH_REQUIRE(!(flags & LH_RK4) || !(flags & (LH_FP32_LIFT | LH_SURROGATE)),
+               "rom_step: LH_RK4 takes neither LH_FP32_LIFT nor LH_SURROGATE");
     const lh_problem* p = R->p;
     RomArgs A;
     A.T = p->tab;

@@ -20,10 +20,12 @@ LH_OK = 0
 LH_ERRORS = {-1: "LH_EINVAL", -2: "LH_EWORKSPACE", -3: "LH_EDEVICE", -4: "LH_ETANGLED", -5: "LH_ENONFINITE",
              -6: "LH_EDTCOLLAPSE", -7: "LH_ERANK"}
 LH_F1, LH_FTV, LH_TAU, LH_KEEP_STRESS, LH_USE_STRESS, LH_NO_BC = 1, 2, 4, 8, 16, 32
-LH_FP32_LIFT, LH_REPLAY_DT, LH_FIXED_DT, LH_SURROGATE = 1, 2, 4, 8
+LH_FP32_LIFT, LH_REPLAY_DT, LH_FIXED_DT, LH_SURROGATE, LH_RK4 = 1, 2, 4, 8, 16
 LH_MLP_MAX_LAYERS = 8
 LH_NMAX = 64
-KIND = {"taylor_green": 1, "sedov": 2, "gresho": 3}
+KIND = {"taylor_green": 1, "sedov": 2, "gresho": 3, "triple_point": 4}
+SCHEMES = {"rk2avg": 0, "rk4": 1}
+SNAPS_PER_STEP = {"rk2avg": 2, "rk4": 4}
 
 
 class LagromError(RuntimeError):
@@ -42,7 +44,7 @@ class FomRunDesc(C.Structure):
     _fields_ = [("t_final", C.c_double), ("fixed_dt", C.c_double), ("dt_replay", C.POINTER(C.c_double)),
                 ("n_replay", C.c_int32), ("max_steps", C.c_int32), ("snap_x", C.c_void_p), ("snap_v", C.c_void_p),
                 ("snap_e", C.c_void_p), ("max_snap", C.c_int32), ("t_out", C.POINTER(C.c_double)),
-                ("dt_out", C.POINTER(C.c_double))]
+                ("dt_out", C.POINTER(C.c_double)), ("scheme", C.c_int32)]
 
 
 class FomRunStats(C.Structure):
@@ -128,7 +130,7 @@ _SIGNATURES = {
     "lh_mass_orthonormalize": (_I32, [_VP, _I32, _VP, _I32, _I64, _VP]),
     "lh_windows_by_samples": (_I32, [_I32, C.POINTER(C.POINTER(_D)), C.POINTER(_I32), _I32, C.POINTER(_D), _I32,
                                      C.POINTER(_I32)]),
-    "lh_window_columns": (_I32, [C.POINTER(_D), _I32, C.POINTER(_D), _I32, C.POINTER(_I32), C.POINTER(_I32)]),
+    "lh_window_columns": (_I32, [C.POINTER(_D), _I32, C.POINTER(_D), _I32, _I32, C.POINTER(_I32), C.POINTER(_I32)]),
     "lh_status_read": (_I32, [_VP, C.POINTER(_I32), _VP]),
     "lh_last_error": (C.c_char_p, []),
 }
@@ -289,13 +291,16 @@ class Problem:
         return f.value
 
     def fom_run(self, x, v, e, t_final, fixed_dt=0.0, dt_replay=None, max_steps=200000, record=True,
-                max_snap=None):
-        """Advance (x, v, e) in place; returns dict with times, steps and snapshot matrices."""
+                max_snap=None, scheme="rk2avg"):
+        """Advance (x, v, e) in place with RK2-average or RK4; returns dict with times, steps and snapshot
+        matrices (r = 2 or 4 snapshots per step)."""
         lib = load()
         ws = torch.empty(int(lib.lh_fom_run_workspace_size(self.h)), dtype=torch.uint8, device="cuda")
         d = FomRunDesc()
         d.t_final = float(t_final)
         d.fixed_dt = float(fixed_dt)
+        d.scheme = SCHEMES[scheme]
+        r = SNAPS_PER_STEP[scheme]
         rep = None
         if dt_replay is not None:
             rep = (C.c_double * len(dt_replay))(*[float(h) for h in dt_replay])
@@ -305,7 +310,7 @@ class Problem:
         d.max_steps = int(max_steps)
         snaps = None
         if record:
-            ms = int(max_snap if max_snap is not None else 2 * max_steps)
+            ms = int(max_snap if max_snap is not None else r * max_steps)
             snaps = (torch.empty((ms, self.NV), dtype=torch.float64, device="cuda"),
                      torch.empty((ms, self.NV), dtype=torch.float64, device="cuda"),
                      torch.empty((ms, self.NE), dtype=torch.float64, device="cuda"))
@@ -320,7 +325,7 @@ class Problem:
                               stream_handle()))
         n = st.n_steps
         out = dict(t=list(t_out[: n + 1]), dt=list(dt_out[:n]), n_steps=n, n_rejected=st.n_rejected,
-                   n_snap=st.n_snap)
+                   n_snap=st.n_snap, r=r)
         if record:
             out["snaps"] = tuple(s[: st.n_snap] for s in snaps)  # rows are snapshots
         return out

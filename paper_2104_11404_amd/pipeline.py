@@ -32,24 +32,25 @@ def windows_physical(t_final: float, n_windows: int) -> list:
     return [t_final * (w + 1) / n_windows for w in range(n_windows)]
 
 
-def window_columns(t: list, T: list):
+def window_columns(t: list, T: list, r: int = 2):
     so = lib.load()
     ta = (C.c_double * len(t))(*t)
     Ta = (C.c_double * len(T))(*T)
     first = (C.c_int32 * len(T))()
     ncol = (C.c_int32 * len(T))()
-    lib._check(so.lh_window_columns(ta, len(t) - 1, Ta, len(T), first, ncol))
+    lib._check(so.lh_window_columns(ta, len(t) - 1, Ta, len(T), int(r), first, ncol))
     return list(first), list(ncol)
 
 
-def fom_trajectory(P: lib.Problem, t_final: float, fixed_dt: float = 0.0, max_steps: int = 200000):
+def fom_trajectory(P: lib.Problem, t_final: float, fixed_dt: float = 0.0, max_steps: int = 200000,
+                   scheme: str = "rk2avg"):
     """GPU FOM from the problem's initial state; returns initial state, final state and snapshots."""
     x0, v0, e0 = P.initial_state()
     x, v, e = x0.clone(), v0.clone(), e0.clone()
-    probe = P.fom_run(x, v, e, t_final, fixed_dt=fixed_dt, max_steps=max_steps, record=False)
+    probe = P.fom_run(x, v, e, t_final, fixed_dt=fixed_dt, max_steps=max_steps, record=False, scheme=scheme)
     x, v, e = x0.clone(), v0.clone(), e0.clone()
     out = P.fom_run(x, v, e, t_final, fixed_dt=fixed_dt, max_steps=probe["n_steps"], record=True,
-                    max_snap=2 * probe["n_steps"])
+                    max_snap=lib.SNAPS_PER_STEP[scheme] * probe["n_steps"], scheme=scheme)
     out.update(y0=(x0, v0, e0), y_final=(x, v, e))
     return out
 
@@ -77,7 +78,7 @@ def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_f
     so = lib.load()
     stream = lib.stream_handle()
     sizes = (P.NV, P.NV, P.NE)
-    cols = [window_columns(tr["t"], T) for tr in trajs]
+    cols = [window_columns(tr["t"], T, tr.get("r", 2)) for tr in trajs]
     windows, train_offsets = [], []
     for w, Tw in enumerate(T):
         m_tot = sum(c[1][w] for c in cols)
@@ -167,10 +168,15 @@ def build_batch(wl, lam=(2.0, 2.0), energy_frac=0.9999, verbose=False):
 
 
 def snapshot_times(traj) -> list:
-    """Times of the recorded states: stage n+1/2 at t_n + dt_n / 2, step n+1 at t_{n+1}."""
+    """Times of the recorded states: RK2-average stage n+1/2 at t_n + dt_n / 2 and step n+1 at t_{n+1};
+    RK4 stages at t_n + dt_n / 2 (twice) and t_{n+1}, then step n+1 at t_{n+1}."""
     out = []
+    r = traj.get("r", 2)
     for n, h in enumerate(traj["dt"]):
-        out += [traj["t"][n] + 0.5 * h, traj["t"][n + 1]]
+        if r == 4:
+            out += [traj["t"][n] + 0.5 * h, traj["t"][n] + 0.5 * h, traj["t"][n + 1], traj["t"][n + 1]]
+        else:
+            out += [traj["t"][n] + 0.5 * h, traj["t"][n + 1]]
     return out
 
 
