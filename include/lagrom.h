@@ -561,6 +561,14 @@ int mlp_forward(lh_mlp* m, const double* X, int32_t B, double* Y, float* const* 
  * NULL) receives the loss before the step. */
 int mlp_gradients(lh_mlp* m, const double* X, const double* T, int32_t B, float* const* gW, float* const* gb,
                   float* loss, hipStream_t stream);
+/* The output gradients of the layers from the last mlp_gradients or
+ * mlp_train_step call, which must have had batch B: D[l] (device FP32,
+ * B x sizes[l+1], may be NULL to skip) receives D_{l+1} = dloss/dz_{l+1},
+ * before its bfloat16 rounding (for the output layer 2 (y~ - t~) / (B d_out)
+ * with t~ the normalised targets; for a hidden layer
+ * (r(D_{l+2}) r(W_{l+1})^T) * (1 - z_{l+1}^2)), so that each layer's
+ * products can be checked from the network's own inputs. */
+int mlp_last_deltas(const lh_mlp* m, int32_t B, float* const* D, hipStream_t stream);
 /* One Adam step with learning rate lr on the minibatch (X, T). */
 int mlp_train_step(lh_mlp* m, const double* X, const double* T, int32_t B, double lr, float* loss,
                    hipStream_t stream);

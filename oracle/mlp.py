@@ -291,7 +291,10 @@ def run_surrogate(op: F.Operator, rom: R.ROM, nets: dict, y0: tuple, t_final: fl
                   tol: float, r=bf16, max_steps=10**7, fixed_dt=None) -> SurrogateRun:
     """Online phase with the network in the windows of ``nets`` ({window: MLP}), DEIM elsewhere.
 
-    With ``fixed_dt`` every step has that size and nothing is rejected (as ``rom.run_rom``).
+    The first step of a window and every audit_every-th accepted step after it is an audit; a failed
+    audit, or a surrogate step whose new state is not finite, sends the rest of the window to DEIM
+    (the non-finite step itself is redone with DEIM).  With ``fixed_dt`` every step has that size and
+    nothing is rejected (as ``rom.run_rom``).
     """
     w = 0
     yhat = R.initial_coords(rom, y0)
@@ -322,6 +325,11 @@ def run_surrogate(op: F.Operator, rom: R.ROM, nets: dict, y0: tuple, t_final: fl
         else:
             new = surrogate_step(win, net, *yhat, t, h, r)
             tau = tau_est
+            if not all(np.all(np.isfinite(c)) for c in new):
+                # a non-finite network state: the rest of the window, this step included, takes DEIM
+                fallen = True
+                run.fallback_windows.append(w)
+                new, _, tau = R.rom_step(op, win, *yhat, h)
         if fixed_dt is None:
             if h >= tau:
                 dt = F.BETA1 * h

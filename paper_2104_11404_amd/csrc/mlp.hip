@@ -720,6 +720,19 @@ int mlp_gradients(lh_mlp* m, const double* X, const double* T, int32_t B, float*
     return launch_check("mlp_gradients");
 }
 
+int mlp_last_deltas(const lh_mlp* m, int32_t B, float* const* D, hipStream_t s) {
+    using namespace lh;
+    using namespace lh::mlp;
+    LH_REQUIRE(m && D && B >= 1 && B <= m->max_batch, "mlp_last_deltas: bad arguments");
+    for (int l = 1; l <= m->L; ++l) {
+        if (!D[l - 1]) continue;
+        const int64_t n = (int64_t)B * m->sizes[l];
+        hipLaunchKernelGGL(unpad_kernel, dim3(blocks(n)), dim3(BLK), 0, s, m->del32[l], B, m->sizes[l], m->npad[l],
+                           D[l - 1]);
+    }
+    return launch_check("mlp_last_deltas");
+}
+
 int mlp_fit_normalisation(lh_mlp* m, const double* X, const double* T, int32_t B, hipStream_t s) {
     using namespace lh;
     using namespace lh::mlp;

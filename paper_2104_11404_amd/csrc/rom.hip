@@ -874,7 +874,8 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         }
         const bool has_net = surrogate && W.net.L > 0 && !fallen;
         const bool audit_now = has_net && since % W.audit_every == 0;
-        double tau;
+        const bool surr_step = has_net && !audit_now;  // this attempt takes the network's forces
+        double tau = INFINITY;
         if constexpr (RK4) {
             // ---- classical RK4 (eq. RK4) of the reduced system: stage state in S.yh, the slope sums
             // kv1 + 2 kv2 + 2 kv3 + kv4 (ke likewise) in S.yn[1], S.yn[2], and the same sum of the stage
@@ -918,7 +919,8 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             x_update(W, L, S.y[0], h, S.vc, S.yn[0], S.red);
             __syncthreads();
             evals += 4 * W.n_el;
-        } else if (has_net && !audit_now) {
+        } else {
+        if (surr_step) {
             // ---- surrogate step: the network's F^1 and F^tv = g + H v^_c in both stages
             float* out;
             mlp_eval(W.net, S.y[0], S.y[1], S.y[2], W.n, t, mscr, out);
@@ -941,6 +943,16 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             for (int i = tid; i < W.n[2]; i += BLK) S.yn[2][i] = S.y[2][i] + h * S.ftvh[i];
             x_update(W, L, S.y[0], h, S.vc, S.yn[0], S.red);
             __syncthreads();
+            // a non-finite network state sends the rest of the window to DEIM: this step is attempted
+            // again, with the same size, on the DEIM chain
+            int bad = 0;
+            for (int f = 0; f < 3; ++f)
+                for (int i = tid; i < W.n[f]; i += BLK) bad |= !isfinite(S.yn[f][i]);
+            if (__syncthreads_or(bad)) {
+                fallen = 1;
+                ++n_fallbacks;
+                continue;
+            }
             tau = tau_est;
         } else {
         // ---- stage 1 at y_n
@@ -993,6 +1005,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         tau = fmin(tau1, tau2);
         if (audit_now) tau_est = tau;
         }
+        }
         if (s_status & (LH_FLAG_TANGLED | LH_FLAG_NONFINITE | LH_FLAG_TIMEOUT)) {
             done = true;
             break;
@@ -1009,7 +1022,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         t = t + h;
         ++n_steps;
         ++accepted;
-        if (has_net && !audit_now) ++n_surr;
+        if (surr_step) ++n_surr;
         ++since;
         // window change (eq. ic-tw): y^w = T_w y^{w-1} + c_w
         bool moved = false;

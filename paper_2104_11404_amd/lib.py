@@ -117,6 +117,7 @@ _SIGNATURES = {
     "mlp_get_params": (_I32, [_VP, _VP, _VP, _VP]),
     "mlp_forward": (_I32, [_VP, _VP, _I32, _VP, _VP, _VP]),
     "mlp_gradients": (_I32, [_VP, _VP, _VP, _I32, _VP, _VP, _VP, _VP]),
+    "mlp_last_deltas": (_I32, [_VP, _I32, _VP, _VP]),
     "mlp_train_step": (_I32, [_VP, _VP, _VP, _I32, _D, _VP, _VP]),
     "rom_surrogate_targets": (_I32, [_VP, _I32, _I32, _VP, _I32, _I32, _VP, _VP]),
     "mlp_fit_normalisation": (_I32, [_VP, _VP, _VP, _I32, _VP]),
@@ -593,6 +594,12 @@ class Mlp:
         _check(load().mlp_gradients(self.h, ptr(X), ptr(T), B, _ptr_array(gW), _ptr_array(gb), ptr(loss),
                                     stream_handle()))
         return gW, gb, loss
+
+    def last_deltas(self, B):
+        """D_1 .. D_L (FP32, B x sizes[l]) of the last gradients or training call with batch B."""
+        D = [torch.empty((int(B), self.sizes[l + 1]), dtype=torch.float32, device="cuda") for l in range(self.L)]
+        _check(load().mlp_last_deltas(self.h, int(B), _ptr_array(D), stream_handle()))
+        return D
 
     def fit_normalisation(self, X, T):
         _check(load().mlp_fit_normalisation(self.h, ptr(X), ptr(T), int(X.shape[0]), stream_handle()))

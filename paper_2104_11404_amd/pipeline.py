@@ -121,7 +121,7 @@ def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_f
         z1, a1 = lib.rom_sample_deim(PF1, int(round(lam[0] * dims[1])), method=sampler)
         z2, a2 = lib.rom_sample_deim(PFtv, int(round(lam[1] * dims[2])), method=sampler)
         os_on = online_offsets[w] if isinstance(online_offsets, list) else online_offsets
-        windows.append(dict(t_end=Tw, phi=phis, os=list(os_on), z1=z1, z2=z2, a1=a1, a2=a2))
+        windows.append(dict(t_end=Tw, phi=phis, os=list(os_on), z1=z1, z2=z2, a1=a1, a2=a2, phiF=(PF1, PFtv)))
     return dict(t_final=t_final if t_final is not None else T[-1], windows=windows, window_ic=window_ic,
                 basis=basis, train_offsets=train_offsets)
 

@@ -96,11 +96,15 @@ def test_batched_gresho_fp32_lift(gpu_lib, batch):
     assert np.median(errs, axis=0).max() < 2e-5
 
 
-def test_batched_launch_replays_from_a_graph(gpu_lib, batch):
-    """init_state + rom_step captured once and replayed; every replay equals the eager run."""
+@pytest.mark.parametrize("Gw", [2, 20])
+def test_batched_launch_replays_from_a_graph(gpu_lib, batch, Gw):
+    """init_state + rom_step captured once and replayed, as a cooperative launch of G > 1 workgroups per
+    instance; every replay equals the eager run at the same launch shape."""
     wl, items = batch
-    print("[case] batched gresho graph replay", flush=True)
+    print(f"[case] batched gresho graph replay G={Gw}", flush=True)
     P, G, y0 = _launch(wl, items)
+    G.set_workgroups(Gw)
+    assert G.workgroups() == Gw
     G.init_state(*y0)
     G.step()
     torch.cuda.synchronize()

@@ -102,6 +102,33 @@ def test_gradients_and_adam_match_oracle(gpu_lib):
         assert nrel(Wg[l].cpu().numpy() - W0[l], net.W[l] - W0[l]) < 5e-2, l
 
 
+def test_backward_layer_by_layer_from_the_gpus_own_activations_and_deltas(gpu_lib):
+    """Each product of the backward pass from the GPU's own bfloat16-rounded inputs to it: the output
+    delta from the GPU's normalised output, D_l = (r(D_{l+1}) r(W_l)^T) (1 - z_l^2), grad W_l =
+    r(z_l)^T r(D_{l+1}) and grad b_l = column sums of D_{l+1}, at the FP32 accumulation bound."""
+    sizes = [61, 256, 256, 256, 440]
+    print(f"[case] mlp backward per layer {sizes}", flush=True)
+    net = make_net(sizes, 51)
+    g = W.rng(52)
+    B = 300
+    X = g.normal(0, 1, (B, 61))
+    T = g.normal(0, 1, (B, 440)) * net.s_out + net.mu_out
+    m = gpu_net(net, 512)
+    _, zs = m.forward(_t(X), trace=True)
+    gW, gb, _ = m.gradients(_t(X), _t(T))
+    D = [d.cpu().numpy().astype(np.float64) for d in m.last_deltas(B)]
+    z = [t.cpu().numpy().astype(np.float64) for t in zs]
+    L = len(net.W)
+    tt = (T - net.mu_out) / net.s_out
+    assert nrel(D[L - 1], 2.0 * (z[L] - tt) / (B * sizes[-1])) < 1e-6
+    for l in range(L - 1, -1, -1):
+        assert nrel(gW[l].cpu().numpy(), M.bf16(z[l]).T @ M.bf16(D[l])) < 1e-5, l
+        assert nrel(gb[l].cpu().numpy(), D[l].sum(axis=0)) < 1e-5, l
+        if l > 0:
+            ref = (M.bf16(D[l]) @ M.bf16(net.W[l]).T) * (1.0 - z[l] ** 2)
+            assert nrel(D[l - 1], ref) < 1e-5, l
+
+
 def test_training_fits_a_teacher_network(gpu_lib):
     from paper_2104_11404_amd import lib
     print("[case] mlp training on a teacher", flush=True)
@@ -196,6 +223,39 @@ def test_failed_audit_falls_back_bitwise(gpu_lib, tg_surrogate):
     assert st.n_steps == s2.n_steps and st.t == s2.t
     for a, b in zip(G.coords(0), G2.coords(0)):
         np.testing.assert_array_equal(a, b)
+
+
+def test_nonfinite_surrogate_step_falls_back_bitwise(gpu_lib, tg_surrogate):
+    """A network that is exactly 0 at the zero initial coordinates (the audit passes) and overflows the
+    first surrogate step: the non-finite state is caught, the step is redone with DEIM and the rest of the
+    window stays on DEIM, as in the oracle; the run is bitwise the plain ROM's."""
+    from paper_2104_11404_amd import lib
+    from tests.test_oracle_mlp import blowup_net
+    wl, op, tr, y0, rom, X, T = tg_surrogate
+    print("[case] surrogate non-finite fallback tg2d", flush=True)
+    din, dout = M.layout(rom.windows[0])
+    net = blowup_net([din, 8, dout])
+    with np.errstate(over="ignore", invalid="ignore"):
+        run = M.run_surrogate(op, rom, {0: net}, y0, wl.t_final, audit_every=5, tol=1.0)
+    assert run.audits == 1 and run.fallback_windows == [0] and run.surrogate_steps == 0
+    P = lib.Problem.from_workload(wl)
+    G = lib.Rom(P, [gpu_instance(rom, wl.t_final)])
+    m = gpu_net(net, 16)
+    G.attach_surrogate(0, 0, m, audit_every=5, tol=1.0)
+    G.init_state(_t(y0[0]), _t(y0[1]), _t(y0[2]))
+    G.step(flags=lib.LH_SURROGATE)
+    st = G.states()[0]
+    assert st.status == 0 and st.done == 1
+    assert st.n_fallbacks == 1 and st.n_audits == 1 and st.n_surrogate_steps == 0
+    G2 = lib.Rom(P, [gpu_instance(rom, wl.t_final)])
+    G2.init_state(_t(y0[0]), _t(y0[1]), _t(y0[2]))
+    G2.step()
+    s2 = G2.states()[0]
+    assert st.n_steps == s2.n_steps and st.t == s2.t
+    for a, b in zip(G.coords(0), G2.coords(0)):
+        np.testing.assert_array_equal(a, b)
+    for a, b in zip(G.coords(0), R.run_rom(op, rom, y0, wl.t_final).yhat):
+        assert rel(a, b) < 1e-9
 
 
 def test_trained_network_gains_over_untrained_and_over_deim_work(gpu_lib):

@@ -6,6 +6,7 @@ import pytest
 import torch
 
 import workloads as W
+from oracle import deim as D
 from oracle import fom as F
 from oracle import rom as R
 from oracle.problems import initial_state
@@ -66,6 +67,11 @@ def test_gpu_offline_pipeline_against_oracle(gpu_lib):
             k = min(4, G.shape[1])
             s = np.linalg.svd(G[:, :k].T @ O[:, :k], compute_uv=False)
             assert s.min() > 1 - 1e-8
+    # the sampler on the GPU-built SNS bases picks the oracle's greedy rows bit for bit
+    for wd in inst["windows"]:
+        for z, PF in ((wd["z1"], wd["phiF"][0]), (wd["z2"], wd["phiF"][1])):
+            U = PF.cpu().numpy().T
+            np.testing.assert_array_equal(z.cpu().numpy(), D.greedy_deim(U, int(z.numel())))
     G = lib.Rom(P, [inst])
     G.init_state(*traj["y0"])
     G.step()

@@ -152,6 +152,32 @@ def test_failed_audit_falls_back_to_the_plain_rom(tg_rom):
         np.testing.assert_array_equal(a, b)
 
 
+def blowup_net(sizes, seed=4):
+    """A network that outputs exactly 0 at the all-zero input (zero biases, tanh(0) = 0) and, through an
+    output scale of 1e300, overflows the first surrogate step elsewhere: an audit at the zero initial
+    coordinates (initial-state offsets, t = 0) passes, the next step's state is not finite."""
+    g = np.random.default_rng(seed)
+    Ws, bs = M.glorot_init(sizes, g)
+    return M.MLP(Ws, [np.zeros_like(b) for b in bs], np.zeros(sizes[0]), np.ones(sizes[0]), np.zeros(sizes[-1]),
+                 np.full(sizes[-1], 1e300))
+
+
+def test_nonfinite_surrogate_state_falls_back_and_redoes_the_step(tg_rom):
+    op, tr, y0, rom = tg_rom
+    din, dout = M.layout(rom.windows[0])
+    net = blowup_net([din, 8, dout])
+    nv = rom.windows[0].dims[1]
+    with np.errstate(over="ignore", invalid="ignore"):
+        new = M.surrogate_step(rom.windows[0], net, *(0.01 * np.ones(n) for n in rom.windows[0].dims), 1e-3, 1e-3)
+        assert not all(np.all(np.isfinite(c)) for c in new)
+        run = M.run_surrogate(op, rom, {0: net}, y0, 0.03, audit_every=5, tol=1.0)
+    ref = R.run_rom(op, rom, y0, 0.03)
+    assert run.audits == 1 and run.fallback_windows == [0] and run.surrogate_steps == 0, (run.audits, nv)
+    assert run.dt == ref.dt
+    for a, b in zip(run.yhat, ref.yhat):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_training_set_inputs_are_projected_snapshots(tg_rom):
     op, tr, y0, rom = tg_rom
     win = rom.windows[0]
