@@ -230,7 +230,7 @@ int rom_build_basis(const double* S, int64_t N, int32_t m, int64_t ldS, double e
 
 size_t rom_sample_deim_workspace_size(int64_t N, int32_t n, int32_t n_s);
 
-/* Oversampled greedy DEIM (Sec. 3.6) on the nonlinear-term basis U
+/* Oversampled greedy DEIM (Sec. 3.7) on the nonlinear-term basis U
  * (dev, N x n, ld): n_s = min(N, n_s) row indices written to idx (dev,
  * selection order) and the pseudo-inverse (Z^T U)^+ (dev, n x n_s,
  * column-major, ld n) of eq. sol-ls-hyper.  Iteration k takes
@@ -242,7 +242,7 @@ int rom_sample_deim(const double* U, int64_t N, int32_t n, int64_t ld, int32_t n
 
 size_t rom_sample_qdeim_workspace_size(int64_t N, int32_t n, int32_t n_s);
 
-/* Q-DEIM (Sec. 3.6, the sampler based on QR with column pivoting): the
+/* Q-DEIM (Sec. 3.7, the sampler based on QR with column pivoting): the
  * same outputs as rom_sample_deim, with the rows taken as the pivots of the
  * QR factorisation with column pivoting of U^T.  Step k takes the unselected
  * row j of largest ||W[j, k:]|| (W = U with the previous steps' Householder
@@ -351,7 +351,8 @@ void rom_destroy(lh_rom* r);
  * the initial state y0 = (x0, v0, e0) (dev arrays, one set per instance
  * packed as x0[i*N_V], v0[i*N_V], e0[i*N_E]); inst (host) is the array
  * passed to rom_create.  dt = dt0 when dt0 > 0, otherwise the first rom_step
- * call starts from 0.85 tau(y~_0). */
+ * call starts from 0.85 tau(y~_0).  The projections use the ROM's own partial
+ * sum buffer, so two rom_init_state calls on one ROM must not overlap. */
 int rom_init_state(const lh_rom* r, const lh_instance_desc* inst, const double* x0, const double* v0,
                    const double* e0, double dt0, lh_rom_state* state, hipStream_t stream);
 
@@ -392,7 +393,7 @@ int rom_step(const lh_rom* r, lh_rom_state* state, int32_t max_steps, uint32_t f
 int rom_lift(const lh_rom* r, const lh_rom_state* state, int32_t inst, const lh_instance_desc* inst_desc,
              double* x, double* v, double* e, hipStream_t stream);
 
-/* Window switch with the previous-window offsets (Sec. 4.5,
+/* Window switch with the previous-window offsets (Sec. 4.6.2,
  * eq. previous_os) for an instance created with LH_OFFSETS_PREVIOUS that
  * rom_step has stopped at the end of window w: its offsets
  * become its lifted state os_w + Phi_w y^_w (a full-size lift, kept in the
@@ -465,7 +466,7 @@ int lh_idw_weights(const double* params, int32_t K, int32_t d, const double* mu,
  * w (host, K), out (dev, N; may not alias any x[k]). */
 int lh_weighted_sum(const double* const* x, const double* w, int32_t K, int64_t N, double* out, hipStream_t stream);
 
-/* Snapshot deviations (Sec. 3.4): out[:, j] = snaps[:, j] - os for j < m.
+/* Snapshot deviations (Sec. 3.5): out[:, j] = snaps[:, j] - os for j < m.
  * snaps (dev, N x m, ld), os (dev, N), out (dev, N x m, ldo); out may be a
  * column block of a larger matrix holding several parameters' snapshots. */
 int lh_snapshot_deviation(const double* snaps, int64_t N, int32_t m, int64_t ld, const double* os, double* out,
@@ -479,7 +480,7 @@ int lh_snapshot_deviation(const double* snaps, int64_t N, int32_t m, int64_t ld,
 int lh_project_snapshots(const double* Phi, int32_t n, int64_t N, int64_t ldp, const double* S, int32_t m,
                          int64_t lds, const double* os, double* out, int64_t ldo, hipStream_t stream);
 
-/* SNS nonlinear bases (Sec. 3.5): out = M_V in with the wall rows and
+/* SNS nonlinear bases (Sec. 3.6): out = M_V in with the wall rows and
  * columns eliminated and identity on the wall rows (the form whose inverse
  * lh_mass_solve_v applies), and out = M_E in.  One column (N_V resp. N_E,
  * dev); in and out must differ for the kinematic apply. */

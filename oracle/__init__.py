@@ -21,7 +21,7 @@ Modules, in the order of the paper's method:
 * ``pod``      -- POD by thin SVD and the energy criterion (eq. SVD,
                   eq. energy_criteria).
 * ``deim``     -- oversampled greedy DEIM, pseudo-inverse, element closure
-                  (Sec. 3.6, 3.3).
+                  (Sec. 3.7, 3.3).
 * ``rom``      -- SNS hyper-reduced ROM with RK2-average and windows
                   (eq. RK2-avg-rom-hr, eq. rom-hr-sns, eq. ic-tw, eq. relerrors).
 * ``mlp``      -- the MLP surrogate of the reduced force coefficients (not

@@ -2,7 +2,7 @@
 
 Hyper-reduction replaces f by Phi_F (Z^T Phi_F)^+ Z^T f, where Z selects n_s
 rows (eq. DEIM_f, eq. sol-ls-hyper); only the indices and the n x n_s matrix
-(Z^T Phi_F)^+ are stored.  The rows are chosen greedily (Sec. 3.6): classic
+(Z^T Phi_F)^+ are stored.  The rows are chosen greedily (Sec. 3.7): classic
 DEIM takes one row per basis vector, the row where the residual of
 interpolating the next basis vector from the previous ones at the rows chosen
 so far is largest; the oversampled variant (GNAT / Carlberg) allows
@@ -23,7 +23,7 @@ Reading of the oversampled greedy (the paper only cites it):
 * n_s = N returns all rows in order.
 
 For n_s = n this is classic DEIM, whose indices equal the pivots of
-row-pivoted LU of U (Sec. 3.6).
+row-pivoted LU of U (Sec. 3.7).
 """
 from __future__ import annotations
 
@@ -77,7 +77,7 @@ def greedy_deim(U: np.ndarray, ns: int) -> np.ndarray:
 
 
 def qdeim(U: np.ndarray, ns: int) -> np.ndarray:
-    """Q-DEIM row indices (Sec. 3.6 names it as the alternative to the greedy choice): the pivots of
+    """Q-DEIM row indices (Sec. 3.7 names it as the alternative to the greedy choice): the pivots of
     the QR factorisation with column pivoting of U^T.
 
     Column j of U^T is row j of U.  Step k of the pivoted QR takes the unselected row j of largest

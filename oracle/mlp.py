@@ -5,7 +5,7 @@ path imports this module.
 
 The paper has no learned component (it mentions neural-network ROMs only as
 related work, Sec. 1); the surrogate is an addition to the hyper-reduced ROM
-of Sec. 3.6 and the windowed SNS system (eq. rom-hr-sns):
+of Sec. 3.3 and the windowed SNS system (eq. rom-hr-sns):
 
 * Network: z0 = ([x^, v^, e^, t] - mu_in) / s_in; for l = 1..L-1,
   a_l = tanh(r(a_{l-1}) r(W_l) + b_l); output y~ = r(a_{L-1}) r(W_L) + b_L and

@@ -5,7 +5,7 @@ Online system (eq. rom-hr-sns, windowed as eq. rom-hr-tw):
     dv^/dt = -F^1,  de^/dt = F^tv,  dx^/dt = Phi_x^T v_os + Phi_x^T Phi_v v^,
 
 where, with the SNS bases Phi_F1 = M_V Phi_v and Phi_Ftv = M_E Phi_e
-(Sec. 3.5), the reduced right-hand sides are the DEIM least-squares
+(Sec. 3.6), the reduced right-hand sides are the DEIM least-squares
 coefficients F^1 = (Z1^T Phi_F1)^+ Z1^T F.1 and F^tv = (Z2^T Phi_Ftv)^+ Z2^T F^T.v
 (eq. sol-ls-hyper, eq. sol-ls-hyper-2).  The fully discrete scheme is
 RK2-average applied to it (eq. RK2-avg-rom-hr): the energy uses the lifted
@@ -64,7 +64,7 @@ class ROM:
 
 
 def sns_bases(op: F.Operator, Phi_v: np.ndarray, Phi_e: np.ndarray):
-    """Phi_F1 = M_V Phi_v (eliminated form), Phi_Ftv = M_E Phi_e (Sec. 3.5)."""
+    """Phi_F1 = M_V Phi_v (eliminated form), Phi_Ftv = M_E Phi_e (Sec. 3.6)."""
     return op.Mv_eff @ Phi_v, op.Me @ Phi_e
 
 
@@ -152,7 +152,7 @@ def build_rom(op, trajs, offsets, T_ends, energy_frac=0.9999, n_fixed=None, lam=
     reduced operators.  window_ic: "orthogonal" (eq. ic-tw) or "oblique" (eq. ic2-tw: velocity and
     energy projected in the M_V and M_E inner products, position as in eq. ic-tw).
 
-    window_offsets (Sec. 4.5): "initial", every window's snapshots relative to offsets (one initial
+    window_offsets (Sec. 4.6): "initial", every window's snapshots relative to offsets (one initial
     state per trajectory); "window_start", window w's snapshots of trajectory k relative to that
     trajectory's state at the window's start.  online_offsets: one (x, v, e) for every window, or a
     list with one per window (for instance the interpolated offsets of eq. interpolate_os).

@@ -85,7 +85,7 @@ def window_columns(traj, T_ends: list):
 
 
 def window_start_states(traj, y0, T_ends: list) -> list:
-    """The trajectory's state at the start of each window (Sec. 4.5, the offset choice of the
+    """The trajectory's state at the start of each window (Sec. 4.6, the offset choice of the
     previous and the interpolated offsets): y0 for the first window, then the step state at which the
     previous window closed (the window's 'init' column)."""
     out = []

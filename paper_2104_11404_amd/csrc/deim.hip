@@ -1,4 +1,4 @@
-// rom_sample_deim: oversampled greedy DEIM row selection (Sec. 3.6) and the
+// rom_sample_deim: oversampled greedy DEIM row selection (Sec. 3.7) and the
 // pseudo-inverse (Z^T U)^+ of eq. sol-ls-hyper.
 //
 // Iteration k fits U[Z, k] by U[Z, :k] in the least-squares sense on the rows

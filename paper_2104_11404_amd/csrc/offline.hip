@@ -1,5 +1,5 @@
 // Offline helpers of the ROM construction: snapshot deviations, the SNS
-// nonlinear bases Phi_F1 = M_V Phi_v and Phi_Ftv = M_E Phi_e (Sec. 3.5), and
+// nonlinear bases Phi_F1 = M_V Phi_v and Phi_Ftv = M_E Phi_e (Sec. 3.6), and
 // the placement of time windows (Sec. 4.4) with the column ranges of the
 // per-window snapshot matrices (eq. window_sample).
 #include <algorithm>

@@ -1233,20 +1233,33 @@ __global__ void sub_kernel(const double* a, const double* b, double* d, int64_t 
     if (t < n) d[t] = a[t] - b[t];
 }
 
-// y^ = Phi^T (y0 - os), one block per basis column
-__global__ void __launch_bounds__(256) init_coords_kernel(const double* Phi, int64_t N, const double* y0,
-                                                         const double* os, double* out) {
+// y^ = Phi^T (y0 - os) in two passes: block (k, c) sums chunk c of the rows of column k into
+// part[k * INIT_SPLIT + c], then thread k adds its INIT_SPLIT partial sums in chunk order
+constexpr int INIT_SPLIT = 64;
+
+__global__ void __launch_bounds__(256) init_coords_part_kernel(const double* Phi, int64_t N, const double* y0,
+                                                              const double* os, double* part) {
     __shared__ double sh[256];
-    const int k = blockIdx.x;
+    const int k = blockIdx.x, c = blockIdx.y;
+    const int64_t len = (N + INIT_SPLIT - 1) / INIT_SPLIT;
+    const int64_t r0 = (int64_t)c * len, r1 = min(N, r0 + len);
     double acc = 0.0;
-    for (int64_t r = threadIdx.x; r < N; r += 256) acc += Phi[(int64_t)k * N + r] * (y0[r] - os[r]);
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) acc += Phi[(int64_t)k * N + r] * (y0[r] - os[r]);
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[k] = sh[0];
+    if (threadIdx.x == 0) part[k * INIT_SPLIT + c] = sh[0];
+}
+
+__global__ void init_coords_sum_kernel(const double* part, int n, double* out) {
+    const int k = threadIdx.x;
+    if (k >= n) return;
+    double acc = 0.0;
+    for (int c = 0; c < INIT_SPLIT; ++c) acc += part[k * INIT_SPLIT + c];
+    out[k] = acc;
 }
 
 // zero every field of the online state, set the controller step
@@ -1344,6 +1357,7 @@ struct lh_rom {
     std::vector<lh::rom::PrevOs> prev;  // per instance; os == nullptr: offsets as given
     std::vector<char> mass_basis;       // per instance: bases orthonormal in the mass inner products
     double* init_tmp = nullptr;         // [2 max(N_V, N_E)] scratch of their initial projection
+    double* init_part = nullptr;        // [LH_NMAX * INIT_SPLIT] partial sums of the initial projections
 };
 
 namespace lh {
@@ -1911,6 +1925,10 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
         if ((rc = upload(R, R->h_win[i], &dw))) return fail(rc);
         I.win = dw;
     }
+    {
+        const int rc = dev_alloc(R, &R->init_part, (int64_t)LH_NMAX * INIT_SPLIT);
+        if (rc) return fail(rc);
+    }
     bool any_mass = false;
     for (int i = 0; i < n_inst; ++i) any_mass = any_mass || (R->mass_basis[i] = inst[i].basis == LH_BASIS_MASS);
     if (any_mass) {
@@ -1953,7 +1971,9 @@ int rom_init_state(const lh_rom* R, const lh_instance_desc* inst, const double* 
             LH_REQUIRE(w0.n[f] == R->h_win[i][0].n[f], "rom_init_state: description differs from rom_create");
             double* dst = reinterpret_cast<double*>(reinterpret_cast<char*>(state + i) + offsetof(lh_rom_state, yhat)) +
                           f * LH_NMAX;
-            hipLaunchKernelGGL(init_coords_kernel, dim3(w0.n[f]), dim3(256), 0, s, w0.phi[f], N, y0[f], w0.os[f], dst);
+            hipLaunchKernelGGL(init_coords_part_kernel, dim3(w0.n[f], INIT_SPLIT), dim3(256), 0, s, w0.phi[f], N, y0[f],
+                               w0.os[f], R->init_part);
+            hipLaunchKernelGGL(init_coords_sum_kernel, dim3(1), dim3(LH_NMAX), 0, s, R->init_part, w0.n[f], dst);
             if (R->mass_basis[i] && f > 0) {
                 // mass-orthonormal basis: y^ = Phi^T M (y0 - os), the M-orthogonal projection
                 double* d = R->init_tmp;

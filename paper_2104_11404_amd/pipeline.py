@@ -61,7 +61,7 @@ def build_offline(P: lib.Problem, trajs: list, T: list, online_offsets, energy_f
     """Per-window POD, SNS and DEIM (greedy, or Q-DEIM with sampler="qdeim") on the GPU; returns a lib.Rom
     instance description.
 
-    Offsets (Sec. 4.5): with window_offsets="initial", snapshots are taken relative to each
+    Offsets (Sec. 4.6): with window_offsets="initial", snapshots are taken relative to each
     trajectory's own initial state, or to snapshot_offsets (one (x, v, e) for every trajectory) when
     given; with "window_start", window w's snapshots of each trajectory are taken relative to that
     trajectory's state at the window's start (the step state that closed window w - 1).  The offsets
@@ -206,16 +206,39 @@ def surrogate_inputs(rom, inst, w, trajs, t_start=-1.0):
     return X
 
 
-def train_surrogate(rom, inst, w, X, hidden=(256, 256, 256), steps=3000, lr=1e-3, seed=0, lr_final=None):
-    """Train the window's network on the GPU, full batch, on inputs X and the DEIM chain's targets.
+def perturbed_inputs(X, noise, seed=0):
+    """X with one perturbed copy per entry of noise appended: copy k adds to every reduced coordinate
+    a normal draw of standard deviation noise[k] times that column's standard deviation over X (the
+    time column is left as it is).  Training on the DEIM chain's targets at such states teaches the
+    network how the reduced forces respond to a state off the training trajectories, which is where a
+    closed-loop surrogate run drifts."""
+    if not noise:
+        return X
+    g = torch.Generator(device="cuda").manual_seed(int(seed))
+    sd = X[:, :-1].std(dim=0, keepdim=True)
+    parts = [X]
+    for eps in noise:
+        Y = X.clone()
+        Y[:, :-1] += float(eps) * sd * torch.randn(Y[:, :-1].shape, dtype=X.dtype, device=X.device, generator=g)
+        parts.append(Y)
+    return torch.cat(parts)
+
+
+def train_surrogate(rom, inst, w, X, hidden=(256, 256, 256), steps=3000, lr=1e-3, seed=0, lr_final=None, noise=()):
+    """Train the window's network on the GPU, full batch, on inputs X (with perturbed copies, see
+    perturbed_inputs) and the DEIM chain's targets at them.
 
     Weights start from a uniform Glorot draw of numpy's PCG64(seed), biases at zero; Adam with the
     learning rate decayed geometrically from lr to lr_final over the steps.  Returns (Mlp, targets,
-    [loss every 100 steps]).
+    [loss every 100 steps]); the targets are those of the inputs actually used.
     """
     import numpy as np
 
+    X = perturbed_inputs(X, noise, seed)
     T = lib.rom_surrogate_targets(rom, inst, w, X)
+    if noise:  # a perturbed state whose lifted mesh tangles has no targets (its row reads NaN): drop it
+        keep = torch.isfinite(T).all(dim=1)
+        X, T = X[keep].contiguous(), T[keep].contiguous()
     din, dout = int(X.shape[1]), int(T.shape[1])
     sizes = [din, *hidden, dout]
     g = np.random.Generator(np.random.PCG64(seed))

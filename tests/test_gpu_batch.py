@@ -125,3 +125,33 @@ def test_batched_launch_replays_from_a_graph(gpu_lib, batch, Gw):
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(G.state, eager), rep
+
+
+def test_a_failing_batch_instance_fails_in_the_oracle_too(gpu_lib):
+    """Instance 94 of the 256-instance Gresho batch (48 x 48, lambda = 8), which the batched launch reports as
+    failed: the oracle's ROM on the same bases tangles its mesh too (during accepted step 253, t = 0.065), the
+    GPU's run ends with a failure status, and up to step 100 the GPU follows the oracle step for step."""
+    from paper_2104_11404_amd import lib
+    from tests.test_gpu_rom import _gpu_rom
+
+    wl = W.gresho_batch(256)
+    prm = wl.params[94]
+    print(f"[case] failing gresho instance 94 {prm}", flush=True)
+    op = F.build_operator(oracle_problem(wl, amp=prm["amp"], p_bg=prm["p_bg"]))
+    tr = F.run_fom(op, wl.t_final)
+    y0 = initial_state(op.prob)
+    n = prm["n"]
+    rom = R.build_rom(op, [tr], [y0], windows_physical(wl.t_final, prm["n_windows"]), n_fixed=(n, n, n), lam=wl.lam)
+    with pytest.raises(F.TangledMesh):
+        R.run_rom(op, rom, y0, wl.t_final)
+    run = R.run_rom(op, rom, y0, wl.t_final, max_steps=100)
+    P, G = _gpu_rom(wl, [(rom, wl.t_final)], [y0])
+    G.step(max_steps=100)
+    st = G.states()[0]
+    assert st.status == 0 and st.n_steps == 100 and st.n_rejected == run.rejections
+    for a, b in zip(G.coords(0), run.yhat):
+        assert rel(a, b) < 1e-9
+    G.step()
+    st = G.states()[0]
+    assert st.status != 0 and st.t < wl.t_final
+

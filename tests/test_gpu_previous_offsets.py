@@ -1,4 +1,4 @@
-"""Previous-window offsets (Sec. 4.5, eq. previous_os) on the GPU (MI355X).
+"""Previous-window offsets (Sec. 4.6.2, eq. previous_os) on the GPU (MI355X).
 
 An instance created with offsets="previous" stops in rom_step at every window
 end; rom_switch_window_previous lifts its state with the closing window, makes

@@ -234,7 +234,9 @@ def test_instances_on_shared_bases_share_their_tables(gpu_lib, tg):
     per_instance = b[2] - b[1]
     assert 0 < per_instance < b[1]
     assert b[16] == b[1] + 15 * per_instance
-    assert distinct.device_bytes() == 16 * b[1]
+    # besides its instances' data a ROM holds one buffer: the 64 x 64 partial sums of rom_init_state
+    init_part = 64 * 64 * 8
+    assert distinct.device_bytes() == 16 * (b[1] - init_part) + init_part
     x0, v0, e0 = (torch.cat([_t(y0[f])] * 16) for f in range(3))
     one = roms[1]
     one.init_state(_t(y0[0]), _t(y0[1]), _t(y0[2]), wl.fixed_dt)

@@ -126,18 +126,22 @@ def tg2d_param(n: int = 32, t_final: float = 0.2, n_inst: int = 64, seed: int = 
                     fixed_dt=1e-3, n_windows=1, n_fixed=(20, 20, 20), params=tuple(dict(amp=float(a)) for a in amps))
 
 
-def tg3d_param(n: int = 24, t_final: float = 0.05, n_inst: int = 64, seed: int = SEED) -> Workload:
+def tg3d_param(n: int = 24, t_final: float = 0.05, n_inst: int = 64, seed: int = SEED, use_av: bool = False,
+               n_fixed: tuple = (10, 10, 10)) -> Workload:
     """Parametric 3D Taylor-Green on [0,1]^3: amplitude A ~ U[0.8, 1.2] per instance (the draws of
     tg2d_param), training at 0.8, 1.0, 1.2; alpha = 0.1, the paper's Taylor-Green CFL.
 
     Fixed dt = 1.5625e-4 to t = 0.05 (320 steps), about the step estimate of the initial state at
     24^3 (1.57e-4 with alpha = 0.1); the FOM stays untangled with up to 2.5e-4 at A = 0.8 and 1.2.
-    One window, dims 20/20/20, lambda = 2; bases shared by every instance with the nominal (A = 1)
-    initial state as offset.
+    One window, dims 10/10/10, lambda = 2; bases shared by every instance with the nominal (A = 1)
+    initial state as offset.  Artificial viscosity is off by default: with it on, the viscosity of
+    this smooth flow (traceless strain, so a negative smallest eigenvalue everywhere) leaves the
+    plain DEIM ROM at a few 1e-2 in v even at the training amplitudes, so no form reaches the 1e-3
+    error at which the surrogate and DEIM forms are compared; without it the DEIM ROM is at 1e-5.
     """
     amps = rng(seed).uniform(0.8, 1.2, n_inst)
-    return Workload("tg3d_param", TAYLOR_GREEN, 3, (n, n, n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), 5.0 / 3.0, True, 0.1,
-                    t_final, fixed_dt=1.5625e-4, n_windows=1, n_fixed=(20, 20, 20),
+    return Workload("tg3d_param", TAYLOR_GREEN, 3, (n, n, n), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), 5.0 / 3.0, use_av,
+                    0.1, t_final, fixed_dt=1.5625e-4, n_windows=1, n_fixed=tuple(n_fixed),
                     params=tuple(dict(amp=float(a)) for a in amps))
 
 
