@@ -274,20 +274,28 @@ def batched_gresho(lib, pipeline, n_inst: int = 256, reps: int = 3, lam=None):
             ms.append(a.elapsed_time(b))
         sts = rom.states()
         bad = [i for i, st in enumerate(sts) if st.status != 0 or st.done != 1]
-        steps = sum(st.n_steps for st in sts)
-        evals = sum(st.n_force_evals for st in sts)
         ok = [i for i in range(n_inst) if i not in bad]
+        # steps and force evaluations of the instances that reached t_final; those of the failed ones
+        # (their runs end early, often after a run of rejected steps) are reported on their own
+        steps = sum(sts[i].n_steps for i in ok)
+        evals = sum(sts[i].n_force_evals for i in ok)
         errs = np.zeros((len(ok), 3))
         for r, i in enumerate(ok):
             for f, (x, y) in enumerate(zip(rom.lift(i), finals[i])):
                 errs[r, f] = float(torch.linalg.norm(x - y) / torch.linalg.norm(y))
+        worst = ok[int(np.argmax(errs[:, 1]))] if ok else None
         t = sorted(ms)[len(ms) // 2] / 1e3
         out[name] = {"ms_per_launch": t * 1e3, "rom_steps_per_launch": int(steps), "rom_steps_per_s": steps / t,
                      "sampled_force_evals_per_s": evals / t, "autotune": tuned,
-                     "failed_instances": [dict(instance=i, status=sts[i].status, t=sts[i].t, **wl.params[i])
+                     "completed_instances": len(ok),
+                     "failed_instances": [dict(instance=i, status=sts[i].status, t=sts[i].t,
+                                               n_steps=sts[i].n_steps, n_rejected=sts[i].n_rejected, **wl.params[i])
                                           for i in bad],
                      "max_rel_error_vs_fom_completed": dict(zip("xve", errs.max(axis=0).tolist())),
-                     "median_rel_error_vs_fom_completed": dict(zip("xve", np.median(errs, axis=0).tolist()))}
+                     "median_rel_error_vs_fom_completed": dict(zip("xve", np.median(errs, axis=0).tolist())),
+                     "worst_completed_instance": None if worst is None else dict(
+                         instance=worst, rel_error_vs_fom=dict(zip("xve", errs[ok.index(worst)].tolist())),
+                         **wl.params[worst])}
         print(f"[bench] batched {name}: {t * 1e3:.2f} ms, {steps / t:.0f} ROM steps/s", file=sys.stderr, flush=True)
     out["f32_lift_graph"] = graph_replay(lib, torch, rom, y0, lib.LH_FP32_LIFT, reps)
     print(f"[bench] batched f32 graph: {out['f32_lift_graph']['ms_per_replay']:.2f} ms per replay", file=sys.stderr,
@@ -320,7 +328,7 @@ def graph_replay(lib, torch, rom, y0, flags, reps):
         torch.cuda.synchronize()
         ms.append(a.elapsed_time(b))
         same &= bool(torch.equal(rom.state, eager))
-    sts = rom.states()
+    sts = [st for st in rom.states() if st.status == 0 and st.done == 1]  # completed instances only
     t = float(np.median(ms)) / 1e3
     return {"ms_per_replay": t * 1e3, "rom_steps_per_s": sum(st.n_steps for st in sts) / t,
             "sampled_force_evals_per_s": sum(st.n_force_evals for st in sts) / t, "replays": reps,
@@ -351,12 +359,15 @@ def surrogate_setup(lib, pipeline, wl, n_train: int = 9, train_steps: int = 6000
     del trajs
     t_offline = time.perf_counter() - t0
     y0s, finals = [], []
-    for prm in wl.params:
+    for k, prm in enumerate(wl.params):
         Pi = lib.Problem.from_workload(wl, amp=prm["amp"])
         x, v, e = Pi.initial_state()
         y0s.append((x.clone(), v.clone(), e.clone()))
         Pi.fom_run(x, v, e, wl.t_final, fixed_dt=wl.fixed_dt, record=False)
         finals.append((x, v, e))
+        if (k + 1) % 16 == 0:
+            print(f"[bench] surrogate {wl.dim}D set-up: {k + 1} of {n_inst} reference FOM runs", file=sys.stderr,
+                  flush=True)
     y0 = [torch.cat([y[f] for y in y0s]) for f in range(3)]
     rom = lib.Rom(P, [inst] * n_inst)
     t1 = time.perf_counter()

@@ -245,7 +245,8 @@ __device__ __forceinline__ double lift_row(const TT* tp, const double* os, int n
 }
 
 // The same sum with the tile in global memory: eight loads in flight per
-// round trip instead of four.
+// round trip instead of four (3D kernels; in the 2D kernels the extra
+// registers would cost the second co-resident workgroup per compute unit).
 template <class TT>
 __device__ __forceinline__ double lift_row_g(const TT* tp, const double* os, int n, int rows, const double* y) {
     TT a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -258,7 +259,7 @@ __device__ __forceinline__ double lift_row_g(const TT* tp, const double* os, int
     return *os + (double)(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
 }
 
-// lift_row_g when GL (tiles in global memory), lift_row otherwise
+// lift_row_g when GL (3D tiles in global memory), lift_row otherwise
 template <bool GL, class TT>
 __device__ __forceinline__ double lift_at(const TT* tp, const double* os, int n, int rows, const double* y) {
     if constexpr (GL)
@@ -314,13 +315,13 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
             const int r = t % (2 * NKD + NT);
             const int slot = c0 + sl;
             if (r < NKD)
-                B.x[sl][r] = lift_at<GL>(L.tile[0] + (int64_t)slot * W.n[0] * NKD + r, L.os[0] + slot * NKD + r, W.n[0],
+                B.x[sl][r] = lift_at<GL && DIM == 3>(L.tile[0] + (int64_t)slot * W.n[0] * NKD + r, L.os[0] + slot * NKD + r, W.n[0],
                                       NKD, yx);
             else if (r < 2 * NKD)
-                B.v[sl][r - NKD] = lift_at<GL>(L.tile[1] + (int64_t)slot * W.n[1] * NKD + (r - NKD),
+                B.v[sl][r - NKD] = lift_at<GL && DIM == 3>(L.tile[1] + (int64_t)slot * W.n[1] * NKD + (r - NKD),
                                             L.os[1] + slot * NKD + (r - NKD), W.n[1], NKD, yv);
             else
-                B.e[sl][r - 2 * NKD] = lift_at<GL>(L.tile[2] + (int64_t)slot * W.n[2] * NT + (r - 2 * NKD),
+                B.e[sl][r - 2 * NKD] = lift_at<GL && DIM == 3>(L.tile[2] + (int64_t)slot * W.n[2] * NT + (r - 2 * NKD),
                                                 L.os[2] + slot * NT + (r - 2 * NKD), W.n[2], NT, ye);
         }
         __syncthreads();
@@ -377,7 +378,7 @@ __device__ void pass_b(const RomArgs& A, const WinDev& W, const WgView& V, const
         for (int t = tid; t < ne * NKD; t += BLK) {
             const int o = t / NKD, r = t % NKD;
             const int slot = V.own[c0 + o];
-            B.v[o][r] = lift_at<GL>(L.tile[1] + (int64_t)slot * W.n[1] * NKD + r, L.os[1] + slot * NKD + r, W.n[1], NKD,
+            B.v[o][r] = lift_at<GL && DIM == 3>(L.tile[1] + (int64_t)slot * W.n[1] * NKD + r, L.os[1] + slot * NKD + r, W.n[1], NKD,
                                  yvc);
         }
         __syncthreads();
@@ -920,91 +921,77 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             __syncthreads();
             evals += 4 * W.n_el;
         } else {
-        if (surr_step) {
-            // ---- surrogate step: the network's F^1 and F^tv = g + H v^_c in both stages
-            float* out;
-            mlp_eval(W.net, S.y[0], S.y[1], S.y[2], W.n, t, mscr, out);
-            mlp_f1(W.net, out, W.n[1], S.f1h);
-            for (int i = tid; i < W.n[1]; i += BLK) S.yh[1][i] = S.y[1][i] - 0.5 * h * S.f1h[i];
-            __syncthreads();
-            mlp_ftv(W.net, out, W.n[1], W.n[2], S.yh[1], S.y[1], S.ftvh, S.red);
-            for (int i = tid; i < W.n[2]; i += BLK) S.yh[2][i] = S.y[2][i] + 0.5 * h * S.ftvh[i];
-            x_update(W, L, S.y[0], 0.5 * h, S.yh[1], S.yh[0], S.red);
-            __syncthreads();
-            mlp_eval(W.net, S.yh[0], S.yh[1], S.yh[2], W.n, t + 0.5 * h, mscr, out);
-            mlp_f1(W.net, out, W.n[1], S.f1h);
-            for (int i = tid; i < W.n[1]; i += BLK) {
-                const double vn = S.y[1][i] - h * S.f1h[i];
-                S.yn[1][i] = vn;
-                S.vc[i] = 0.5 * (S.y[1][i] + vn);
+            // ---- RK2-average (eq. RK2-avg-rom-hr): stage k = 0 at y_n, k = 1 at y_{n+1/2} = S.yh.  A
+            // surrogate step takes the network's F^1 and F^tv = f + H (v^_c - v^) in both stages; an
+            // audit takes the DEIM chain and also evaluates the network at y_n.
+            for (int k = 0; k < 2; ++k) {
+                double(*const ys)[LH_NMAX] = k == 0 ? S.y : S.yh;
+                const double c = k == 0 ? 0.5 * h : h;
+                double* const vcon = k == 0 ? S.yh[1] : S.vc;  // contraction velocity of this stage
+                float* out = nullptr;
+                if (surr_step || (audit_now && k == 0))
+                    mlp_eval(W.net, ys[0], ys[1], ys[2], W.n, k == 0 ? t : t + 0.5 * h, mscr, out);
+                if (surr_step) {
+                    mlp_f1(W.net, out, W.n[1], S.f1h);
+                } else {
+                    pass_a<DIM, TT, !RES>(A, W, V, L, B, S, fe, ys[0], ys[1], ys[2], (phase & 1) ? part1 : part0,
+                                          &s_status);
+                    sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
+                    tau = fmin(tau, combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage));
+                    ++phase;
+                }
+                // v^_{n+1/2} (k = 0), or v^_{n+1} and the average velocity (k = 1)
+                for (int i = tid; i < W.n[1]; i += BLK) {
+                    const double vn = S.y[1][i] - c * S.f1h[i];
+                    if (k == 0) {
+                        S.yh[1][i] = vn;
+                    } else {
+                        S.yn[1][i] = vn;
+                        S.vc[i] = 0.5 * (S.y[1][i] + vn);
+                    }
+                }
+                __syncthreads();
+                if (surr_step) {
+                    mlp_ftv(W.net, out, W.n[1], W.n[2], vcon, ys[1], S.ftvh, S.red);
+                } else {
+                    pass_b<DIM, TT, !RES>(A, W, V, L, B, te, vcon, (phase & 1) ? part1 : part0, &s_status, S.red);
+                    sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
+                    combine((phase & 1) ? all1 : all0, A.G, W.n[2], S.ftvh, &s_status, S, stage);
+                    ++phase;
+                    if (audit_now && k == 0) {
+                        // the network against the DEIM chain at the first stage: F^1 at y_n, F^tv at v^_{1/2}
+                        mlp_f1(W.net, out, W.n[1], S.tmp);
+                        const double d1 = rel_disc(S.tmp, S.f1h, W.net.s_out, W.n[1], S.red);
+                        mlp_ftv(W.net, out, W.n[1], W.n[2], S.yh[1], S.y[1], S.tmp, S.red);
+                        const double d2 = rel_disc(S.tmp, S.ftvh, W.net.s_out + W.n[1], W.n[2], S.red);
+                        ++n_audits;
+                        if (!(fmax(d1, d2) <= W.tol) || isnan(d1) || isnan(d2)) {
+                            fallen = 1;
+                            ++n_fallbacks;
+                        }
+                    }
+                }
+                double* const edst = k == 0 ? S.yh[2] : S.yn[2];
+                for (int i = tid; i < W.n[2]; i += BLK) edst[i] = S.y[2][i] + c * S.ftvh[i];
+                x_update(W, L, S.y[0], c, vcon, k == 0 ? S.yh[0] : S.yn[0], S.red);
+                __syncthreads();
             }
-            __syncthreads();
-            mlp_ftv(W.net, out, W.n[1], W.n[2], S.vc, S.yh[1], S.ftvh, S.red);
-            for (int i = tid; i < W.n[2]; i += BLK) S.yn[2][i] = S.y[2][i] + h * S.ftvh[i];
-            x_update(W, L, S.y[0], h, S.vc, S.yn[0], S.red);
-            __syncthreads();
-            // a non-finite network state sends the rest of the window to DEIM: this step is attempted
-            // again, with the same size, on the DEIM chain
-            int bad = 0;
-            for (int f = 0; f < 3; ++f)
-                for (int i = tid; i < W.n[f]; i += BLK) bad |= !isfinite(S.yn[f][i]);
-            if (__syncthreads_or(bad)) {
-                fallen = 1;
-                ++n_fallbacks;
-                continue;
+            if (surr_step) {
+                // a non-finite network state sends the rest of the window to DEIM: this step is attempted
+                // again, with the same size, on the DEIM chain
+                int bad = 0;
+                for (int f = 0; f < 3; ++f)
+                    for (int i = tid; i < W.n[f]; i += BLK) bad |= !isfinite(S.yn[f][i]);
+                if (__syncthreads_or(bad)) {
+                    fallen = 1;
+                    ++n_fallbacks;
+                    continue;
+                }
+                tau = tau_est;
+            } else {
+                evals += 2 * W.n_el;
+                if (audit_now) tau_est = tau;
             }
-            tau = tau_est;
-        } else {
-        // ---- stage 1 at y_n
-        pass_a<DIM, TT, !RES>(A, W, V, L, B, S, fe, S.y[0], S.y[1], S.y[2], (phase & 1) ? part1 : part0, &s_status);
-        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
-        const double tau1 = combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage);
-        ++phase;
-        for (int i = tid; i < W.n[1]; i += BLK) S.yh[1][i] = S.y[1][i] - 0.5 * h * S.f1h[i];
-        __syncthreads();
-        pass_b<DIM, TT, !RES>(A, W, V, L, B, te, S.yh[1], (phase & 1) ? part1 : part0, &s_status, S.red);
-        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
-        combine((phase & 1) ? all1 : all0, A.G, W.n[2], S.ftvh, &s_status, S, stage);
-        ++phase;
-        if (audit_now) {
-            // the network against the DEIM chain at the first stage: F^1 at y_n, F^tv at v^_{1/2}
-            float* out;
-            mlp_eval(W.net, S.y[0], S.y[1], S.y[2], W.n, t, mscr, out);
-            mlp_f1(W.net, out, W.n[1], S.tmp);
-            const double d1 = rel_disc(S.tmp, S.f1h, W.net.s_out, W.n[1], S.red);
-            mlp_ftv(W.net, out, W.n[1], W.n[2], S.yh[1], S.y[1], S.tmp, S.red);
-            const double d2 = rel_disc(S.tmp, S.ftvh, W.net.s_out + W.n[1], W.n[2], S.red);
-            ++n_audits;
-            if (!(fmax(d1, d2) <= W.tol) || isnan(d1) || isnan(d2)) {
-                fallen = 1;
-                ++n_fallbacks;
-            }
-        }
-        for (int i = tid; i < W.n[2]; i += BLK) S.yh[2][i] = S.y[2][i] + 0.5 * h * S.ftvh[i];
-        x_update(W, L, S.y[0], 0.5 * h, S.yh[1], S.yh[0], S.red);
-        __syncthreads();
-        // ---- stage 2 at y_{n+1/2}
-        pass_a<DIM, TT, !RES>(A, W, V, L, B, S, fe, S.yh[0], S.yh[1], S.yh[2], (phase & 1) ? part1 : part0, &s_status);
-        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
-        const double tau2 = combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage);
-        ++phase;
-        for (int i = tid; i < W.n[1]; i += BLK) {
-            const double vn = S.y[1][i] - h * S.f1h[i];
-            S.yn[1][i] = vn;
-            S.vc[i] = 0.5 * (S.y[1][i] + vn);
-        }
-        __syncthreads();
-        pass_b<DIM, TT, !RES>(A, W, V, L, B, te, S.vc, (phase & 1) ? part1 : part0, &s_status, S.red);
-        sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
-        combine((phase & 1) ? all1 : all0, A.G, W.n[2], S.ftvh, &s_status, S, stage);
-        ++phase;
-        for (int i = tid; i < W.n[2]; i += BLK) S.yn[2][i] = S.y[2][i] + h * S.ftvh[i];
-        x_update(W, L, S.y[0], h, S.vc, S.yn[0], S.red);
-        __syncthreads();
-        evals += 2 * W.n_el;
-        tau = fmin(tau1, tau2);
-        if (audit_now) tau_est = tau;
-        }
         }
         if (s_status & (LH_FLAG_TANGLED | LH_FLAG_NONFINITE | LH_FLAG_TIMEOUT)) {
             done = true;
