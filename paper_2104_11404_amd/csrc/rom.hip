@@ -739,20 +739,36 @@ __device__ __noinline__ bool same_xcd(const InstDev& I, int G, int g, int target
 
 // Total energy 1/2 v~^T M_V v~ + 1^T M_E e~ of the state lifted from window W (conserved by the
 // semi-discrete RK2-average step, Sec. 2.2.1), in FP64 from the reduced coordinates yv, ye (LDS):
-// Ec + Emv.v^ + 1/2 v^T EMv v^ + Eme.e^.  Lane i < 64 of the first wave forms coordinate i's terms,
-// the lanes are summed by a fixed butterfly and lane 0's value is broadcast through red[0].
-__device__ __noinline__ double reduced_energy(const WinDev& W, const double* yv, const double* ye, double* red) {
+// Ec + Emv.v^ + 1/2 v^T EMv v^ + Eme.e^.  Thread (i, c) sums quarter c of row i of EMv v^ (two
+// accumulators, so that its loads overlap), the quarters are added in order, lane i < 64 of the
+// first wave forms coordinate i's terms, the lanes are summed by a fixed butterfly and lane 0's
+// value is broadcast through red[0] (red: BLK doubles).
+__device__ __forceinline__ double reduced_energy(const WinDev& W, const double* yv, const double* ye, double* red) {
+    static_assert(BLK == 256, "four quarters of 64 rows");
     const int tid = threadIdx.x;
+    const int nv = W.n[1];
+    const int i = tid & 63, c = tid >> 6;
+    double r = 0.0;
+    if (i < nv) {
+        const int cl = (nv + 3) / 4;
+        const int j1 = min(nv, (c + 1) * cl);
+        double r0 = 0.0, r1 = 0.0;
+        int j = c * cl;
+        for (; j + 1 < j1; j += 2) {
+            r0 += W.EMv[(int64_t)j * nv + i] * yv[j];
+            r1 += W.EMv[(int64_t)(j + 1) * nv + i] * yv[j + 1];
+        }
+        if (j < j1) r0 += W.EMv[(int64_t)j * nv + i] * yv[j];
+        r = r0 + r1;
+    }
+    red[tid] = r;
+    __syncthreads();
     if (tid < 64) {
         double acc = 0.0;
-        if (tid < W.n[1]) {
-            double r = 0.0;
-            for (int j = 0; j < W.n[1]; ++j) r += W.EMv[(int64_t)j * W.n[1] + tid] * yv[j];
-            acc = yv[tid] * (W.Emv[tid] + 0.5 * r);
-        }
+        if (tid < nv) acc = yv[tid] * (W.Emv[tid] + 0.5 * (((red[tid] + red[64 + tid]) + red[128 + tid]) + red[192 + tid]));
         if (tid < W.n[2]) acc += W.Eme[tid] * ye[tid];
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (tid == 0) red[0] = W.Ec[0] + acc;
+        if (tid == 0) red[0] = W.Ec[0] + acc;  // lanes 1..63 read no red[0]; the butterfly has joined them
     }
     __syncthreads();
     const double E = red[0];
@@ -2024,23 +2040,59 @@ struct LaunchShape {
     bool resident;
 };
 
-static LaunchShape launch_shape(const lh_rom* R, int G, bool f32, int mlp_floats) {
+// Workgroups per compute unit of the kernel that `flags` and `resident` select, with dyn bytes of
+// dynamic LDS.
+static int occupancy(const lh_rom* R, uint32_t flags, bool resident, size_t dyn, int* nb) {
+    const bool f32 = (flags & LH_FP32_LIFT) != 0;
+    if (flags & LH_RK4)
+        return R->p->dim == 2 ? (resident ? blocks_per_cu<2, double, true, true>(dyn, nb)
+                                          : blocks_per_cu<2, double, false, true>(dyn, nb))
+                              : (resident ? blocks_per_cu<3, double, true, true>(dyn, nb)
+                                          : blocks_per_cu<3, double, false, true>(dyn, nb));
+    if (R->p->dim == 2)
+        return f32 ? (resident ? blocks_per_cu<2, float, true>(dyn, nb) : blocks_per_cu<2, float, false>(dyn, nb))
+                   : (resident ? blocks_per_cu<2, double, true>(dyn, nb) : blocks_per_cu<2, double, false>(dyn, nb));
+    return f32 ? (resident ? blocks_per_cu<3, float, true>(dyn, nb) : blocks_per_cu<3, float, false>(dyn, nb))
+               : (resident ? blocks_per_cu<3, double, true>(dyn, nb) : blocks_per_cu<3, double, false>(dyn, nb));
+}
+
+// Dynamic LDS and tile placement of a launch with G workgroups per instance and the given flags.
+// The tiles stay in LDS when they fit there, unless the cooperative launch (G > 1) would then not
+// be co-resident while it would be with the tiles read from global memory (where instances on
+// shared bases find them in the L2).
+static int launch_shape(const lh_rom* R, int G, uint32_t flags, LaunchShape* out) {
+    const int mlp_floats = (flags & LH_SURROGATE) ? R->mlp_floats : 0;
     const size_t entries = 8 * (size_t)(R->nkin_max + R->nth_max + (int64_t)((G + 7) / 8) * PSTRIDE) +
                            4 * (size_t)mlp_floats;
     const int budget = lds_budget() - STATIC_LDS_RESERVE;
-    const int res = f32 ? R->res_max32 : R->res_max64;
-    const bool resident = (int64_t)entries + res <= budget;
-    return {entries + (resident ? (size_t)res : 0), resident};
+    const int res = (flags & LH_FP32_LIFT) ? R->res_max32 : R->res_max64;
+    bool resident = (int64_t)entries + res <= budget;
+    if (resident && G > 1) {
+        const int64_t need = (int64_t)R->n_inst * G;
+        int nb = 0;
+        int rc = occupancy(R, flags, true, entries + res, &nb);
+        if (rc) return rc;
+        if (need > (int64_t)nb * cu_count()) {
+            int nbg = 0;
+            rc = occupancy(R, flags, false, entries, &nbg);
+            if (rc) return rc;
+            if (need <= (int64_t)nbg * cu_count()) resident = false;
+        }
+    }
+    *out = {entries + (resident ? (size_t)res : 0), resident};
+    return LH_OK;
 }
 
 template <int DIM>
-static int dispatch(const lh_rom* R, const RomArgs& A, bool f32, hipStream_t s) {
-    const LaunchShape sh = launch_shape(R, A.G, f32, A.mlp_floats);
+static int dispatch(const lh_rom* R, const RomArgs& A, hipStream_t s) {
+    LaunchShape sh;
+    const int rc = launch_shape(R, A.G, A.flags, &sh);
+    if (rc) return rc;
     const size_t dyn = sh.dyn;
     if (A.flags & LH_RK4)
         return sh.resident ? launch_rom<DIM, double, true, true>(R, A, dyn, s)
                            : launch_rom<DIM, double, false, true>(R, A, dyn, s);
-    if (f32)
+    if (A.flags & LH_FP32_LIFT)
         return sh.resident ? launch_rom<DIM, float, true>(R, A, dyn, s) : launch_rom<DIM, float, false>(R, A, dyn, s);
     return sh.resident ? launch_rom<DIM, double, true>(R, A, dyn, s) : launch_rom<DIM, double, false>(R, A, dyn, s);
 }
@@ -2056,21 +2108,11 @@ static int blocks_per_cu(size_t dyn, int* nb) {
 // Whether n_inst x R->G workgroups can all be resident at once (needed for the
 // cooperative launch when G > 1) with the launch that `flags` selects.
 static int fits_coresident(const lh_rom* R, uint32_t flags, bool* ok) {
-    const bool f32 = (flags & LH_FP32_LIFT) != 0;
-    const int mlp = (flags & LH_SURROGATE) ? R->mlp_floats : 0;
-    const LaunchShape sh = launch_shape(R, R->G, f32, mlp);
-    int nb = 0, rc;
-    if (flags & LH_RK4)
-        rc = R->p->dim == 2 ? (sh.resident ? blocks_per_cu<2, double, true, true>(sh.dyn, &nb)
-                                           : blocks_per_cu<2, double, false, true>(sh.dyn, &nb))
-                            : (sh.resident ? blocks_per_cu<3, double, true, true>(sh.dyn, &nb)
-                                           : blocks_per_cu<3, double, false, true>(sh.dyn, &nb));
-    else if (R->p->dim == 2)
-        rc = f32 ? (sh.resident ? blocks_per_cu<2, float, true>(sh.dyn, &nb) : blocks_per_cu<2, float, false>(sh.dyn, &nb))
-                 : (sh.resident ? blocks_per_cu<2, double, true>(sh.dyn, &nb) : blocks_per_cu<2, double, false>(sh.dyn, &nb));
-    else
-        rc = f32 ? (sh.resident ? blocks_per_cu<3, float, true>(sh.dyn, &nb) : blocks_per_cu<3, float, false>(sh.dyn, &nb))
-                 : (sh.resident ? blocks_per_cu<3, double, true>(sh.dyn, &nb) : blocks_per_cu<3, double, false>(sh.dyn, &nb));
+    LaunchShape sh;
+    int rc = launch_shape(R, R->G, flags, &sh);
+    if (rc) return rc;
+    int nb = 0;
+    rc = occupancy(R, flags, sh.resident, sh.dyn, &nb);
     if (rc) return rc;
     *ok = R->G == 1 || (int64_t)R->n_inst * R->G <= (int64_t)nb * cu_count();
     return LH_OK;
@@ -2128,8 +2170,7 @@ int rom_step(const lh_rom* R, lh_rom_state* state, int32_t max_steps, uint32_t f
     A.nth_max = R->nth_max;
     A.mlp_floats = (flags & LH_SURROGATE) ? R->mlp_floats : 0;
     A.xcd_map = 0;  // set per launch in launch_rom
-    const bool f32 = (flags & LH_FP32_LIFT) != 0;
-    return p->dim == 2 ? dispatch<2>(R, A, f32, s) : dispatch<3>(R, A, f32, s);
+    return p->dim == 2 ? dispatch<2>(R, A, s) : dispatch<3>(R, A, s);
 }
 
 int rom_lift(const lh_rom* R, const lh_rom_state* state, int32_t inst, const lh_instance_desc* d, double* x,
