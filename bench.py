@@ -78,7 +78,7 @@ def measured_traffic(workgroups: int, name: str = "rom_step_kernel_sedov2d_64x64
 # gradient, stress and viscosity, both contractions), 2D Q2-Q1 with 16 points and 3D with 64
 ALG_FLOPS_PER_ELEM = {2: 5.0e3, 3: 1.26e5}
 # FP64 flops per element the kernel executes, from SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 x 64 lanes
-EXEC_FLOPS_PER_ELEM = {2: 1.19e4, 3: 3.81e5}
+EXEC_FLOPS_PER_ELEM = {2: 1.19e4, 3: 3.84e5}
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
@@ -476,7 +476,6 @@ def net_eval_flops(sizes):
 
 
 ERROR_BAR = 1e-3  # relative error against the FOM at which the forms are compared
-SURROGATE_MARGIN = 1.05
 
 
 HEADLINE_TRAFFIC = "rom_step_kernel_tg3d_24_batch64_traffic.md"
@@ -501,11 +500,10 @@ def headline(lib, pipeline, steps, warmup, train_steps, only_form=None, workgrou
         out[name] = time_form(lib, S, name, flags, net, k_audit, tol, warmup, steps, workgroups)
     ok = {n: max(out[n]["max_rel_error_vs_fom"].values()) <= ERROR_BAR and not out[n]["failed_instances"]
           for n, *_ in forms}
-    # a surrogate form is reported only when it is within the bar and at least SURROGATE_MARGIN faster
-    # than the plain DEIM form (a form that fell back everywhere runs as fast as DEIM, within noise)
+    # the fastest form within the bar (the plain DEIM form when none is)
     best = forms[0][0]
     for n, *_ in forms[1:]:
-        if ok[n] and (best not in out or out[n]["rom_steps_per_s"] > SURROGATE_MARGIN * out[best]["rom_steps_per_s"]):
+        if ok[n] and (best not in out or not ok[best] or out[n]["rom_steps_per_s"] > out[best]["rom_steps_per_s"]):
             best = n
     out["error_bar"] = ERROR_BAR
     out["within_error_bar"] = ok

@@ -30,13 +30,27 @@ struct ForceArgs {
     int32_t n_work;  // elements to evaluate
     int64_t n_elem;
     uint32_t ops;
-    double* f1_loc;  // (n_elem, NK, DIM) element-local F.1
+    double* f1_loc;  // element-local F.1 rows, laid out by f1_loc_index
     double* ftv;
     double* stress;  // (n_elem, NQ, DIM, DIM) kept / used stress
     double* tau;
     int32_t* status;
     const double* mat;  // per element (gamma, rho0 det J0), or null: fc.gamma and fc.detJ0
 };
+
+// Position of entry (a, c) of element K's local F.1 row.  2D: component and
+// local node major, element index fastest, so that a block's 16 elements write
+// one run per entry and a wavefront of the gather reads contiguous runs.  3D:
+// element major, so that each element's 81 entries are written as one run (a
+// block holds only 4 elements).
+template <int DIM>
+__device__ __forceinline__ int64_t f1_loc_index(int64_t K, int a, int c, int64_t n_elem) {
+    constexpr int NK = ElemDims<DIM>::NK;
+    if constexpr (DIM == 2)
+        return (int64_t)(c * NK + a) * n_elem + K;
+    else
+        return (K * NK + a) * DIM + c;
+}
 
 template <int DIM>
 struct FCfg {
@@ -54,7 +68,7 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
     __shared__ double s_v[EPB][NK * DIM];
     __shared__ double s_vc[EPB][NK * DIM];
     __shared__ double s_e[EPB][NT];
-    __shared__ double s_sig[EPB][NQ][DD];
+    __shared__ double s_sig[EPB][NQ * DD + 1];  // padded: element slots fall in different LDS banks
     __shared__ double s_s[EPB][NQ];
     __shared__ int s_elem[EPB];
     __shared__ double s_m[EPB][2];  // element material: gamma, rho0 det J0
@@ -126,7 +140,7 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
 #pragma unroll
         for (int c = 0; c < DIM; ++c)
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) s_sig[s][q][c * DIM + i] = sig[c][i];
+            for (int i = 0; i < DIM; ++i) s_sig[s][q * DD + c * DIM + i] = sig[c][i];
         if (want_ftv) {
             // sigma~ : (sum_a v_c,a (x) grad_xi N_a)
             int qx, qy, qz;
@@ -156,9 +170,11 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
     }
     __syncthreads();
     if (want_f1) {
+        // 2D: consecutive threads take consecutive element slots of one entry; 3D: consecutive
+        // entries of one element (the order f1_loc_index stores them in)
         for (int t = tid; t < EPB * NK * DIM; t += 256) {
-            const int ss = t / (NK * DIM);
-            const int r = t % (NK * DIM);
+            const int ss = DIM == 2 ? t % EPB : t / (NK * DIM);
+            const int r = DIM == 2 ? t / EPB : t % (NK * DIM);
             const int a = r / DIM;
             const int c = r % DIM;
             const int KK = s_elem[ss];
@@ -171,9 +187,9 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
                 q_coords<DIM>(qq, qx, qy, qz);
 #pragma unroll
                 for (int i = 0; i < DIM; ++i)
-                    acc += s_sig[ss][qq][c * DIM + i] * dshape(A.T, qx, qy, qz, ax, ay, az, i, DIM);
+                    acc += s_sig[ss][qq * DD + c * DIM + i] * dshape(A.T, qx, qy, qz, ax, ay, az, i, DIM);
             }
-            A.f1_loc[((int64_t)KK * NK + a) * DIM + c] = acc;
+            A.f1_loc[f1_loc_index<DIM>(KK, a, c, A.n_elem)] = acc;
         }
     }
     if (want_ftv) {
@@ -226,13 +242,14 @@ __global__ void gather_f1_kernel(const double* __restrict__ f1_loc, double* __re
             if (hi[k] > ne[k] - 1) hi[k] = ne[k] - 1;
         }
     }
+    const int64_t n_elem = (int64_t)nex * ney * (DIM == 3 ? nez : 1);
     double acc = 0.0;
     for (int ez = lo[2]; ez <= hi[2]; ++ez)
         for (int ey = lo[1]; ey <= hi[1]; ++ey)
             for (int ex = lo[0]; ex <= hi[0]; ++ex) {
                 const int64_t K = ex + (int64_t)nex * (ey + (int64_t)ney * ez);
                 const int a = (g[0] - 2 * ex) + 3 * (g[1] - 2 * ey) + (DIM == 3 ? 9 * (g[2] - 2 * ez) : 0);
-                acc += f1_loc[(K * NK + a) * DIM + c];
+                acc += f1_loc[f1_loc_index<DIM>(K, a, c, n_elem)];
             }
     F1[tid] = acc;
 }

@@ -245,10 +245,10 @@ __device__ inline void sym3_eig(double a[3][3], double lam[3]) {
 
 // Pulled-back stress sigma~ = w det J sigma J^{-T} and the step estimate at
 // one quadrature point, from the element-local node positions xe[a*DIM+c],
-// velocities ve[...] and energies ee[j], for an element whose adiabatic index
-// and mass constant rho0 det J0 (rho = rho0 det J0 / det J) are mat[0] and
-// mat[1] (element data staged in LDS next to xe, read where they are used).
-// Returns status flag bits.
+// velocities ve[...] (read only with the artificial viscosity on) and energies
+// ee[j], for an element whose adiabatic index and mass constant rho0 det J0
+// (rho = rho0 det J0 / det J) are mat[0] and mat[1] (element data staged in LDS
+// next to xe, read where they are used).  Returns status flag bits.
 template <int DIM>
 __device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, const double* mat, int q, const double* xe,
                                 const double* ve, const double* ee, double sig_t[DIM][DIM], double& tau) {
@@ -261,21 +261,38 @@ __device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, const dou
     for (int c = 0; c < DIM; ++c)
 #pragma unroll
         for (int i = 0; i < DIM; ++i) J[c][i] = G[c][i] = 0.0;
+    if (fc.use_av) {  // the velocity gradient G enters only the viscosity
 #pragma unroll 3
-    for (int a = 0; a < NK; ++a) {
-        int ax, ay, az;
-        a_coords<DIM>(a, ax, ay, az);
-        double g[DIM];
+        for (int a = 0; a < NK; ++a) {
+            int ax, ay, az;
+            a_coords<DIM>(a, ax, ay, az);
+            double g[DIM];
 #pragma unroll
-        for (int i = 0; i < DIM; ++i) g[i] = dshape(T, qx, qy, qz, ax, ay, az, i, DIM);
+            for (int i = 0; i < DIM; ++i) g[i] = dshape(T, qx, qy, qz, ax, ay, az, i, DIM);
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            const double xa = xe[a * DIM + c];
-            const double va = ve[a * DIM + c];
+            for (int c = 0; c < DIM; ++c) {
+                const double xa = xe[a * DIM + c];
+                const double va = ve[a * DIM + c];
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) {
-                J[c][i] += xa * g[i];
-                G[c][i] += va * g[i];
+                for (int i = 0; i < DIM; ++i) {
+                    J[c][i] += xa * g[i];
+                    G[c][i] += va * g[i];
+                }
+            }
+        }
+    } else {
+#pragma unroll 3
+        for (int a = 0; a < NK; ++a) {
+            int ax, ay, az;
+            a_coords<DIM>(a, ax, ay, az);
+            double g[DIM];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) g[i] = dshape(T, qx, qy, qz, ax, ay, az, i, DIM);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const double xa = xe[a * DIM + c];
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) J[c][i] += xa * g[i];
             }
         }
     }

@@ -314,6 +314,7 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
             const int sl = t / (2 * NKD + NT);
             const int r = t % (2 * NKD + NT);
             const int slot = c0 + sl;
+            if (r >= NKD && r < 2 * NKD && !A.fc.use_av) continue;  // the stress reads v only for the viscosity
             if (r < NKD)
                 B.x[sl][r] = lift_at<GL && DIM == 3>(L.tile[0] + (int64_t)slot * W.n[0] * NKD + r, L.os[0] + slot * NKD + r, W.n[0],
                                       NKD, yx);
