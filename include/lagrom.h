@@ -130,7 +130,11 @@ size_t lh_fom_force_workspace_size(const lh_problem* p);
  * dofs of evaluated elements are written, others untouched.  tau_min (dev, 1
  * double): overwritten with the minimum (+inf if no element is limiting).
  * With LH_USE_STRESS only LH_FTV may be requested and x, v, e are ignored.
- * A tangled element (det J <= 0) sets LH_FLAG_TANGLED in the status word. */
+ * A tangled element (det J <= 0) sets LH_FLAG_TANGLED in the status word.
+ * Cost: the stress and contractions scale with the listed elements, but F1
+ * is assembled over the whole mesh (element-local rows zeroed, then a
+ * gather over every node), so a short list still pays a full-mesh assembly;
+ * the hyper-reduced ROM evaluates its sampled elements inside rom_step. */
 int fom_force(const lh_problem* p, const double* x, const double* v, const double* e, const double* v_c,
               const int32_t* elems, int32_t n_elems, uint32_t ops, double* F1, double* Ftv, double* tau_min,
               void* work, size_t work_bytes, hipStream_t stream);
@@ -311,7 +315,8 @@ typedef struct {
     int32_t done;
     double yhat[3][LH_NMAX]; /* x^, v^, e^ of the current window                   */
     /* surrogate bookkeeping (rom_attach_surrogate) */
-    double tau_est;          /* step estimate of the last audit                       */
+    double tau_est;          /* step estimate of the last audit (infinity with        */
+                             /* LH_FIXED_DT / LH_REPLAY_DT: no estimate is formed)    */
     int32_t since;           /* accepted steps since entering the window              */
     int32_t fallen;          /* the current window has fallen back to DEIM            */
     int32_t n_audits;

@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
 #pragma unroll
                 for (int i = 0; i < DIM; ++i) sig[c][i] = src[c * DIM + i];
         } else {
-            const int fl = qp_stress<DIM>(A.T, A.fc, s_m[s], q, s_x[s], s_v[s], s_e[s], sig, tau);
+            const int fl = qp_stress<DIM>(A.T, A.fc, s_m[s], q, s_x[s], s_v[s], s_e[s], sig, tau, want_tau);
             if (fl) atomicOr(A.status, fl);
             if (A.ops & LH_KEEP_STRESS) {
                 double* dst = A.stress + ((int64_t)K * NQ + q) * DD;

@@ -248,10 +248,12 @@ __device__ inline void sym3_eig(double a[3][3], double lam[3]) {
 // velocities ve[...] (read only with the artificial viscosity on) and energies
 // ee[j], for an element whose adiabatic index and mass constant rho0 det J0
 // (rho = rho0 det J0 / det J) are mat[0] and mat[1] (element data staged in LDS
-// next to xe, read where they are used).  Returns status flag bits.
+// next to xe, read where they are used).  Without need_tau the step estimate is
+// not formed (tau = infinity).  Returns status flag bits.
 template <int DIM>
 __device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, const double* mat, int q, const double* xe,
-                                const double* ve, const double* ee, double sig_t[DIM][DIM], double& tau) {
+                                const double* ve, const double* ee, double sig_t[DIM][DIM], double& tau,
+                                bool need_tau = true) {
     constexpr int NK = ElemDims<DIM>::NK;
     constexpr int NT = ElemDims<DIM>::NT;
     int qx, qy, qz;
@@ -332,9 +334,10 @@ __device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, const dou
     const double gm = mat[0];
     const double p = (gm - 1.0) * rho * eq;
     const double cs = sqrt(fmax(gm * (gm - 1.0) * eq, 0.0));
-    // smallest singular value of J: |det J| / (product of the larger ones)
-    double hmin;
-    {
+    // smallest singular value of J: |det J| / (product of the larger ones); it enters only the
+    // step estimate and the viscosity
+    double hmin = 1.0;
+    if (need_tau || fc.use_av) {
         double M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
         for (int i = 0; i < DIM; ++i)
@@ -419,6 +422,7 @@ __device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, const dou
     const double denom = cs / hmin + ALPHA_MU * mu / (rho * hmin * hmin);
     tau = denom > 0.0 ? fc.cfl / denom : INFINITY;
     if (isnan(tau)) flags |= LH_FLAG_NONFINITE;
+    if (!need_tau) tau = INFINITY;
     return flags;
 }
 

@@ -112,6 +112,7 @@ struct RomArgs {
     int nkin_max, nth_max;  // sizes of the entry-value arrays in LDS
     int mlp_floats;         // LDS scratch of the surrogate (0: no surrogate this launch)
     int xcd_map;            // blocks placed so that an instance's workgroups share one XCD (see rom_block)
+    int sig_lds;            // tiles in global memory, kept stress at the start of the dynamic LDS
 };
 
 template <int DIM>
@@ -296,13 +297,15 @@ __device__ void project_share(const TT* a, bool res, const int* ent, int ne, int
 }
 
 // Pass A for one workgroup: kept stress, entries of F.1 at the sampled rows,
-// the share of F^1 and the minimum step estimate (written to `share`).
+// the share of F^1 and the minimum step estimate (written to `share`; not
+// formed, infinity, when the launch's step sizes are fixed or replayed).
 template <int DIM, class TT, bool GL = false>
 __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const Local<TT>& L, NodeBuf<DIM>& B,
                        Shared& S, double* fe, const double* yx, const double* yv, const double* ye, double* share,
                        int* status) {
     constexpr int EC = Cfg<DIM>::EC, NKD = Cfg<DIM>::NKD, NT = Cfg<DIM>::NT, NQ = Cfg<DIM>::NQ, DD = Cfg<DIM>::DD;
     const int tid = threadIdx.x;
+    const bool need_tau = (A.flags & (LH_FIXED_DT | LH_REPLAY_DT)) == 0;  // the step control alone reads tau
     double tau = INFINITY;
     for (int c0 = 0; c0 < V.ns; c0 += EC) {
         const int ne = min(EC, V.ns - c0);
@@ -331,7 +334,7 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
             if (sl < ne) {
                 double sig[DIM][DIM];
                 double tq;
-                const int fl = qp_stress<DIM>(A.T, A.fc, B.m[sl], q, B.x[sl], B.v[sl], B.e[sl], sig, tq);
+                const int fl = qp_stress<DIM>(A.T, A.fc, B.m[sl], q, B.x[sl], B.v[sl], B.e[sl], sig, tq, need_tau);
                 if (fl) atomicOr(status, fl);
                 tau = fmin(tau, tq);
                 double* dst = L.sig + ((int64_t)(c0 + sl) * NQ + q) * DD;
@@ -478,7 +481,8 @@ __device__ double combine(const double* part, int G, int n, double* out, int* st
 
 // Make the workgroup's window data resident in LDS (or point at global memory).
 template <int DIM, class TT>
-__device__ void load_local(const WinDev& W, const WgView& V, const InstDev& I, bool res, char* dyn, Local<TT>& L) {
+__device__ void load_local(const WinDev& W, const WgView& V, const InstDev& I, bool res, bool sig_lds, char* dyn,
+                           Local<TT>& L) {
     constexpr int NKD = Cfg<DIM>::NKD, NT = Cfg<DIM>::NT, NQ = Cfg<DIM>::NQ, DD = Cfg<DIM>::DD;
     const int rows[3] = {NKD, NKD, NT};
     const TT* gt[3];
@@ -504,7 +508,7 @@ __device__ void load_local(const WinDev& W, const WgView& V, const InstDev& I, b
         L.a2 = ga2;
         L.Bxv = W.Bxv;
         L.bx = W.bx;
-        L.sig = I.sig + (int64_t)V.s0 * NQ * DD;
+        L.sig = sig_lds ? reinterpret_cast<double*>(dyn) : I.sig + (int64_t)V.s0 * NQ * DD;
         return;
     }
     // layout: sig (double) | os x, v, e (double) | tiles x, v, e (TT) | a1 | a2 (TT)
@@ -851,7 +855,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
         ++phase;
     }
     Local<TT> L;
-    load_local<DIM, TT>(I.win[w], I.win[w].views[g], I, RES, dyn, L);
+    load_local<DIM, TT>(I.win[w], I.win[w].views[g], I, RES, A.sig_lds != 0, dyn, L);
     double* const part0 = I.part + (int64_t)g * PSTRIDE;                     // my share, even phases
     double* const part1 = I.part + ((int64_t)A.G + g) * PSTRIDE;             // my share, odd phases
     const double* const all0 = I.part;                                       // every share, even phases
@@ -1049,7 +1053,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             moved = true;
         }
         if (moved) {
-            load_local<DIM, TT>(I.win[w], I.win[w].views[g], I, RES, dyn, L);
+            load_local<DIM, TT>(I.win[w], I.win[w].views[g], I, RES, A.sig_lds != 0, dyn, L);
             since = 0;
             fallen = 0;
             tau_est = INFINITY;
@@ -1349,6 +1353,7 @@ struct lh_rom {
     int G;
     int nkin_max, nth_max;
     int res_max64, res_max32;
+    int sig_max;         // bytes of the largest workgroup's kept stress (NQ x DD doubles per element)
     int mlp_floats = 0;  // LDS scratch of the largest attached surrogate
     std::vector<void*> allocs;
     std::vector<void*> view_allocs;  // workgroup views: rebuilt when G changes
@@ -1763,6 +1768,8 @@ static int build_views(lh_rom* R, int i, int G) {
             R->nth_max = std::max(R->nth_max, V.nth);
             R->res_max64 = std::max(R->res_max64, V.res_bytes64);
             R->res_max32 = std::max(R->res_max32, V.res_bytes32);
+            const int nq = dim == 3 ? 64 : 16;
+            R->sig_max = std::max(R->sig_max, 8 * V.ns * nq * dim * dim);
         }
         const WgView* dv;
         int rc = upload(R, views, &dv, &R->view_allocs);
@@ -1816,7 +1823,7 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
     R->p = p;
     R->n_inst = n_inst;
     R->G = 1;
-    R->nkin_max = R->nth_max = R->res_max64 = R->res_max32 = 0;
+    R->nkin_max = R->nth_max = R->res_max64 = R->res_max32 = R->sig_max = 0;
     R->h_inst.resize(n_inst);
     R->h_win.resize(n_inst);
     R->h_struct.resize(n_inst);
@@ -2038,7 +2045,8 @@ static int launch_rom(const lh_rom* R, const RomArgs& A, size_t dyn, hipStream_t
 // workgroup's window tiles fit in it (otherwise they are read from global memory).
 struct LaunchShape {
     size_t dyn;
-    bool resident;
+    bool resident;  // every window table of a workgroup in LDS
+    bool sig_lds;   // tiles in global memory, the kept stress in LDS
 };
 
 // Workgroups per compute unit of the kernel that `flags` and `resident` select, with dyn bytes of
@@ -2057,38 +2065,51 @@ static int occupancy(const lh_rom* R, uint32_t flags, bool resident, size_t dyn,
                : (resident ? blocks_per_cu<3, double, true>(dyn, nb) : blocks_per_cu<3, double, false>(dyn, nb));
 }
 
-// Dynamic LDS and tile placement of a launch with G workgroups per instance and the given flags.
-// The tiles stay in LDS when they fit there, unless the cooperative launch (G > 1) would then not
-// be co-resident while it would be with the tiles read from global memory (where instances on
-// shared bases find them in the L2).
+// Dynamic LDS and data placement of a launch with G workgroups per instance and the given flags, in
+// order of preference: every window table in LDS; the tiles in global memory (where instances on
+// shared bases find them in the L2) and the kept stress in LDS; both in global memory.  A placement
+// is taken when it fits the LDS budget and, for a cooperative launch (G > 1), keeps all the
+// instances' workgroups co-resident.
 static int launch_shape(const lh_rom* R, int G, uint32_t flags, LaunchShape* out) {
     const int mlp_floats = (flags & LH_SURROGATE) ? R->mlp_floats : 0;
     const size_t entries = 8 * (size_t)(R->nkin_max + R->nth_max + (int64_t)((G + 7) / 8) * PSTRIDE) +
                            4 * (size_t)mlp_floats;
-    const int budget = lds_budget() - STATIC_LDS_RESERVE;
+    const int64_t budget = lds_budget() - STATIC_LDS_RESERVE;
+    const int64_t need = (int64_t)R->n_inst * G;
     const int res = (flags & LH_FP32_LIFT) ? R->res_max32 : R->res_max64;
-    bool resident = (int64_t)entries + res <= budget;
-    if (resident && G > 1) {
-        const int64_t need = (int64_t)R->n_inst * G;
+    auto fits = [&](bool resident, size_t dyn, bool* ok) -> int {
+        *ok = (int64_t)dyn <= budget;
+        if (!*ok || G == 1) return LH_OK;
         int nb = 0;
-        int rc = occupancy(R, flags, true, entries + res, &nb);
+        const int rc = occupancy(R, flags, resident, dyn, &nb);
         if (rc) return rc;
-        if (need > (int64_t)nb * cu_count()) {
-            int nbg = 0;
-            rc = occupancy(R, flags, false, entries, &nbg);
-            if (rc) return rc;
-            if (need <= (int64_t)nbg * cu_count()) resident = false;
-        }
+        *ok = need <= (int64_t)nb * cu_count();
+        return LH_OK;
+    };
+    bool ok = false;
+    int rc = fits(true, entries + res, &ok);
+    if (rc) return rc;
+    if (ok) {
+        *out = {entries + (size_t)res, true, false};
+        return LH_OK;
     }
-    *out = {entries + (resident ? (size_t)res : 0), resident};
+    rc = fits(false, entries + R->sig_max, &ok);
+    if (rc) return rc;
+    if (ok) {
+        *out = {entries + (size_t)R->sig_max, false, true};
+        return LH_OK;
+    }
+    *out = {entries, false, false};  // both in global memory (fits_coresident tells whether it is co-resident)
     return LH_OK;
 }
 
 template <int DIM>
-static int dispatch(const lh_rom* R, const RomArgs& A, hipStream_t s) {
+static int dispatch(const lh_rom* R, const RomArgs& A0, hipStream_t s) {
     LaunchShape sh;
-    const int rc = launch_shape(R, A.G, A.flags, &sh);
+    const int rc = launch_shape(R, A0.G, A0.flags, &sh);
     if (rc) return rc;
+    RomArgs A = A0;
+    A.sig_lds = sh.sig_lds ? 1 : 0;
     const size_t dyn = sh.dyn;
     if (A.flags & LH_RK4)
         return sh.resident ? launch_rom<DIM, double, true, true>(R, A, dyn, s)
@@ -2126,7 +2147,7 @@ static int repartition(lh_rom* R, int G, hipStream_t s) {
     for (void* q : R->view_allocs) (void)hipFree(q);
     R->view_allocs.clear();
     R->view_bytes = 0;
-    R->nkin_max = R->nth_max = R->res_max64 = R->res_max32 = 0;
+    R->nkin_max = R->nth_max = R->res_max64 = R->res_max32 = R->sig_max = 0;
     for (int i = 0; i < R->n_inst; ++i) {
         const int rc = build_views(R, i, G);
         if (rc) return rc;
@@ -2171,6 +2192,7 @@ int rom_step(const lh_rom* R, lh_rom_state* state, int32_t max_steps, uint32_t f
     A.nth_max = R->nth_max;
     A.mlp_floats = (flags & LH_SURROGATE) ? R->mlp_floats : 0;
     A.xcd_map = 0;  // set per launch in launch_rom
+    A.sig_lds = 0;  // set per launch in dispatch
     return p->dim == 2 ? dispatch<2>(R, A, s) : dispatch<3>(R, A, s);
 }
 
