@@ -251,11 +251,15 @@ __device__ inline void sym3_eig(double a[3][3], double lam[3]) {
 // next to xe, read where they are used).  Without need_tau the step estimate is
 // not formed (tau = infinity).  Returns status flag bits.
 template <int DIM>
+__device__ inline int qp_stress_jg(const RefTab& T, const ForceConst& fc, const double* mat, int q,
+                                   const double J[DIM][DIM], const double G[DIM][DIM], const double* ee,
+                                   double sig_t[DIM][DIM], double& tau, bool need_tau);
+
+template <int DIM>
 __device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, const double* mat, int q, const double* xe,
                                 const double* ve, const double* ee, double sig_t[DIM][DIM], double& tau,
                                 bool need_tau = true) {
     constexpr int NK = ElemDims<DIM>::NK;
-    constexpr int NT = ElemDims<DIM>::NT;
     int qx, qy, qz;
     q_coords<DIM>(q, qx, qy, qz);
     double J[DIM][DIM], G[DIM][DIM];
@@ -298,6 +302,18 @@ __device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, const dou
             }
         }
     }
+    return qp_stress_jg<DIM>(T, fc, mat, q, J, G, ee, sig_t, tau, need_tau);
+}
+
+// The stress and step estimate of qp_stress from the reference gradients J = dx/dxi and (read only
+// with the viscosity) G = dv/dxi at the quadrature point.
+template <int DIM>
+__device__ inline int qp_stress_jg(const RefTab& T, const ForceConst& fc, const double* mat, int q,
+                                   const double J[DIM][DIM], const double G[DIM][DIM], const double* ee,
+                                   double sig_t[DIM][DIM], double& tau, bool need_tau) {
+    constexpr int NT = ElemDims<DIM>::NT;
+    int qx, qy, qz;
+    q_coords<DIM>(q, qx, qy, qz);
     int flags = 0;
     double det, Jinv[DIM][DIM];
     if constexpr (DIM == 2) {
@@ -424,6 +440,56 @@ __device__ inline int qp_stress(const RefTab& T, const ForceConst& fc, const dou
     if (isnan(tau)) flags |= LH_FLAG_NONFINITE;
     if (!need_tau) tau = INFINITY;
     return flags;
+}
+
+// Reference gradients d u_c / d xi_i of a Q2 field at the 64 quadrature points of up to ne 3D
+// elements, by sum factorisation (the tensor-product form of the Q2 gradient): u[s][a * 3 + c] holds
+// element slot s's nodal values, a = ax + 3 ay + 9 az.  sf_grad3 contracts z then y, each over the
+// 3 nodes of a line, into sf2 (two workgroup barriers; sf1: 216 ne doubles, sf2: 432 ne doubles);
+// sf_grad3_at then contracts x at one point: 3 FMA per entry instead of 27 nodes per entry.
+template <int BLOCK>
+__device__ inline void sf_grad3(const double (*u)[81], int ne, double* sf1, double* sf2, const RefTab& T) {
+    // sf1[(((s * 3 + c) * 2 + k) * 9 + axy) * 4 + qz] = sum_az u[s][(axy + 9 az) * 3 + c] (k ? D : B)[qz][az]
+    for (int t = threadIdx.x; t < ne * 216; t += BLOCK) {
+        const int qz = t & 3;
+        int r = t >> 2;
+        const int axy = r % 9;
+        r /= 9;
+        const int k = r & 1;
+        r >>= 1;
+        const int c = r % 3, s = r / 3;
+        const double* w = k ? T.D[qz] : T.B[qz];
+        const double* us = u[s] + axy * 3 + c;
+        sf1[t] = (us[0] * w[0] + us[27] * w[1]) + us[54] * w[2];
+    }
+    __syncthreads();
+    // sf2[(((((s * 3 + c) * 3 + i) * 3 + ax) * 4 + qy) * 4 + qz] for direction i: y contraction of the
+    // z-values (i = 0: B in y; i = 1: D in y) or of the z-derivatives (i = 2: B in y)
+    for (int t = threadIdx.x; t < ne * 432; t += BLOCK) {
+        const int qz = t & 3, qy = (t >> 2) & 3;
+        int r = t >> 4;
+        const int ax = r % 3;
+        r /= 3;
+        const int i = r % 3;
+        r /= 3;
+        const int c = r % 3, s = r / 3;
+        const double* w = i == 1 ? T.D[qy] : T.B[qy];
+        const double* p = sf1 + ((((s * 3 + c) * 2 + (i == 2 ? 1 : 0)) * 9 + ax) * 4 + qz);
+        sf2[t] = (p[0] * w[0] + p[12] * w[1]) + p[24] * w[2];
+    }
+    __syncthreads();
+}
+
+__device__ inline void sf_grad3_at(const double* sf2, const RefTab& T, int s, int q, double g[3][3]) {
+    const int qx = q & 3, qy = (q >> 2) & 3, qz = q >> 4;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double* w = i == 0 ? T.D[qx] : T.B[qx];
+            const double* p = sf2 + ((((s * 3 + c) * 3 + i) * 3) * 4 + qy) * 4 + qz;
+            g[c][i] = (p[0] * w[0] + p[16] * w[1]) + p[32] * w[2];
+        }
 }
 
 // Global node id of local node a of element (ex, ey, ez).

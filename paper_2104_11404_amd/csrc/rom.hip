@@ -125,6 +125,11 @@ struct Cfg {
     static constexpr int EC = BLK / NQ;  // elements per chunk (one thread per quadrature point)
 };
 
+// LDS staging of the sum-factorised 3D gradients for a chunk of Cfg<3>::EC elements: the z
+// contractions (216 doubles per element), then the y contractions (432 per element) at SF1.
+constexpr int SF1 = 216 * (BLK / 64);
+constexpr int SF_DOUBLES = SF1 + 432 * (BLK / 64);
+
 // Pointers to one workgroup's data in one window, in LDS or in global memory.
 template <class TT>
 struct Local {
@@ -302,7 +307,7 @@ __device__ void project_share(const TT* a, bool res, const int* ent, int ne, int
 template <int DIM, class TT, bool GL = false>
 __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const Local<TT>& L, NodeBuf<DIM>& B,
                        Shared& S, double* fe, const double* yx, const double* yv, const double* ye, double* share,
-                       int* status) {
+                       int* status, double* sf) {
     constexpr int EC = Cfg<DIM>::EC, NKD = Cfg<DIM>::NKD, NT = Cfg<DIM>::NT, NQ = Cfg<DIM>::NQ, DD = Cfg<DIM>::DD;
     const int tid = threadIdx.x;
     const bool need_tau = (A.flags & (LH_FIXED_DT | LH_REPLAY_DT)) == 0;  // the step control alone reads tau
@@ -331,10 +336,24 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
         __syncthreads();
         {
             const int sl = tid / NQ, q = tid % NQ;
+            double J3[3][3], G3[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            if constexpr (DIM == 3) {  // gradients by sum factorisation (every thread takes part)
+                sf_grad3<BLK>(B.x, ne, sf, sf + SF1, A.T);
+                if (sl < ne) sf_grad3_at(sf + SF1, A.T, sl, q, J3);
+                if (A.fc.use_av) {
+                    __syncthreads();  // every J read before the staging is overwritten
+                    sf_grad3<BLK>(B.v, ne, sf, sf + SF1, A.T);
+                    if (sl < ne) sf_grad3_at(sf + SF1, A.T, sl, q, G3);
+                }
+            }
             if (sl < ne) {
                 double sig[DIM][DIM];
                 double tq;
-                const int fl = qp_stress<DIM>(A.T, A.fc, B.m[sl], q, B.x[sl], B.v[sl], B.e[sl], sig, tq, need_tau);
+                int fl;
+                if constexpr (DIM == 3)
+                    fl = qp_stress_jg<3>(A.T, A.fc, B.m[sl], q, J3, G3, B.e[sl], sig, tq, need_tau);
+                else
+                    fl = qp_stress<DIM>(A.T, A.fc, B.m[sl], q, B.x[sl], B.v[sl], B.e[sl], sig, tq, need_tau);
                 if (fl) atomicOr(status, fl);
                 tau = fmin(tau, tq);
                 double* dst = L.sig + ((int64_t)(c0 + sl) * NQ + q) * DD;
@@ -374,7 +393,7 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
 // Pass B for one workgroup: F^T.v_c at its sampled energy dofs and its share of F^tv.
 template <int DIM, class TT, bool GL = false>
 __device__ void pass_b(const RomArgs& A, const WinDev& W, const WgView& V, const Local<TT>& L, NodeBuf<DIM>& B,
-                       double* te, const double* yvc, double* share, const int* status, double* red) {
+                       double* te, const double* yvc, double* share, const int* status, double* red, double* sf) {
     constexpr int EC = Cfg<DIM>::EC, NKD = Cfg<DIM>::NKD, NK = Cfg<DIM>::NK, NQ = Cfg<DIM>::NQ, DD = Cfg<DIM>::DD;
     const int tid = threadIdx.x;
     for (int c0 = 0; c0 < V.nown; c0 += EC) {
@@ -386,7 +405,21 @@ __device__ void pass_b(const RomArgs& A, const WinDev& W, const WgView& V, const
                                  yvc);
         }
         __syncthreads();
-        {
+        if constexpr (DIM == 3) {  // sigma~ : grad_xi v_c with the gradient by sum factorisation
+            sf_grad3<BLK>(B.v, ne, sf, sf + SF1, A.T);
+            const int o = tid / NQ, q = tid % NQ;
+            if (o < ne) {
+                const double* sg = L.sig + ((int64_t)V.own[c0 + o] * NQ + q) * DD;
+                double gv[3][3];
+                sf_grad3_at(sf + SF1, A.T, o, q, gv);
+                double acc = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) acc += sg[c * 3 + i] * gv[c][i];
+                B.s[o][q] = acc;
+            }
+        } else {
             const int o = tid / NQ, q = tid % NQ;
             if (o < ne) {
                 const double* sg = L.sig + ((int64_t)V.own[c0 + o] * NQ + q) * DD;
@@ -802,6 +835,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
     __shared__ NodeBuf<DIM> B;
     __shared__ Shared S;
     __shared__ lh_rom_state st;
+    __shared__ double sfb[DIM == 3 ? SF_DOUBLES : 1];  // sum-factorisation staging (3D)
     __shared__ int s_status, s_base, s_local;
     const int tid = threadIdx.x;
     int ii, g;
@@ -864,7 +898,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
     if (adaptive && !(dt > 0.0)) {
         const WinDev& W = I.win[w];
         pass_a<DIM, TT, !RES>(A, W, W.views[g], L, B, S, fe, S.y[0], S.y[1], S.y[2], (phase & 1) ? part1 : part0,
-                        &s_status);
+                        &s_status, sfb);
         sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
         const double tau0 = combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage);
         ++phase;
@@ -908,11 +942,11 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
             tau = INFINITY;
             for (int k = 0; k < 4; ++k) {
                 pass_a<DIM, TT, !RES>(A, W, V, L, B, S, fe, S.yh[0], S.yh[1], S.yh[2], (phase & 1) ? part1 : part0,
-                                      &s_status);
+                                      &s_status, sfb);
                 sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
                 tau = fmin(tau, combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage));
                 ++phase;
-                pass_b<DIM, TT, !RES>(A, W, V, L, B, te, S.yh[1], (phase & 1) ? part1 : part0, &s_status, S.red);
+                pass_b<DIM, TT, !RES>(A, W, V, L, B, te, S.yh[1], (phase & 1) ? part1 : part0, &s_status, S.red, sfb);
                 sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
                 combine((phase & 1) ? all1 : all0, A.G, W.n[2], S.ftvh, &s_status, S, stage);
                 ++phase;
@@ -956,7 +990,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
                     mlp_f1(W.net, out, W.n[1], S.f1h);
                 } else {
                     pass_a<DIM, TT, !RES>(A, W, V, L, B, S, fe, ys[0], ys[1], ys[2], (phase & 1) ? part1 : part0,
-                                          &s_status);
+                                          &s_status, sfb);
                     sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
                     tau = fmin(tau, combine((phase & 1) ? all1 : all0, A.G, W.n[1], S.f1h, &s_status, S, stage));
                     ++phase;
@@ -975,7 +1009,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
                 if (surr_step) {
                     mlp_ftv(W.net, out, W.n[1], W.n[2], vcon, ys[1], S.ftvh, S.red);
                 } else {
-                    pass_b<DIM, TT, !RES>(A, W, V, L, B, te, vcon, (phase & 1) ? part1 : part0, &s_status, S.red);
+                    pass_b<DIM, TT, !RES>(A, W, V, L, B, te, vcon, (phase & 1) ? part1 : part0, &s_status, S.red, sfb);
                     sync_shares(I.flag, A.G, g, s_base + phase + 1, &s_status, local);
                     combine((phase & 1) ? all1 : all0, A.G, W.n[2], S.ftvh, &s_status, S, stage);
                     ++phase;
@@ -1128,6 +1162,7 @@ __global__ void __launch_bounds__(BLK) targets_kernel(RomArgs A, const InstDev* 
     __shared__ NodeBuf<DIM> Bn;
     __shared__ Shared S;
     __shared__ int s_status;
+    __shared__ double sfb[DIM == 3 ? SF_DOUBLES : 1];  // sum-factorisation staging (3D)
     const int smp = s0 + blockIdx.x;
     if (smp >= B) return;
     const int tid = threadIdx.x;
@@ -1149,7 +1184,7 @@ __global__ void __launch_bounds__(BLK) targets_kernel(RomArgs A, const InstDev* 
     for (int g = 0; g < G; ++g) {
         const Local<double> L = global_local<DIM>(W, W.views[g], sig);
         pass_a<DIM, double>(A, W, W.views[g], L, Bn, S, fe, S.y[0], S.y[1], S.y[2], share + (int64_t)g * PSTRIDE,
-                            &s_status);
+                            &s_status, sfb);
         __syncthreads();
     }
     __threadfence();
@@ -1163,7 +1198,8 @@ __global__ void __launch_bounds__(BLK) targets_kernel(RomArgs A, const InstDev* 
         for (int g = 0; g < G; ++g) {
             Local<double> L = global_local<DIM>(W, W.views[g], sig);
             if (k >= 0) L.os[1] = zeros;  // rows of every slot read zero
-            pass_b<DIM, double>(A, W, W.views[g], L, Bn, te, S.vc, share + (int64_t)g * PSTRIDE, &s_status, S.red);
+            pass_b<DIM, double>(A, W, W.views[g], L, Bn, te, S.vc, share + (int64_t)g * PSTRIDE, &s_status, S.red,
+                                sfb);
             __syncthreads();
         }
         __threadfence();
@@ -1806,7 +1842,12 @@ static bool same_windows(const lh_instance_desc& a, const lh_instance_desc& b) {
     return true;
 }
 
-constexpr int STATIC_LDS_RESERVE = 24 * 1024;  // node buffers, reduced vectors, state (bytes, upper bound)
+// node buffers, reduced vectors, state (bytes, upper bound), and in 3D the sum-factorisation staging
+constexpr int STATIC_LDS_RESERVE_2D = 24 * 1024;
+constexpr int STATIC_LDS_RESERVE_3D = 24 * 1024 + 8 * SF_DOUBLES;
+static int static_lds_reserve(const lh_problem* p) {
+    return p->dim == 3 ? STATIC_LDS_RESERVE_3D : STATIC_LDS_RESERVE_2D;
+}
 constexpr int MAX_G = 64;                      // workgroups per instance (bounds the share staging in LDS)
 constexpr int ELEMS_PER_WG = 10;               // default cap on sampled elements per workgroup
 
@@ -1887,7 +1928,7 @@ int rom_create(const lh_problem* p, int32_t n_inst, const lh_instance_desc* inst
     }
     // workgroups per instance: enough that every workgroup's window data fits in LDS, within
     // what can be co-resident (one workgroup per compute unit)
-    const int budget = lds_budget() - STATIC_LDS_RESERVE - 8 * (MAX_G / 8) * PSTRIDE;
+    const int budget = lds_budget() - static_lds_reserve(p) - 8 * (MAX_G / 8) * PSTRIDE;
     const int max_g = std::max(1, std::min(MAX_G, cu_count() / n_inst));
     int G = 1;
     if (max_g > 1) {
@@ -2074,7 +2115,7 @@ static int launch_shape(const lh_rom* R, int G, uint32_t flags, LaunchShape* out
     const int mlp_floats = (flags & LH_SURROGATE) ? R->mlp_floats : 0;
     const size_t entries = 8 * (size_t)(R->nkin_max + R->nth_max + (int64_t)((G + 7) / 8) * PSTRIDE) +
                            4 * (size_t)mlp_floats;
-    const int64_t budget = lds_budget() - STATIC_LDS_RESERVE;
+    const int64_t budget = lds_budget() - static_lds_reserve(R->p);
     const int64_t need = (int64_t)R->n_inst * G;
     const int res = (flags & LH_FP32_LIFT) ? R->res_max32 : R->res_max64;
     auto fits = [&](bool resident, size_t dyn, bool* ok) -> int {
