@@ -125,6 +125,9 @@ struct Cfg {
     static constexpr int EC = BLK / NQ;  // elements per chunk (one thread per quadrature point)
 };
 
+// Lanes that share one sampled entry's sum over quadrature points (divides 64 and both NQ).
+constexpr int FP = 16;
+
 // LDS staging of the sum-factorised 3D gradients for a chunk of Cfg<3>::EC elements: the z
 // contractions (216 doubles per element), then the y contractions (432 per element) at SF1.
 constexpr int SF1 = 216 * (BLK / 64);
@@ -163,7 +166,16 @@ struct NodeBuf {
     double e[Cfg<DIM>::EC][Cfg<DIM>::NT];
     double s[Cfg<DIM>::EC][Cfg<DIM>::NQ];
     double m[Cfg<DIM>::EC][2];  // element material: gamma, rho0 det J0
+    RefTab T;                   // the 1D tables, copied from the kernel arguments (lane-dependent reads)
 };
+
+// Copy of the 1D tables into LDS, where the per-lane indexed reads of the passes go (from the
+// kernel-argument segment they are vector memory loads).  Followed by a barrier at the caller.
+template <int DIM>
+__device__ __forceinline__ void stage_tables(const RefTab& src, NodeBuf<DIM>& B) {
+    constexpr int ND = sizeof(RefTab) / sizeof(double);
+    if (threadIdx.x < ND) reinterpret_cast<double*>(&B.T)[threadIdx.x] = reinterpret_cast<const double*>(&src)[threadIdx.x];
+}
 
 // Minimum over the workgroup: within each wave by shuffles, then over the waves (wred: BLK / 64).
 __device__ double block_min(double v, double* wred) {
@@ -338,12 +350,12 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
             const int sl = tid / NQ, q = tid % NQ;
             double J3[3][3], G3[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
             if constexpr (DIM == 3) {  // gradients by sum factorisation (every thread takes part)
-                sf_grad3<BLK>(B.x, ne, sf, sf + SF1, A.T);
-                if (sl < ne) sf_grad3_at(sf + SF1, A.T, sl, q, J3);
+                sf_grad3<BLK>(B.x, ne, sf, sf + SF1, B.T);
+                if (sl < ne) sf_grad3_at(sf + SF1, B.T, sl, q, J3);
                 if (A.fc.use_av) {
                     __syncthreads();  // every J read before the staging is overwritten
-                    sf_grad3<BLK>(B.v, ne, sf, sf + SF1, A.T);
-                    if (sl < ne) sf_grad3_at(sf + SF1, A.T, sl, q, G3);
+                    sf_grad3<BLK>(B.v, ne, sf, sf + SF1, B.T);
+                    if (sl < ne) sf_grad3_at(sf + SF1, B.T, sl, q, G3);
                 }
             }
             if (sl < ne) {
@@ -351,9 +363,9 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
                 double tq;
                 int fl;
                 if constexpr (DIM == 3)
-                    fl = qp_stress_jg<3>(A.T, A.fc, B.m[sl], q, J3, G3, B.e[sl], sig, tq, need_tau);
+                    fl = qp_stress_jg<3>(B.T, A.fc, B.m[sl], q, J3, G3, B.e[sl], sig, tq, need_tau);
                 else
-                    fl = qp_stress<DIM>(A.T, A.fc, B.m[sl], q, B.x[sl], B.v[sl], B.e[sl], sig, tq, need_tau);
+                    fl = qp_stress<DIM>(B.T, A.fc, B.m[sl], q, B.x[sl], B.v[sl], B.e[sl], sig, tq, need_tau);
                 if (fl) atomicOr(status, fl);
                 tau = fmin(tau, tq);
                 double* dst = L.sig + ((int64_t)(c0 + sl) * NQ + q) * DD;
@@ -365,21 +377,27 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
         }
         __syncthreads();
     }
-    // F.1 entries of this workgroup's elements at the sampled rows
-    for (int e = tid; e < V.nkin; e += BLK) {
-        const int slot = V.kin[3 * e], dof = V.kin[3 * e + 1];
-        const int a = dof / DIM, c = dof % DIM;
-        int ax, ay, az;
-        a_coords<DIM>(a, ax, ay, az);
-        const double* sg = L.sig + (int64_t)slot * NQ * DD;
+    // F.1 entries of this workgroup's elements at the sampled rows: FP lanes per entry, each summing
+    // every FP-th quadrature point, then a fixed butterfly over the FP lanes
+    for (int e0 = 0; e0 < V.nkin; e0 += BLK / FP) {
+        const int e = e0 + tid / FP, part = tid % FP;
         double acc = 0.0;
-        for (int q = 0; q < NQ; ++q) {
-            int qx, qy, qz;
-            q_coords<DIM>(q, qx, qy, qz);
+        if (e < V.nkin) {
+            const int slot = V.kin[3 * e], dof = V.kin[3 * e + 1];
+            const int a = dof / DIM, c = dof % DIM;
+            int ax, ay, az;
+            a_coords<DIM>(a, ax, ay, az);
+            const double* sg = L.sig + (int64_t)slot * NQ * DD;
+            for (int q = part; q < NQ; q += FP) {
+                int qx, qy, qz;
+                q_coords<DIM>(q, qx, qy, qz);
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) acc += sg[q * DD + c * DIM + i] * dshape(A.T, qx, qy, qz, ax, ay, az, i, DIM);
+                for (int i = 0; i < DIM; ++i)
+                    acc += sg[q * DD + c * DIM + i] * dshape(B.T, qx, qy, qz, ax, ay, az, i, DIM);
+            }
         }
-        fe[e] = acc;
+        for (int off = FP / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (e < V.nkin && part == 0) fe[e] = acc;
     }
     __syncthreads();
     project_share<TT>(L.a1, L.res, V.kin, V.nkin, W.n[1], fe, S.red, share);
@@ -406,12 +424,12 @@ __device__ void pass_b(const RomArgs& A, const WinDev& W, const WgView& V, const
         }
         __syncthreads();
         if constexpr (DIM == 3) {  // sigma~ : grad_xi v_c with the gradient by sum factorisation
-            sf_grad3<BLK>(B.v, ne, sf, sf + SF1, A.T);
+            sf_grad3<BLK>(B.v, ne, sf, sf + SF1, B.T);
             const int o = tid / NQ, q = tid % NQ;
             if (o < ne) {
                 const double* sg = L.sig + ((int64_t)V.own[c0 + o] * NQ + q) * DD;
                 double gv[3][3];
-                sf_grad3_at(sf + SF1, A.T, o, q, gv);
+                sf_grad3_at(sf + SF1, B.T, o, q, gv);
                 double acc = 0.0;
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
@@ -431,7 +449,7 @@ __device__ void pass_b(const RomArgs& A, const WinDev& W, const WgView& V, const
                     a_coords<DIM>(a, ax, ay, az);
 #pragma unroll
                     for (int i = 0; i < DIM; ++i) {
-                        const double g = dshape(A.T, qx, qy, qz, ax, ay, az, i, DIM);
+                        const double g = dshape(B.T, qx, qy, qz, ax, ay, az, i, DIM);
 #pragma unroll
                         for (int c = 0; c < DIM; ++c) acc += sg[c * DIM + i] * B.v[o][a * DIM + c] * g;
                     }
@@ -440,17 +458,22 @@ __device__ void pass_b(const RomArgs& A, const WinDev& W, const WgView& V, const
             }
         }
         __syncthreads();
-        for (int e = tid; e < V.nth; e += BLK) {
-            const int oi = V.th[3 * e];
-            if (oi < c0 || oi >= c0 + ne) continue;
-            const int j = V.th[3 * e + 1];
+        // F^T.v_c at the sampled energy dofs of this chunk's owners, FP lanes per dof as for F.1
+        for (int e0 = 0; e0 < V.nth; e0 += BLK / FP) {
+            const int e = e0 + tid / FP, part = tid % FP;
+            const int oi = e < V.nth ? V.th[3 * e] : -1;
+            const bool mine = oi >= c0 && oi < c0 + ne;
             double acc = 0.0;
-            for (int q = 0; q < NQ; ++q) {
-                int qx, qy, qz;
-                q_coords<DIM>(q, qx, qy, qz);
-                acc += tshape<DIM>(A.T, qx, qy, qz, j) * B.s[oi - c0][q];
+            if (mine) {
+                const int j = V.th[3 * e + 1];
+                for (int q = part; q < NQ; q += FP) {
+                    int qx, qy, qz;
+                    q_coords<DIM>(q, qx, qy, qz);
+                    acc += tshape<DIM>(B.T, qx, qy, qz, j) * B.s[oi - c0][q];
+                }
             }
-            te[e] = acc;
+            for (int off = FP / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+            if (mine && part == 0) te[e] = acc;
         }
         __syncthreads();
     }
@@ -847,6 +870,7 @@ __global__ void __launch_bounds__(BLK) rom_step_kernel(RomArgs A) {
     double* stage = te + A.nth_max;  // ceil(G / 8) x PSTRIDE partial results of combine
     float* mscr = reinterpret_cast<float*>(stage + (int64_t)((A.G + 7) / 8) * PSTRIDE);  // surrogate scratch
     char* dyn = reinterpret_cast<char*>(mscr + A.mlp_floats);
+    stage_tables(A.T, B);
     if (tid == 0) {
         st = A.state[ii];
         s_status = 0;
@@ -1179,6 +1203,7 @@ __global__ void __launch_bounds__(BLK) targets_kernel(RomArgs A, const InstDev* 
     for (int f = 0, off = 0; f < 3; off += W.n[f], ++f)
         for (int k = tid; k < LH_NMAX; k += BLK) S.y[f][k] = k < W.n[f] ? yhat[(int64_t)smp * ldy + off + k] : 0.0;
     if (tid == 0) s_status = 0;
+    stage_tables(A.T, Bn);
     __syncthreads();
     double* out = T + (int64_t)smp * dout;
     for (int g = 0; g < G; ++g) {
