@@ -422,6 +422,17 @@ int rom_sampled_elements(const lh_rom* r, int32_t inst, int32_t window, int32_t*
  * complete within a few seconds sets LH_FLAG_TIMEOUT and ends the launch. */
 int rom_workgroups_per_instance(const lh_rom* r, int32_t* G);
 
+/* Where a rom_step launch with these flags and the current workgroup count
+ * keeps each workgroup's window data (host query):
+ *   LH_PLACE_LDS    every table in LDS (tiles, offsets, DEIM columns, B_xv, stress);
+ *   LH_PLACE_STRESS tiles and operators in global memory (instances on shared
+ *                   bases find them in the L2), the kept stress in LDS;
+ *   LH_PLACE_GLOBAL tables and stress in global memory.
+ * The first that fits the LDS budget and, for G > 1, keeps every workgroup
+ * co-resident is taken; results agree across placements to rounding. */
+enum { LH_PLACE_LDS = 0, LH_PLACE_STRESS = 1, LH_PLACE_GLOBAL = 2 };
+int rom_data_placement(const lh_rom* r, uint32_t flags, int32_t* placement);
+
 /* Device memory held by r (host query, bytes): window tables, workgroup
  * tables and per-instance exchange buffers.  Instances whose window
  * descriptions are equal field by field (same pointers, sizes and times)

@@ -73,8 +73,15 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
     __shared__ int s_elem[EPB];
     __shared__ double s_m[EPB][2];  // element material: gamma, rho0 det J0
     __shared__ double s_tau[256];
+    // 3D: LDS staging of the sum-factorised gradients (z then y contractions), reused for the first
+    // contraction of F.1; the 1D tables, read with lane-dependent indices
+    constexpr int SF1F = 216 * EPB;
+    __shared__ double sf[DIM == 3 ? SF1F + 432 * EPB : 1];
+    __shared__ RefTab sT;
 
     const int tid = threadIdx.x;
+    constexpr int ND = sizeof(RefTab) / sizeof(double);
+    if (tid < ND) reinterpret_cast<double*>(&sT)[tid] = reinterpret_cast<const double*>(&A.T)[tid];
     const bool use_stress = (A.ops & LH_USE_STRESS) != 0;
     const bool want_f1 = (A.ops & LH_F1) && !use_stress;
     const bool want_ftv = (A.ops & LH_FTV) != 0;
@@ -118,6 +125,23 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
     const int q = tid % NQ;
     const int K = s_elem[s];
     double tau = INFINITY;
+    // 3D reference gradients at this point by sum factorisation (every thread takes part): dx/dxi,
+    // dv/dxi for the viscosity, dv_c/dxi for F^T.v_c
+    double J3[3][3], G3[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, C3[3][3];
+    if constexpr (DIM == 3) {
+        if (!use_stress) {
+            sf_grad3<256>(s_x, EPB, sf, sf + SF1F, sT);
+            sf_grad3_at(sf + SF1F, sT, s, q, J3);
+            if (A.fc.use_av) {
+                sf_grad3<256>(s_v, EPB, sf, sf + SF1F, sT);
+                sf_grad3_at(sf + SF1F, sT, s, q, G3);
+            }
+        }
+        if (want_ftv) {
+            sf_grad3<256>(s_vc, EPB, sf, sf + SF1F, sT);
+            sf_grad3_at(sf + SF1F, sT, s, q, C3);
+        }
+    }
     if (K >= 0) {
         double sig[DIM][DIM];
         if (use_stress) {
@@ -127,7 +151,11 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
 #pragma unroll
                 for (int i = 0; i < DIM; ++i) sig[c][i] = src[c * DIM + i];
         } else {
-            const int fl = qp_stress<DIM>(A.T, A.fc, s_m[s], q, s_x[s], s_v[s], s_e[s], sig, tau, want_tau);
+            int fl;
+            if constexpr (DIM == 3)
+                fl = qp_stress_jg<3>(sT, A.fc, s_m[s], q, J3, G3, s_e[s], sig, tau, want_tau);
+            else
+                fl = qp_stress<DIM>(sT, A.fc, s_m[s], q, s_x[s], s_v[s], s_e[s], sig, tau, want_tau);
             if (fl) atomicOr(A.status, fl);
             if (A.ops & LH_KEEP_STRESS) {
                 double* dst = A.stress + ((int64_t)K * NQ + q) * DD;
@@ -142,18 +170,25 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
 #pragma unroll
             for (int i = 0; i < DIM; ++i) s_sig[s][q * DD + c * DIM + i] = sig[c][i];
         if (want_ftv) {
-            // sigma~ : (sum_a v_c,a (x) grad_xi N_a)
-            int qx, qy, qz;
-            q_coords<DIM>(q, qx, qy, qz);
+            // sigma~ : (sum_a v_c,a (x) grad_xi N_a) = sigma~ : dv_c/dxi
             double acc = 0.0;
-            for (int a = 0; a < NK; ++a) {
-                int ax, ay, az;
-                a_coords<DIM>(a, ax, ay, az);
+            if constexpr (DIM == 3) {
 #pragma unroll
-                for (int i = 0; i < DIM; ++i) {
-                    const double g = dshape(A.T, qx, qy, qz, ax, ay, az, i, DIM);
+                for (int c = 0; c < 3; ++c)
 #pragma unroll
-                    for (int c = 0; c < DIM; ++c) acc += sig[c][i] * s_vc[s][a * DIM + c] * g;
+                    for (int i = 0; i < 3; ++i) acc += sig[c][i] * C3[c][i];
+            } else {
+                int qx, qy, qz;
+                q_coords<DIM>(q, qx, qy, qz);
+                for (int a = 0; a < NK; ++a) {
+                    int ax, ay, az;
+                    a_coords<DIM>(a, ax, ay, az);
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i) {
+                        const double g = dshape(sT, qx, qy, qz, ax, ay, az, i, DIM);
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) acc += sig[c][i] * s_vc[s][a * DIM + c] * g;
+                    }
                 }
             }
             s_s[s][q] = acc;
@@ -169,9 +204,53 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
         if (tid == 0 && s_tau[0] < INFINITY) atomic_min_pos_double(A.tau, s_tau[0]);
     }
     __syncthreads();
-    if (want_f1) {
-        // 2D: consecutive threads take consecutive element slots of one entry; 3D: consecutive
-        // entries of one element (the order f1_loc_index stores them in)
+    if (want_f1 && DIM == 3) {
+        // 3D, by sum factorisation: F1[a][c] = sum_q sum_i sigma~[q][c][i] dN_a/dxi_i(q).  First the
+        // x contraction into sf, u[s][c][i][ax][qy][qz] = sum_qx sigma~ (i = 0: D, else B)[qx][ax] ...
+        for (int t = tid; t < EPB * 432; t += 256) {
+            const int qyz = t & 15;
+            int r = t >> 4;
+            const int ax = r % 3;
+            r /= 3;
+            const int i = r % 3;
+            r /= 3;
+            const int c = r % 3, ss = r / 3;
+            const double* w = i == 0 ? sT.D[0] : sT.B[0];  // [qx][ax] rows of 3
+            const double* sg = &s_sig[ss][(qyz * 4) * DD + c * DIM + i];
+            double acc = sg[0] * w[ax];
+            acc += sg[DD] * w[3 + ax];
+            acc += sg[2 * DD] * w[6 + ax];
+            acc += sg[3 * DD] * w[9 + ax];
+            sf[t] = acc;
+        }
+        __syncthreads();
+        // ... then each entry (a, c) sums over i, qy, qz (consecutive threads: consecutive entries of
+        // one element, the order f1_loc_index stores them in)
+        for (int t = tid; t < EPB * NK * DIM; t += 256) {
+            const int ss = t / (NK * DIM);
+            const int r = t % (NK * DIM);
+            const int a = r / DIM, c = r % DIM;
+            const int KK = s_elem[ss];
+            if (KK < 0) continue;
+            int ax, ay, az;
+            a_coords<DIM>(a, ax, ay, az);
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double* u = sf + (((ss * 3 + c) * 3 + i) * 3 + ax) * 16;
+                for (int qz = 0; qz < 4; ++qz) {
+                    const double wz = i == 2 ? sT.D[qz][az] : sT.B[qz][az];
+                    double row = 0.0;
+#pragma unroll
+                    for (int qy = 0; qy < 4; ++qy) row += u[qz * 4 + qy] * (i == 1 ? sT.D[qy][ay] : sT.B[qy][ay]);
+                    acc += wz * row;
+                }
+            }
+            A.f1_loc[f1_loc_index<DIM>(KK, a, c, A.n_elem)] = acc;
+        }
+    } else if (want_f1) {
+        // 2D: consecutive threads take consecutive element slots of one entry (the order
+        // f1_loc_index stores them in)
         for (int t = tid; t < EPB * NK * DIM; t += 256) {
             const int ss = DIM == 2 ? t % EPB : t / (NK * DIM);
             const int r = DIM == 2 ? t / EPB : t % (NK * DIM);
@@ -187,7 +266,7 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
                 q_coords<DIM>(qq, qx, qy, qz);
 #pragma unroll
                 for (int i = 0; i < DIM; ++i)
-                    acc += s_sig[ss][qq * DD + c * DIM + i] * dshape(A.T, qx, qy, qz, ax, ay, az, i, DIM);
+                    acc += s_sig[ss][qq * DD + c * DIM + i] * dshape(sT, qx, qy, qz, ax, ay, az, i, DIM);
             }
             A.f1_loc[f1_loc_index<DIM>(KK, a, c, A.n_elem)] = acc;
         }
@@ -202,7 +281,7 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
             for (int qq = 0; qq < NQ; ++qq) {
                 int qx, qy, qz;
                 q_coords<DIM>(qq, qx, qy, qz);
-                acc += tshape<DIM>(A.T, qx, qy, qz, j) * s_s[ss][qq];
+                acc += tshape<DIM>(sT, qx, qy, qz, j) * s_s[ss][qq];
             }
             A.ftv[(int64_t)KK * NT + j] = acc;
         }

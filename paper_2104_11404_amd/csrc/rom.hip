@@ -2471,6 +2471,17 @@ int rom_workgroups_per_instance(const lh_rom* R, int32_t* G) {
     return LH_OK;
 }
 
+int rom_data_placement(const lh_rom* R, uint32_t flags, int32_t* placement) {
+    using namespace lh;
+    using namespace lh::rom;
+    LH_REQUIRE(R && placement, "rom_data_placement: null argument");
+    LaunchShape sh;
+    const int rc = launch_shape(R, R->G, flags, &sh);
+    if (rc) return rc;
+    *placement = sh.resident ? LH_PLACE_LDS : sh.sig_lds ? LH_PLACE_STRESS : LH_PLACE_GLOBAL;
+    return LH_OK;
+}
+
 int rom_device_bytes(const lh_rom* R, int64_t* bytes) {
     using namespace lh;
     LH_REQUIRE(R && bytes, "rom_device_bytes: null argument");

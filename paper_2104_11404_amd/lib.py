@@ -21,6 +21,7 @@ LH_ERRORS = {-1: "LH_EINVAL", -2: "LH_EWORKSPACE", -3: "LH_EDEVICE", -4: "LH_ETA
              -6: "LH_EDTCOLLAPSE", -7: "LH_ERANK"}
 LH_F1, LH_FTV, LH_TAU, LH_KEEP_STRESS, LH_USE_STRESS, LH_NO_BC = 1, 2, 4, 8, 16, 32
 LH_FP32_LIFT, LH_REPLAY_DT, LH_FIXED_DT, LH_SURROGATE, LH_RK4 = 1, 2, 4, 8, 16
+LH_PLACE_LDS, LH_PLACE_STRESS, LH_PLACE_GLOBAL = 0, 1, 2
 LH_MLP_MAX_LAYERS = 8
 LH_NMAX = 64
 KIND = {"taylor_green": 1, "sedov": 2, "gresho": 3, "triple_point": 4}
@@ -107,6 +108,7 @@ _SIGNATURES = {
     "rom_lift": (_I32, [_VP, _VP, _I32, C.POINTER(InstanceDesc), _VP, _VP, _VP, _VP]),
     "rom_sampled_elements": (_I32, [_VP, _I32, _I32, C.POINTER(_I32)]),
     "rom_workgroups_per_instance": (_I32, [_VP, C.POINTER(_I32)]),
+    "rom_data_placement": (_I32, [_VP, C.c_uint32, C.POINTER(_I32)]),
     "rom_set_workgroups": (_I32, [_VP, _I32, _U32, _VP]),
     "rom_device_bytes": (_I32, [_VP, C.POINTER(_I64)]),
     "rom_switch_window_previous": (_I32, [_VP, _VP, _I32, C.POINTER(InstanceDesc), _VP]),
@@ -493,6 +495,12 @@ class Rom:
         g = _I32()
         _check(load().rom_workgroups_per_instance(self.h, C.byref(g)))
         return g.value
+
+    def placement(self, flags=0):
+        """Where a launch with these flags keeps the window data: LH_PLACE_LDS, _STRESS or _GLOBAL."""
+        p = _I32()
+        _check(load().rom_data_placement(self.h, int(flags), C.byref(p)))
+        return p.value
 
     def run_to_end(self, flags=0, dt_replay=None, max_launches=100000):
         """rom_step until every instance has finished.  An instance with offsets="previous" stops at

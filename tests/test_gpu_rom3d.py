@@ -201,3 +201,41 @@ def test_surrogate_with_fp32_lift_keeps_its_audits(gpu_lib, tg3):
     assert st.status == 0 and st.n_audits == run.audits and st.n_surrogate_steps == run.surrogate_steps
     for a, b in zip(G.coords(0), run.yhat):
         assert rel(a, b) < 1e-3
+
+
+@pytest.mark.parametrize("case", ["tg_fixed", "sedov_av_adaptive"])
+def test_rom3d_tiles_global_stress_in_lds(gpu_lib, case):
+    """Enough sampled elements and modes that a workgroup's tiles exceed LDS while its kept stress fits
+    (LH_PLACE_STRESS, the headline batch's placement): against the oracle, with the
+    viscosity off (fixed steps) and on (adaptive steps, velocity gradient in pass A too), and the
+    same run with one workgroup per instance (every table in global memory once the workgroup's stress
+    no longer fits either)."""
+    from paper_2104_11404_amd import lib
+    if case == "tg_fixed":
+        wl = W.replace(W.tg3d(4), t_final=0.004, use_av=False)
+        fixed, lam = 2e-4, 6
+    else:  # the blast samples few elements: more rows per mode to reach 4 workgroups of 10 or so
+        wl = W.replace(W.sedov3d(4), t_final=0.03)
+        fixed, lam = None, 12
+    op = F.build_operator(oracle_problem(wl))
+    tr = F.run_fom(op, wl.t_final, fixed_dt=fixed)
+    y0 = initial_state(op.prob)
+    n = min(14, len(tr.snaps) - 1)
+    rom = R.build_rom(op, [tr], [y0], [wl.t_final], n_fixed=(n, n, n), lam=(lam, lam))
+    run = R.run_rom(op, rom, y0, wl.t_final, fixed_dt=fixed)
+    flags = lib.LH_FIXED_DT if fixed else 0
+    for G_ in (4, 1):
+        P, G = _gpu_rom(wl, [(rom, wl.t_final)], [y0], dt0=fixed or 0.0)
+        G.set_workgroups(G_, flags)
+        G.init_state(_t(y0[0]), _t(y0[1]), _t(y0[2]), fixed or 0.0)
+        place = G.placement(flags)
+        print(f"[case] rom 3d {case}: {len(rom.windows[0].elems)} sampled elements, dims {n}, G={G_}, "
+              f"placement {place}", flush=True)
+        if G_ == 4:
+            assert place == lib.LH_PLACE_STRESS
+        G.step(flags=flags)
+        st = G.states()[0]
+        assert st.status == 0 and st.done == 1
+        assert st.n_steps == len(run.dt) and st.n_rejected == run.rejections
+        for a, b in zip(G.coords(0), run.yhat):
+            assert rel(a, b) < 1e-9
