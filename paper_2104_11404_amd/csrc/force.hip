@@ -81,7 +81,9 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
 
     const int tid = threadIdx.x;
     constexpr int ND = sizeof(RefTab) / sizeof(double);
-    if (tid < ND) reinterpret_cast<double*>(&sT)[tid] = reinterpret_cast<const double*>(&A.T)[tid];
+    if (DIM == 3 && tid < ND) reinterpret_cast<double*>(&sT)[tid] = reinterpret_cast<const double*>(&A.T)[tid];
+    // the tables the passes read: the LDS copy in 3D; in 2D the kernel arguments measured faster
+    const RefTab& TQ = DIM == 3 ? sT : A.T;
     const bool use_stress = (A.ops & LH_USE_STRESS) != 0;
     const bool want_f1 = (A.ops & LH_F1) && !use_stress;
     const bool want_ftv = (A.ops & LH_FTV) != 0;
@@ -155,7 +157,7 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
             if constexpr (DIM == 3)
                 fl = qp_stress_jg<3>(sT, A.fc, s_m[s], q, J3, G3, s_e[s], sig, tau, want_tau);
             else
-                fl = qp_stress<DIM>(sT, A.fc, s_m[s], q, s_x[s], s_v[s], s_e[s], sig, tau, want_tau);
+                fl = qp_stress<DIM>(TQ, A.fc, s_m[s], q, s_x[s], s_v[s], s_e[s], sig, tau, want_tau);
             if (fl) atomicOr(A.status, fl);
             if (A.ops & LH_KEEP_STRESS) {
                 double* dst = A.stress + ((int64_t)K * NQ + q) * DD;
@@ -185,7 +187,7 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
                     a_coords<DIM>(a, ax, ay, az);
 #pragma unroll
                     for (int i = 0; i < DIM; ++i) {
-                        const double g = dshape(sT, qx, qy, qz, ax, ay, az, i, DIM);
+                        const double g = dshape(TQ, qx, qy, qz, ax, ay, az, i, DIM);
 #pragma unroll
                         for (int c = 0; c < DIM; ++c) acc += sig[c][i] * s_vc[s][a * DIM + c] * g;
                     }
@@ -266,7 +268,7 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
                 q_coords<DIM>(qq, qx, qy, qz);
 #pragma unroll
                 for (int i = 0; i < DIM; ++i)
-                    acc += s_sig[ss][qq * DD + c * DIM + i] * dshape(sT, qx, qy, qz, ax, ay, az, i, DIM);
+                    acc += s_sig[ss][qq * DD + c * DIM + i] * dshape(TQ, qx, qy, qz, ax, ay, az, i, DIM);
             }
             A.f1_loc[f1_loc_index<DIM>(KK, a, c, A.n_elem)] = acc;
         }
@@ -281,7 +283,7 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs A) {
             for (int qq = 0; qq < NQ; ++qq) {
                 int qx, qy, qz;
                 q_coords<DIM>(qq, qx, qy, qz);
-                acc += tshape<DIM>(sT, qx, qy, qz, j) * s_s[ss][qq];
+                acc += tshape<DIM>(TQ, qx, qy, qz, j) * s_s[ss][qq];
             }
             A.ftv[(int64_t)KK * NT + j] = acc;
         }
