@@ -1538,6 +1538,18 @@ static int build_window(lh_rom* R, const lh_problem* p, const lh_window_desc& wd
     }
     std::vector<int> elem(els.begin(), els.end());
     const int n_el = (int)elem.size();
+    {
+        // Slot order: the elements that own sampled energy dofs spread evenly through the closure
+        // (each group in ascending element order).  Pass B runs over the owners in a workgroup's
+        // slot range, so every contiguous range, whatever G cuts it, then holds its share of them.
+        std::set<int> owners;
+        for (int r = 0; r < wd.n_s2; ++r) owners.insert(z2[r] / NT);
+        std::vector<int> o, rest;
+        for (int K : elem) (owners.count(K) ? o : rest).push_back(K);
+        const int64_t no = (int64_t)o.size();
+        size_t io = 0, ir = 0;
+        for (int q = 0; q < n_el; ++q) elem[q] = ((q + 1) * no / n_el > q * no / n_el) ? o[io++] : rest[ir++];
+    }
     W.n_el = H.n_el = n_el;
     std::map<int, int> slot_of;
     for (int i = 0; i < n_el; ++i) slot_of[elem[i]] = i;
