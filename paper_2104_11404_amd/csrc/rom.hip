@@ -401,7 +401,7 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
     }
     __syncthreads();
     project_share<TT>(L.a1, L.res, V.kin, V.nkin, W.n[1], fe, S.red, share);
-    const double tmin = block_min(tau, S.wred);
+    const double tmin = need_tau ? block_min(tau, S.wred) : INFINITY;
     if (tid == 0) {
         share[LH_NMAX] = tmin;
         share[LH_NMAX + 1] = (double)*status;
@@ -502,6 +502,31 @@ __device__ double combine(const double* part, int G, int n, double* out, int* st
     const int C = n + 2;
     const int NB = (G + 7) >> 3;
     const int tid = threadIdx.x;
+    if (NB == 1) {
+        // up to 8 workgroups: thread c folds column c of every share and stores the result itself, and
+        // one barrier publishes it (the caller's later barriers order the next writes of S.comb and
+        // the reads of *status)
+        if (tid < C) {
+            const int kind = tid < n ? 0 : tid - n + 1;
+            const double* src = part + (tid < n ? tid : LH_NMAX + (tid - n));
+            double v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = share_load(src + (int64_t)min(j, G - 1) * PSTRIDE);
+            double acc = v[0];
+#pragma unroll
+            for (int j = 1; j < 8; ++j)
+                if (j < G) acc = comb_op(kind, acc, v[j]);
+            if (tid < n)
+                out[tid] = acc;
+            else
+                S.comb[tid - n] = acc;
+        }
+        __syncthreads();
+        const double t = S.comb[0];
+        const int st = (int)S.comb[1];
+        if (tid == 0 && st) atomicOr(status, st);
+        return t;
+    }
     for (int t = tid; t < C * NB; t += BLK) {
         const int c = t % C;
         const int b = t / C;
