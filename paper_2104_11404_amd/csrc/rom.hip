@@ -330,11 +330,13 @@ __device__ void pass_a(const RomArgs& A, const WinDev& W, const WgView& V, const
             B.m[tid][0] = W.mat[2 * (V.s0 + c0 + tid)];
             B.m[tid][1] = W.mat[2 * (V.s0 + c0 + tid) + 1];
         }
-        for (int t = tid; t < ne * (2 * NKD + NT); t += BLK) {
-            const int sl = t / (2 * NKD + NT);
-            const int r = t % (2 * NKD + NT);
+        // rows lifted per slot: x, v (the stress reads v only for the viscosity) and e
+        const int rps = (A.fc.use_av ? 2 * NKD : NKD) + NT;
+        for (int t = tid; t < ne * rps; t += BLK) {
+            const int sl = t / rps;
+            int r = t % rps;
+            if (!A.fc.use_av && r >= NKD) r += NKD;  // past x come the e rows
             const int slot = c0 + sl;
-            if (r >= NKD && r < 2 * NKD && !A.fc.use_av) continue;  // the stress reads v only for the viscosity
             if (r < NKD)
                 B.x[sl][r] = lift_at<GL && DIM == 3>(L.tile[0] + (int64_t)slot * W.n[0] * NKD + r, L.os[0] + slot * NKD + r, W.n[0],
                                       NKD, yx);
