@@ -39,6 +39,17 @@ def test_traffic_is_reported_only_for_the_profiled_sources_and_shape(tmp_path, m
     assert bench.measured_traffic(20) is None
 
 
+def test_every_headline_form_with_traffic_names_a_committed_counter_summary():
+    import re
+    for form, name in bench.HEADLINE_TRAFFIC.items():
+        text = open(os.path.join(ROOT, "profiles", name)).read()
+        m = re.search(r"traffic_bytes_per_launch=(\d+) source_sha1=([0-9a-f]{40}) workgroups=(\d+)", text)
+        assert m, form
+        assert int(m.group(1)) > 0 and int(m.group(3)) >= 1
+        # the command that made it runs the same form
+        assert f"--headline-form {form}" in text, form
+
+
 def test_rom_step_bytes_counts_tiles_offsets_and_operators():
     nx, nv, ne, ns1, ns2 = 3, 5, 4, 10, 8
     wd = {"phi": [torch.zeros(nx, 7), torch.zeros(nv, 7), torch.zeros(ne, 7)],
