@@ -365,7 +365,8 @@ int rom_init_state(const lh_rom* r, const lh_instance_desc* inst, const double* 
  * (eq. RK2-avg-rom-hr) and the step control of Sec. 2.2.3, for at most
  * max_steps accepted steps or until its t_final.  One persistent launch:
  * each instance is advanced by G workgroups (rom_workgroups_per_instance)
- * that split its sampled elements and exchange per-stage partial reduced
+ * that split its sampled elements (contiguous ranges of a closure order that
+ * spreads the owners of sampled energy dofs evenly) and exchange per-stage partial reduced
  * forces through device memory, combined in a fixed order so that results
  * are bitwise reproducible; windows switch on device (eq. ic-tw) once t >= T_w (1 - 1e-12).  With
  * G > 1 the launch is cooperative (every workgroup resident); a partner that
